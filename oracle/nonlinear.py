@@ -1,0 +1,79 @@
+"""Non-linear terms, explicit RK2 and Strang splitting (oracle; test infrastructure).
+
+Paper, Section 3 (the N(U) column of the split):
+
+    N_Phi   = -V.grad Phi' - Phi' div V   = -div(Phi' V)
+    N_zeta  = -div(zeta V)
+    N_delta =  k.curl(zeta V) - lap (V.V / 2)
+
+In h = Phi'/g variables N_h = -div(h V).  zeta is the relative vorticity (the
+Coriolis terms belong to L here, the paper's ``l`` term of Table 1).  The
+products are formed pointwise on the Gauss grid (pseudo-spectral, Section 3.2)
+with velocities from psi = lap^{-1} zeta, chi = lap^{-1} delta.
+
+Time stepping (Section 4.1 and Section 4.4):
+* ``heun``: the second-order explicit Runge-Kutta method (``erk``, Table 2); the
+  paper does not name the variant, Heun's method is the reading used here.
+* ``strang_ver1``: N^{dt/2} o L^{dt} o N^{dt/2} (Section 4.4, version 1), with the
+  linear part by REXI (Eq. rexi) -- scheme ``l_rexi_n_erk_ver1``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import linear
+from .operator import Params
+from .sht import Grid, degree_array, inv_laplacian
+
+
+def tendency(grid: Grid, U: np.ndarray) -> np.ndarray:
+    """N(U) for a spectral state U[3, modes] = (h, zeta, delta)."""
+    L, a = grid.L, grid.p.a
+    h, zeta, delta = U
+    psi = inv_laplacian(zeta, L, a)
+    chi = inv_laplacian(delta, L, a)
+    hg = grid.synthesis(h)
+    zg = grid.synthesis(zeta)
+    Ug, Vg = grid.uv_from_psichi(psi, chi)
+    div_h, _ = grid.div_curl(hg * Ug, hg * Vg)
+    div_z, curl_z = grid.div_curl(zg * Ug, zg * Vg)
+    ke = (Ug * Ug + Vg * Vg) / (2.0 * (grid.sint[:, None] ** 2))
+    ke_s = grid.analysis(ke)
+    l = degree_array(L).astype(np.float64)
+    out = np.empty_like(U, dtype=np.complex128)
+    out[0] = -div_h
+    out[1] = -div_z
+    out[2] = curl_z + (l * (l + 1.0) / (a * a)) * ke_s       # -lap KE
+    return out
+
+
+def heun(grid: Grid, U: np.ndarray, tau: float) -> np.ndarray:
+    """U + tau/2 (N(U) + N(U + tau N(U)))."""
+    N0 = tendency(grid, U)
+    N1 = tendency(grid, U + tau * N0)
+    return U + 0.5 * tau * (N0 + N1)
+
+
+def strang_ver1(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta: np.ndarray) -> np.ndarray:
+    """One step of l_rexi_n_erk_ver1: N^{dt/2} o REXI^{dt} o N^{dt/2}."""
+    U = heun(grid, U, 0.5 * dt)
+    U = linear.rexi_linear_step(U, alpha, beta, dt, grid.L, grid.p)
+    return heun(grid, U, 0.5 * dt)
+
+
+def full_tendency(grid: Grid, U: np.ndarray) -> np.ndarray:
+    """(L + N)(U): the whole right-hand side of Eq. (sw_compact)."""
+    from .operator import apply
+    return apply(U, grid.L, grid.p) + tendency(grid, U)
+
+
+def rk4(grid: Grid, U: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+    """Classical RK4 on the full system; the paper's reference solutions are RK4
+    with a very small step (Section 5)."""
+    for _ in range(nsteps):
+        k1 = full_tendency(grid, U)
+        k2 = full_tendency(grid, U + 0.5 * dt * k1)
+        k3 = full_tendency(grid, U + 0.5 * dt * k2)
+        k4 = full_tendency(grid, U + dt * k3)
+        U = U + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return U
