@@ -1,0 +1,197 @@
+/*
+ * rexi_swe.h -- C-ABI of the MI355X (gfx950) library for REXI time stepping of
+ * the shallow-water equations on the rotating sphere (Schreiber, Schaeffer &
+ * Loft, arXiv:1805.06557).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns an int status: REXI_OK (0) or a negative REXI_E*
+ *   code.  Nothing aborts, throws or exits.  rexi_last_error() returns a
+ *   thread-local message describing the last failure on the calling thread.
+ * - Spectral states are device arrays of complex128 stored as interleaved
+ *   (re, im) doubles.  A state holds 3 fields (h, zeta, delta) = (height
+ *   perturbation h' = Phi'/g [m], relative vorticity [1/s], divergence [1/s]),
+ *   field-major: field f occupies doubles [2 f modes, 2 (f + 1) modes).
+ *   Within a field the (l, m) coefficient with 0 <= m <= l <= L sits at
+ *   idx(l, m) = m (2L + 3 - m) / 2 + (l - m)   (m-major; modes = (L+1)(L+2)/2).
+ *   Only m >= 0 is stored; the fields are real in physical space, so the
+ *   m = 0 coefficients are real.  Normalisation: integral over [-1, 1] of
+ *   Pbar_lm(mu)^2 dmu = 1, no Condon-Shortley phase, e^{+i m lambda}.
+ * - Grid fields are device float64 arrays [nf][nlat][nlon]: Gauss-Legendre
+ *   latitudes ordered north to south, longitudes lambda_k = 2 pi k / nlon.
+ * - Device pointers are caller-owned; the library never frees them.  Calls
+ *   that take a hipStream_t enqueue their work on that stream and return
+ *   without waiting; device buffers must stay valid until that work is done.
+ *   Errors found by the host (bad arguments, a contour that does not enclose
+ *   the spectrum) are returned at once; nothing is enqueued in that case.
+ * - A context (swe_ctx) owns its device tables, cached REXI coefficients and
+ *   workspaces.  It is bound to the device that was current at swe_create.
+ *   Calls on one context must not run concurrently from several host threads.
+ */
+#ifndef REXI_SWE_H
+#define REXI_SWE_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    REXI_OK = 0,
+    REXI_EINVAL = -1,   /* invalid argument (size, pointer, parameter) */
+    REXI_ENOMEM = -2,   /* device or host allocation failed */
+    REXI_EDEVICE = -3,  /* HIP runtime error (launch, copy, no device) */
+    REXI_ENOTSUP = -4,  /* operation not available for this context */
+    REXI_ENUMERIC = -5  /* numerically invalid set-up (contour, dominance) */
+};
+
+/* Functions approximated by the rational sum (Section 4.3: psi_0 = exp,
+ * psi_1(z) = (e^z - 1)/z, psi_2(z) = (e^z - 1 - z)/z^2). */
+enum { REXI_FN_EXP = 0, REXI_FN_PSI1 = 1, REXI_FN_PSI2 = 2 };
+
+/* Precision modes of a context (bit flags; 0 = everything in FP64).
+ * REXI_PREC_FP32_SOLVE: the banded REXI solves run in complex FP32; diagonals
+ *   and right-hand sides are formed in FP64 and rounded once, the
+ *   beta-weighted sum accumulates in FP64. */
+enum {
+    REXI_PREC_FP64 = 0,
+    REXI_PREC_FP32_SOLVE = 1,
+    REXI_PREC_BF16_SPLIT = 2,
+    REXI_PREC_FP16_SPLIT = 4
+};
+
+typedef struct swe_ctx swe_ctx;
+
+/*
+ * rexi_coefficients -- poles and weights of the rational approximation
+ *   f(x) ~ sum_{n<N} beta_n / (x + alpha_n)
+ * from the N-point trapezoidal rule of the Cauchy integral on the circle
+ * through p0 > 0 and +-i y (Section 4.2.1, Eq. cauchy_alpha and Eq.
+ * cauchy_beta; circle from Section 4.2.2: r = (p0^2 + y^2) / (2 p0),
+ * centre mu = p0 - r):
+ *   theta_n = 2 pi (n + 1/2) / N,  alpha_n = -(r e^{i theta_n} + mu),
+ *   beta_n  = -(1/N) r e^{i theta_n} f(r e^{i theta_n} + mu).
+ * Host only; touches no device.  Computed in extended precision and rounded
+ * once.  fn: REXI_FN_*.  N: even, 2 <= N <= 1<<20.  alpha, beta:
+ * caller-owned host arrays of 2N doubles (interleaved re, im).  r, mu: may be
+ * NULL; otherwise receive the radius and centre.
+ * Errors: REXI_EINVAL for a bad fn, odd/out-of-range N, p0 <= 0, y <= 0 or a
+ * NULL alpha/beta.
+ */
+int rexi_coefficients(int fn, int N, double p0, double y,
+                      double* alpha, double* beta, double* r, double* mu);
+
+/*
+ * swe_create -- context for truncation L on an nlat x nlon Gauss grid with
+ * planet radius a [m], gravity g [m/s^2], mean depth H [m], rotation rate
+ * Omega [1/s] and precision flags prec (REXI_PREC_*).
+ * nlat = nlon = 0 makes a linear-only context (no transforms, no nonlinear
+ * step).  Otherwise nlat > L, nlat even, nlon > 2L and nlon a multiple of 4.
+ * 1 <= L <= 1023.  On success *out receives the context.
+ * Errors: REXI_EINVAL, REXI_ENOMEM, REXI_EDEVICE.
+ */
+int swe_create(int L, int nlat, int nlon, double a, double g, double H,
+               double Omega, int prec, swe_ctx** out);
+
+/* swe_destroy -- waits for the context's work and frees it.  NULL is a no-op. */
+int swe_destroy(swe_ctx* ctx);
+
+/*
+ * rexi_linear_step -- the REXI linear stage (Section 4.2, Eq. rexi):
+ *   U1 = sum_{n<N} beta_n (dt L + alpha_n I)^{-1} U0,  L = L_g + L_c,
+ * the paper's sign convention, with alpha/beta as from rexi_coefficients.
+ * L_g: h_t = -H delta, delta_t = -g lap h.  L_c: the Coriolis terms with
+ * f = 2 Omega sin(phi) (Section 3), which couple degree l to l +- 1 within
+ * each zonal order m: every (pole, m) system is banded and is solved on the
+ * device as two complex tridiagonal chains after eliminating h.
+ * alpha, beta: host arrays of 2N doubles; they are copied to the device and
+ * cached inside the context (keyed by their contents and dt).  U0, U1: device
+ * states [3][modes] complex128; they must not overlap.
+ * Before enqueueing, the host checks that the polygon of the poles -alpha_n
+ * winds once around the segment i[-rho, rho], rho = dt (sqrt(g H L(L+1))/a +
+ * 2 Omega), which bounds the spectrum of dt L; otherwise REXI_ENUMERIC.
+ * Errors: REXI_EINVAL (N odd or < 2, dt <= 0, NULL pointers), REXI_ENUMERIC,
+ * REXI_ENOMEM, REXI_EDEVICE.
+ */
+int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta,
+                     int N, double dt, const double* U0, double* U1,
+                     hipStream_t stream);
+
+/*
+ * sh_synthesis -- spectral to grid for nf scalar fields (Section 3.2):
+ *   f(lambda_k, mu_j) = sum_l Pbar_l0 Re f_l0 + 2 Re sum_{m>=1} sum_l f_lm Pbar_lm(mu_j) e^{i m lambda_k}.
+ * spec: device complex128 [nf][modes]; grid: device float64 [nf][nlat][nlon].
+ * Errors: REXI_ENOTSUP for a linear-only context, REXI_EINVAL, REXI_EDEVICE.
+ */
+int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf,
+                 hipStream_t stream);
+
+/*
+ * sh_analysis -- grid to spectral for nf scalar fields by Gauss quadrature:
+ *   f_lm = sum_j w_j Pbar_lm(mu_j) (1/nlon) sum_k f_jk e^{-i m lambda_k}.
+ * grid: device float64 [nf][nlat][nlon]; spec: device complex128 [nf][modes].
+ * Errors: as sh_synthesis.
+ */
+int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf,
+                hipStream_t stream);
+
+/*
+ * swe_nonlinear_step -- integrates dU/dt = N(U) over tau with the
+ * second-order explicit Runge-Kutta method of Heun (Section 4.1 and Table 2,
+ * ``erk``):  U1 = U0 + tau/2 (N(U0) + N(U0 + tau N(U0))), where (Section 3)
+ *   N_h = -div(h V),  N_zeta = -div(zeta V),  N_delta = k.curl(zeta V) - lap(|V|^2 / 2)
+ * are formed pseudo-spectrally on the context's grid.  U0, U1: device states
+ * [3][modes]; U1 may equal U0 (in place).
+ * Errors: REXI_ENOTSUP for a linear-only context, REXI_EINVAL, REXI_EDEVICE.
+ */
+int swe_nonlinear_step(swe_ctx* ctx, double tau, const double* U0, double* U1,
+                       hipStream_t stream);
+
+/*
+ * swe_strang_step -- one step of l_rexi_n_erk_ver1 (Section 4.4, version 1):
+ *   U1 = N^{dt/2} o REXI^{dt} o N^{dt/2} (U0), 2 Heun steps and 1 REXI stage.
+ * Arguments as rexi_linear_step / swe_nonlinear_step; U1 may equal U0.
+ */
+int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta,
+                    int N, double dt, const double* U0, double* U1,
+                    hipStream_t stream);
+
+/* swe_sync -- waits for all work the context enqueued; returns REXI_EDEVICE
+ * if the device reported an error. */
+int swe_sync(swe_ctx* ctx);
+
+/* rexi_last_error -- thread-local text of the last error ("" if none).  The
+ * pointer stays valid until the next library call on the same thread. */
+const char* rexi_last_error(void);
+
+/*
+ * Per-kernel timing (tracing).  swe_profile(ctx, 1) starts recording a HIP
+ * event pair on the launch stream around every launch of the given kernels
+ * (up to 4096 launches per kernel between reads); swe_profile(ctx, 0) stops.
+ * swe_profile_read waits for the recorded events, returns the summed device
+ * duration [ms] and the launch count of one kernel since the last read, and
+ * resets that kernel's record.  kernel: REXI_KERNEL_*.
+ * Errors: REXI_EINVAL (NULL, bad kernel id), REXI_EDEVICE.
+ */
+enum {
+    REXI_KERNEL_SOLVE = 0,     /* banded chain solves + per-wave pole sums */
+    REXI_KERNEL_REDUCE = 1,    /* sum of the pole-block partial sums */
+    REXI_KERNEL_COUNT = 2
+};
+int swe_profile(swe_ctx* ctx, int enable);
+int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches);
+
+/*
+ * swe_set_tuning -- choose the launch shape of the REXI solve kernel:
+ * seg_rows = rows per register-resident segment of the chain sweep (8, 16 or
+ * 32), waves = waves per workgroup (1, 2 or 4).  0 keeps the current value.
+ * Errors: REXI_EINVAL for an unsupported value.
+ */
+int swe_set_tuning(swe_ctx* ctx, int seg_rows, int waves);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REXI_SWE_H */

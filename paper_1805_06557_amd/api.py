@@ -1,0 +1,157 @@
+"""Python binding of the C-ABI: argument marshalling only.
+
+Device memory and streams come from PyTorch (complex128 CUDA tensors for
+spectral states, float64 for grids); every computation runs in the library's
+HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+REXI_OK, REXI_EINVAL, REXI_ENOMEM, REXI_EDEVICE, REXI_ENOTSUP, REXI_ENUMERIC = 0, -1, -2, -3, -4, -5
+FN_EXP, FN_PSI1, FN_PSI2 = 0, 1, 2
+PREC_FP64, PREC_FP32_SOLVE, PREC_BF16_SPLIT, PREC_FP16_SPLIT = 0, 1, 2, 4
+KERNEL_SOLVE, KERNEL_REDUCE = 0, 1
+EARTH = dict(a=6.37122e6, g=9.80616, H=1.0e4, Omega=7.292e-5)
+
+
+class RexiError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != REXI_OK:
+        raise RexiError(rc, where, _lib.load().rexi_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def n_modes(L: int) -> int:
+    return (L + 1) * (L + 2) // 2
+
+
+def rexi_coefficients(fn: int, N: int, p0: float, y: float):
+    """alpha, beta (complex128 numpy arrays), r, mu -- see rexi_coefficients()."""
+    alpha = np.zeros(2 * N)
+    beta = np.zeros(2 * N)
+    r = ctypes.c_double()
+    mu = ctypes.c_double()
+    _check(_lib.load().rexi_coefficients(fn, N, p0, y, _dptr(alpha), _dptr(beta), ctypes.byref(r),
+                                         ctypes.byref(mu)), "rexi_coefficients")
+    return alpha.view(np.complex128), beta.view(np.complex128), r.value, mu.value
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _state_ptr(t, L: int, nf: int, name: str):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous complex128 CUDA tensor")
+    if t.numel() != nf * n_modes(L):
+        raise ValueError(f"{name}: expected {nf} x {n_modes(L)} complex entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _grid_ptr(t, nlat: int, nlon: int, nf: int, name: str):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous float64 CUDA tensor")
+    if t.numel() != nf * nlat * nlon:
+        raise ValueError(f"{name}: expected {nf} x {nlat} x {nlon} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host_coeffs(c) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.complex128))
+    return c.view(np.float64)
+
+
+class SWE:
+    """A library context (swe_ctx) for truncation L on an nlat x nlon Gauss grid."""
+
+    def __init__(self, L: int, nlat: int = 0, nlon: int = 0, a: float = EARTH["a"], g: float = EARTH["g"],
+                 H: float = EARTH["H"], Omega: float = EARTH["Omega"], prec: int = PREC_FP64):
+        self.L, self.nlat, self.nlon, self.prec = L, nlat, nlon, prec
+        self.a, self.g, self.H, self.Omega = a, g, H, Omega
+        self.modes = n_modes(L)
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        _check(self._lib.swe_create(L, nlat, nlon, a, g, H, Omega, prec, ctypes.byref(h)), "swe_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.swe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_tuning(self, seg_rows: int = 0, waves: int = 0) -> None:
+        _check(self._lib.swe_set_tuning(self._h, seg_rows, waves), "swe_set_tuning")
+
+    def rexi_linear_step(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        N = a.size // 2
+        if b.size != a.size:
+            raise ValueError("alpha and beta differ in length")
+        _check(self._lib.rexi_linear_step(self._h, _dptr(a), _dptr(b), N, float(dt),
+                                          _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                          _stream_handle(stream)), "rexi_linear_step")
+
+    def sh_synthesis(self, spec, grid, nf: int, stream=None) -> None:
+        _check(self._lib.sh_synthesis(self._h, _state_ptr(spec, self.L, nf, "spec"),
+                                      _grid_ptr(grid, self.nlat, self.nlon, nf, "grid"), nf,
+                                      _stream_handle(stream)), "sh_synthesis")
+
+    def sh_analysis(self, grid, spec, nf: int, stream=None) -> None:
+        _check(self._lib.sh_analysis(self._h, _grid_ptr(grid, self.nlat, self.nlon, nf, "grid"),
+                                     _state_ptr(spec, self.L, nf, "spec"), nf, _stream_handle(stream)),
+               "sh_analysis")
+
+    def nonlinear_step(self, tau: float, U0, U1, stream=None) -> None:
+        _check(self._lib.swe_nonlinear_step(self._h, float(tau), _state_ptr(U0, self.L, 3, "U0"),
+                                            _state_ptr(U1, self.L, 3, "U1"), _stream_handle(stream)),
+               "swe_nonlinear_step")
+
+    def strang_step(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        _check(self._lib.swe_strang_step(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt),
+                                         _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                         _stream_handle(stream)), "swe_strang_step")
+
+    def profile(self, enable: bool) -> None:
+        _check(self._lib.swe_profile(self._h, 1 if enable else 0), "swe_profile")
+
+    def profile_read(self, kernel: int):
+        """(total_ms, launches) recorded for one kernel since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(self._lib.swe_profile_read(self._h, kernel, ctypes.byref(ms), ctypes.byref(n)),
+               "swe_profile_read")
+        return ms.value, n.value
+
+    def sync(self) -> None:
+        _check(self._lib.swe_sync(self._h), "swe_sync")

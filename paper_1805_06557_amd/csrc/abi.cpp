@@ -1,0 +1,290 @@
+// The C-ABI entry points: argument checks, context set-up, coefficient
+// caching and the contour check, then the kernel launches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace rexi {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? REXI_ENOMEM : REXI_EDEVICE;
+}
+
+namespace {
+
+uint64_t fnv1a(const void* data, size_t bytes, uint64_t h) {
+    const unsigned char* p = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+// RAII guard that makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Uploads (alpha, beta) if they differ from the cached set and checks that the
+// poles enclose the spectrum of dt L.
+int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                  hipStream_t stream) {
+    uint64_t key = 1469598103934665603ULL;
+    key = fnv1a(alpha, sizeof(double) * 2 * N, key);
+    key = fnv1a(beta, sizeof(double) * 2 * N, key);
+    key = fnv1a(&N, sizeof(N), key);
+    if (ctx->poles_valid && key == ctx->poles_key && N == ctx->poles_n && dt == ctx->poles_dt)
+        return REXI_OK;
+
+    std::vector<PoleData> pd(N);
+    build_pole_data(alpha, beta, N, pd.data());
+    for (int n = 0; n < N; ++n) {
+        const PoleData& q = pd[n];
+        if (!std::isfinite(q.zr) || !std::isfinite(q.zi) || !std::isfinite(q.wr) || !std::isfinite(q.wi))
+            return fail(REXI_EINVAL, "rexi_linear_step: non-finite alpha or beta");
+    }
+    const double rho = dt * (std::sqrt(ctx->g * ctx->H * ctx->L * (ctx->L + 1.0)) / ctx->a + 2.0 * ctx->Omega);
+    const double probes[5] = {-rho, -0.5 * rho, 0.0, 0.5 * rho, rho};
+    for (double w : probes) {
+        const int wn = winding_number(pd.data(), N, 0.0, w);
+        if (wn != 1 && wn != -1) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          "rexi_linear_step: the poles do not enclose the spectrum of dt L "
+                          "(winding %d around %.6g i; rho = %.6g)", wn, w, rho);
+            return fail(REXI_ENUMERIC, buf);
+        }
+    }
+    if (!(min_distance_to_segment(pd.data(), N, rho) > 1e-6 * (1.0 + rho)))
+        return fail(REXI_ENUMERIC, "rexi_linear_step: a pole lies on the spectrum of dt L");
+
+    if (N > ctx->poles_cap) {
+        if (ctx->d_poles) REXI_HIP(hipFree(ctx->d_poles));
+        ctx->d_poles = nullptr;
+        ctx->poles_cap = 0;
+        if (hipMalloc(&ctx->d_poles, sizeof(PoleData) * N) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi_linear_step: cannot allocate pole table");
+        ctx->poles_cap = N;
+    }
+    // The host vector dies at return: copy synchronously with respect to the host.
+    REXI_HIP(hipMemcpyAsync(ctx->d_poles, pd.data(), sizeof(PoleData) * N, hipMemcpyHostToDevice, stream));
+    REXI_HIP(hipStreamSynchronize(stream));
+    ctx->poles_key = key;
+    ctx->poles_n = N;
+    ctx->poles_dt = dt;
+    ctx->poles_valid = true;
+    return REXI_OK;
+}
+
+}  // namespace
+
+int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream) {
+    Profiler& p = ctx->prof;
+    if (!p.enabled || p.count[kernel] >= Profiler::kCap) return -1;
+    const int slot = p.count[kernel];
+    if (!p.start[kernel]) {
+        p.start[kernel] = new (std::nothrow) hipEvent_t[Profiler::kCap]();
+        p.stop[kernel] = new (std::nothrow) hipEvent_t[Profiler::kCap]();
+        if (!p.start[kernel] || !p.stop[kernel]) return -1;
+    }
+    if (!p.start[kernel][slot] && hipEventCreate(&p.start[kernel][slot]) != hipSuccess) return -1;
+    if (!p.stop[kernel][slot] && hipEventCreate(&p.stop[kernel][slot]) != hipSuccess) return -1;
+    if (hipEventRecord(p.start[kernel][slot], stream) != hipSuccess) return -1;
+    return slot;
+}
+
+void prof_end(swe_ctx* ctx, int kernel, int slot, hipStream_t stream) {
+    if (slot < 0) return;
+    if (hipEventRecord(ctx->prof.stop[kernel][slot], stream) == hipSuccess) ctx->prof.count[kernel] = slot + 1;
+}
+
+}  // namespace rexi
+
+using namespace rexi;
+
+extern "C" {
+
+const char* rexi_last_error(void) { return rexi::g_last_error.c_str(); }
+
+int rexi_coefficients(int fn, int N, double p0, double y, double* alpha, double* beta, double* r,
+                      double* mu) {
+    return rexi::coefficients(fn, N, p0, y, alpha, beta, r, mu);
+}
+
+int swe_create(int L, int nlat, int nlon, double a, double g, double H, double Omega, int prec,
+               swe_ctx** out) {
+    if (!out) return fail(REXI_EINVAL, "swe_create: NULL output pointer");
+    *out = nullptr;
+    if (L < 1 || L > 1023) return fail(REXI_EINVAL, "swe_create: L must be in [1, 1023]");
+    if (!(a > 0) || !(g > 0) || !(H > 0) || !(Omega >= 0) || !std::isfinite(a) || !std::isfinite(g) ||
+        !std::isfinite(H) || !std::isfinite(Omega))
+        return fail(REXI_EINVAL, "swe_create: a, g, H must be positive and Omega non-negative");
+    const bool linear_only = nlat == 0 && nlon == 0;
+    if (!linear_only) {
+        if (nlat <= L || (nlat & 1)) return fail(REXI_EINVAL, "swe_create: nlat must be even and exceed L");
+        if (nlon <= 2 * L || (nlon % 4)) return fail(REXI_EINVAL, "swe_create: nlon must exceed 2L and be a multiple of 4");
+    }
+    if (prec & ~(REXI_PREC_FP32_SOLVE | REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT))
+        return fail(REXI_EINVAL, "swe_create: unknown precision flags");
+    if ((prec & REXI_PREC_BF16_SPLIT) && (prec & REXI_PREC_FP16_SPLIT))
+        return fail(REXI_EINVAL, "swe_create: BF16 and FP16 Legendre modes are exclusive");
+
+    swe_ctx* ctx = new (std::nothrow) swe_ctx;
+    if (!ctx) return fail(REXI_ENOMEM, "swe_create: out of host memory");
+    ctx->L = L;
+    ctx->nlat = nlat;
+    ctx->nlon = nlon;
+    ctx->prec = prec;
+    ctx->a = a;
+    ctx->g = g;
+    ctx->H = H;
+    ctx->Omega = Omega;
+    ctx->modes = n_modes(L);
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "swe_create: hipGetDevice");
+    }
+    std::vector<ModeCoef> coef(ctx->modes);
+    build_mode_coef(L, a, g, Omega, coef.data());
+    e = hipMalloc(&ctx->d_coef, sizeof(ModeCoef) * ctx->modes);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_coef, coef.data(), sizeof(ModeCoef) * ctx->modes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        swe_destroy(ctx);
+        return hip_fail(e, "swe_create: uploading operator tables");
+    }
+    *out = ctx;
+    return REXI_OK;
+}
+
+int swe_destroy(swe_ctx* ctx) {
+    if (!ctx) return REXI_OK;
+    DeviceGuard guard(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->d_coef) (void)hipFree(ctx->d_coef);
+    if (ctx->d_poles) (void)hipFree(ctx->d_poles);
+    if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+    for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {
+        for (int i = 0; ctx->prof.start[k] && i < Profiler::kCap; ++i) {
+            if (ctx->prof.start[k][i]) (void)hipEventDestroy(ctx->prof.start[k][i]);
+            if (ctx->prof.stop[k][i]) (void)hipEventDestroy(ctx->prof.stop[k][i]);
+        }
+        delete[] ctx->prof.start[k];
+        delete[] ctx->prof.stop[k];
+    }
+    delete ctx;
+    return REXI_OK;
+}
+
+int swe_set_tuning(swe_ctx* ctx, int seg_rows, int waves) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_set_tuning: NULL context");
+    if (seg_rows && seg_rows != 8 && seg_rows != 16 && seg_rows != 32)
+        return fail(REXI_EINVAL, "swe_set_tuning: seg_rows must be 8, 16 or 32");
+    if (waves && waves != 1 && waves != 2 && waves != 4)
+        return fail(REXI_EINVAL, "swe_set_tuning: waves must be 1, 2 or 4");
+    if (seg_rows) ctx->tune.seg_rows = seg_rows;
+    if (waves) ctx->tune.waves = waves;
+    return REXI_OK;
+}
+
+int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                     const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx) return fail(REXI_EINVAL, "rexi_linear_step: NULL context");
+    if (!alpha || !beta || !U0 || !U1) return fail(REXI_EINVAL, "rexi_linear_step: NULL pointer");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "rexi_linear_step: N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "rexi_linear_step: dt must be positive");
+    const size_t bytes = sizeof(double) * 6 * ctx->modes;
+    const char* a0 = reinterpret_cast<const char*>(U0);
+    const char* a1 = reinterpret_cast<const char*>(U1);
+    if (a0 < a1 + bytes && a1 < a0 + bytes) return fail(REXI_EINVAL, "rexi_linear_step: U0 and U1 overlap");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "rexi_linear_step: cannot select the context's device");
+    int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
+    if (rc != REXI_OK) return rc;
+    return launch_rexi_solve(ctx, N, dt, U0, U1, stream);
+}
+
+int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStream_t stream) {
+    (void)spec; (void)grid; (void)nf; (void)stream;
+    if (!ctx) return fail(REXI_EINVAL, "sh_synthesis: NULL context");
+    return fail(REXI_ENOTSUP, "sh_synthesis: not available");
+}
+
+int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStream_t stream) {
+    (void)spec; (void)grid; (void)nf; (void)stream;
+    if (!ctx) return fail(REXI_EINVAL, "sh_analysis: NULL context");
+    return fail(REXI_ENOTSUP, "sh_analysis: not available");
+}
+
+int swe_nonlinear_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
+    (void)tau; (void)U0; (void)U1; (void)stream;
+    if (!ctx) return fail(REXI_EINVAL, "swe_nonlinear_step: NULL context");
+    return fail(REXI_ENOTSUP, "swe_nonlinear_step: not available");
+}
+
+int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                    const double* U0, double* U1, hipStream_t stream) {
+    (void)alpha; (void)beta; (void)N; (void)dt; (void)U0; (void)U1; (void)stream;
+    if (!ctx) return fail(REXI_EINVAL, "swe_strang_step: NULL context");
+    return fail(REXI_ENOTSUP, "swe_strang_step: not available");
+}
+
+int swe_profile(swe_ctx* ctx, int enable) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_profile: NULL context");
+    ctx->prof.enabled = enable != 0;
+    return REXI_OK;
+}
+
+int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches) {
+    if (!ctx || !total_ms || !launches) return fail(REXI_EINVAL, "swe_profile_read: NULL argument");
+    if (kernel < 0 || kernel >= REXI_KERNEL_COUNT) return fail(REXI_EINVAL, "swe_profile_read: bad kernel id");
+    DeviceGuard guard(ctx->device);
+    Profiler& p = ctx->prof;
+    double sum = 0.0;
+    for (int i = 0; i < p.count[kernel]; ++i) {
+        REXI_HIP(hipEventSynchronize(p.stop[kernel][i]));
+        float ms = 0.0f;
+        REXI_HIP(hipEventElapsedTime(&ms, p.start[kernel][i], p.stop[kernel][i]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = p.count[kernel];
+    p.count[kernel] = 0;
+    return REXI_OK;
+}
+
+int swe_sync(swe_ctx* ctx) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_sync: NULL context");
+    DeviceGuard guard(ctx->device);
+    REXI_HIP(hipDeviceSynchronize());
+    return REXI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "rexi_swe.h"
+
+namespace rexi {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define REXI_HIP(call)                                   \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return ::rexi::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------- host numerics --
+inline int n_modes(int L) { return (L + 1) * (L + 2) / 2; }
+inline int mode_index(int L, int l, int m) { return m * (2 * L + 3 - m) / 2 + (l - m); }
+
+// Per-mode coefficients of the chain form of (z I - dt L), m-major like the
+// spectral state.  For degree k of order m:
+//   cm = 2 Omega (k+1)/k eps_k      coupling to degree k-1 (0 if k-1 < max(m,1))
+//   cp = 2 Omega k/(k+1) eps_{k+1}  coupling to degree k+1 (0 if k = L)
+//   s  = 2 Omega m / (k(k+1))       (0 for k = 0)
+//   gN = g k(k+1) / a^2
+struct ModeCoef {
+    double cm, cp, s, gN;
+};
+
+void build_mode_coef(int L, double a, double g, double Omega, ModeCoef* out);
+
+// Poles of one coefficient set in the form the solve kernel uses:
+// z = -alpha (contour point), zi = 1/z, w = -beta, so that
+//   sum_n beta_n (dt L + alpha_n)^{-1} u = sum_n w_n (z_n - dt L)^{-1} u.
+struct PoleData {
+    double zr, zi, zir, zii, wr, wi;
+};
+
+// Fills pd[0..N) from interleaved alpha/beta (1/z in extended precision).
+void build_pole_data(const double* alpha, const double* beta, int N, PoleData* pd);
+
+// Winding number of the closed polygon z_0 .. z_{N-1} around the point (x, y).
+int winding_number(const PoleData* pd, int N, double x, double y);
+
+// Smallest distance between a pole z_n and the segment i[-rho, rho].
+double min_distance_to_segment(const PoleData* pd, int N, double rho);
+
+// Extended-precision REXI coefficients (see rexi_coefficients in rexi_swe.h).
+int coefficients(int fn, int N, double p0, double y, double* alpha, double* beta,
+                 double* r, double* mu);
+
+// ------------------------------------------------------------- context --
+struct Profiler {
+    static constexpr int kCap = 4096;
+    bool enabled = false;
+    hipEvent_t* start[REXI_KERNEL_COUNT] = {};
+    hipEvent_t* stop[REXI_KERNEL_COUNT] = {};
+    int count[REXI_KERNEL_COUNT] = {};
+};
+
+// Records the start event of `kernel` (if profiling) and returns its slot or -1.
+int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream);
+void prof_end(swe_ctx* ctx, int kernel, int slot, hipStream_t stream);
+
+struct Tuning {
+    int seg_rows = 16;   // rows per register-resident segment (8, 16, 32)
+    int waves = 1;       // waves per workgroup (1, 2, 4)
+};
+
+}  // namespace rexi
+
+struct swe_ctx {
+    int L = 0, nlat = 0, nlon = 0, prec = 0, device = 0, modes = 0;
+    double a = 0, g = 0, H = 0, Omega = 0;
+    rexi::Tuning tune;
+    rexi::Profiler prof;
+
+    // REXI tables
+    rexi::ModeCoef* d_coef = nullptr;  // [modes]
+
+    // cached coefficient set
+    rexi::PoleData* d_poles = nullptr;
+    int poles_cap = 0;
+    int poles_n = 0;
+    uint64_t poles_key = 0;
+    double poles_dt = 0;
+    bool poles_valid = false;
+
+    // partial sums over pole blocks: [npb][3][modes] complex
+    double* d_partial = nullptr;
+    size_t partial_cap = 0;   // in doubles
+};
+
+namespace rexi {
+
+// Launches the chain solve + reduction for one REXI stage on `stream`.
+int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
+                      hipStream_t stream);
+
+}  // namespace rexi

@@ -1,0 +1,135 @@
+"""GPU parity of rexi_linear_step against the oracle (Eq. rexi with L = L_g + L_c).
+
+FP64 bar: every entry within max(1e-12, 4 u kappa) of the oracle, relative to
+the largest entry of its field, where kappa = max_{|w|<=rho} sum |beta_n| /
+|i w + alpha_n| is the condition number of the rational sum (the floor any
+implementation of it has, Section 4.2.2).
+FP32-solve bar: 16 u_32 kappa relative per field (diagonals and right-hand
+sides formed in FP64, sweep in FP32, FP64 sum).
+"""
+import numpy as np
+import pytest
+
+from oracle import linear as olinear
+from oracle import rexi as orexi
+from oracle.operator import Params, mode_index, spectral_radius_bound
+from paper_1805_06557_amd.inputs import random_state
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U64 = np.finfo(np.float64).eps / 2
+U32 = np.finfo(np.float32).eps / 2
+
+
+def _api():
+    from paper_1805_06557_amd import api
+    return api
+
+
+def _kappa_max(alpha, beta, rho):
+    w = np.linspace(-rho, rho, 401)
+    return float(orexi.kappa(alpha, beta, 1j * w).max())
+
+
+def _run_gpu(L, alpha, beta, dt, U0, prec=0, seg_rows=0):
+    api = _api()
+    ctx = api.SWE(L, prec=prec)
+    if seg_rows:
+        ctx.set_tuning(seg_rows=seg_rows)
+    d0 = torch.from_numpy(U0).cuda()
+    d1 = torch.empty_like(d0)
+    ctx.rexi_linear_step(alpha, beta, dt, d0, d1)
+    torch.cuda.synchronize()
+    out = d1.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def _assert_close(got, ref, tol, orders=None, L=None):
+    if orders is not None:
+        idx = np.concatenate([np.arange(mode_index(L, m, m), mode_index(L, m, m) + L - m + 1) for m in orders])
+        got, ref = got[:, idx], ref[:, idx]
+    for f in range(3):
+        scale = np.abs(ref[f]).max()
+        err = np.abs(got[f] - ref[f]).max()
+        assert err <= tol * scale, (f, err / scale, tol)
+
+
+CASES = [
+    # name, L, N, dt, p0, y, seg_rows
+    ("T31-paper-contour", 31, 128, 3600.0, 10.0, 30.0, 16),
+    ("ragged-rows-and-poles", 20, 70, 3600.0, 8.0, 12.0, 16),
+    ("checkpointed-segments", 45, 96, 3600.0, 8.0, 16.0, 8),
+    ("smallest", 1, 4, 600.0, 1.0, 2.0, 8),
+    ("single-pole-block-long-chain", 70, 64, 1800.0, 6.0, 9.0, 16),
+]
+
+
+@pytest.mark.parametrize("name,L,N,dt,p0,y,S", CASES, ids=[c[0] for c in CASES])
+def test_fp64_parity(name, L, N, dt, p0, y, S):
+    p = Params()
+    rho = spectral_radius_bound(L, dt, p)
+    assert y > rho
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, y)
+    U0 = random_state(L, 100 + L)
+    ref = olinear.rexi_linear_step(U0, alpha, beta, dt, L, p)
+    got = _run_gpu(L, alpha, beta, dt, U0, seg_rows=S)
+    tol = max(1e-12, 4 * U64 * _kappa_max(alpha, beta, rho))
+    _assert_close(got, ref, tol)
+
+
+def test_fp32_solve_parity_t31():
+    L, N, dt = 31, 128, 3600.0
+    p = Params()
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, N, 10.0, 30.0)
+    U0 = random_state(L, 7)
+    ref = olinear.rexi_linear_step(U0, alpha, beta, dt, L, p)
+    got = _run_gpu(L, alpha, beta, dt, U0, prec=1)
+    tol = 16 * U32 * _kappa_max(alpha, beta, spectral_radius_bound(L, dt, p))
+    _assert_close(got, ref, tol)
+
+
+def test_segment_length_does_not_change_bits():
+    """Re-sweeping a segment from its checkpoint repeats the same operations in
+    the same order, and the pole sum is grouped the same way, so every segment
+    length gives bit-identical results; repeated calls are bit-identical too."""
+    L, N, dt = 57, 200, 3600.0
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, N, 8.0, 16.0)
+    U0 = random_state(L, 8)
+    outs = [_run_gpu(L, alpha, beta, dt, U0, seg_rows=S) for S in (8, 16, 32, 16)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_t255_sampled_orders(prec):
+    """Full T255 / N = 800 in the launch shape the benchmark uses, checked on a
+    sample of zonal orders the oracle solves one by one."""
+    from paper_1805_06557_amd import configs
+    w = configs.T255_FP32 if prec else configs.T255_FP64
+    p = Params()
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, w.N, w.p0, w.y)
+    U0 = random_state(w.L, 2)
+    orders = [0, 1, 2, 97, 200, 254, 255]
+    ref = olinear.rexi_linear_step(U0, alpha, beta, w.dt, w.L, p, orders=orders)
+    got = _run_gpu(w.L, alpha, beta, w.dt, U0, prec=prec)
+    kap = _kappa_max(alpha, beta, spectral_radius_bound(w.L, w.dt, p))
+    tol = max(1e-12, 4 * U64 * kap) if prec == 0 else 16 * U32 * kap
+    _assert_close(got, ref, tol, orders=orders, L=w.L)
+
+
+def test_contour_not_enclosing_spectrum_is_rejected():
+    api = _api()
+    L, dt = 31, 3600.0
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, 64, 2.0, 3.0)   # rho = 6.1 > y
+    ctx = api.SWE(L)
+    d0 = torch.zeros((3, api.n_modes(L)), dtype=torch.complex128, device="cuda")
+    d1 = torch.empty_like(d0)
+    with pytest.raises(api.RexiError) as ei:
+        ctx.rexi_linear_step(alpha, beta, dt, d0, d1)
+    assert ei.value.code == api.REXI_ENUMERIC
+    with pytest.raises(api.RexiError) as ei:
+        ctx.rexi_linear_step(alpha, beta, dt, d0, d0)
+    assert ei.value.code == api.REXI_EINVAL
+    ctx.close()
