@@ -175,9 +175,12 @@ const char* rexi_last_error(void);
  * Errors: REXI_EINVAL (NULL, bad kernel id), REXI_EDEVICE.
  */
 enum {
-    REXI_KERNEL_SOLVE = 0,     /* banded chain solves + per-wave pole sums */
-    REXI_KERNEL_REDUCE = 1,    /* sum of the pole-block partial sums */
-    REXI_KERNEL_COUNT = 2
+    REXI_KERNEL_SOLVE = 0,       /* banded chain solves + per-wave pole sums */
+    REXI_KERNEL_REDUCE = 1,      /* sum of the pole-block partial sums */
+    REXI_KERNEL_LEG_SYNTH = 2,   /* Legendre synthesis (spectral -> Fourier) */
+    REXI_KERNEL_RING = 3,        /* longitude FFTs and pointwise products */
+    REXI_KERNEL_LEG_ANAL = 4,    /* Legendre analysis (Fourier -> spectral) */
+    REXI_KERNEL_COUNT = 5
 };
 int swe_profile(swe_ctx* ctx, int enable);
 int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches);

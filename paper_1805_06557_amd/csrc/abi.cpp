@@ -102,6 +102,81 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     return REXI_OK;
 }
 
+template <typename T>
+int upload(T** dst, const T* src, size_t count) {
+    REXI_HIP(hipMalloc(dst, sizeof(T) * (count ? count : 1)));
+    if (count) REXI_HIP(hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice));
+    return REXI_OK;
+}
+
+// Grid set-up: Gauss nodes, Legendre recurrence tables and seeds, FFT plan and workspaces.
+int setup_sht(swe_ctx* ctx) {
+    ShtHost h;
+    build_legendre_tables(ctx->L, ctx->nlat, ctx->a, h);
+    int rc;
+    if ((rc = upload(&ctx->d_rec, h.rec.data(), h.rec.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_aon, h.a_over_n.data(), h.a_over_n.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_noa2, h.n_over_a2.data(), h.n_over_a2.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_mu, h.mu.data(), h.mu.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_sint, h.sint.data(), h.sint.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_w, h.w.data(), h.w.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_seed_m, h.seed_m.data(), h.seed_m.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_seed_e, h.seed_e.data(), h.seed_e.size())) != REXI_OK) return rc;
+    // FFT of nlon reals = complex FFT of M = nlon/2 points, M = 2^a 3^b
+    const int M = ctx->nlon / 2;
+    std::vector<int> radix;
+    int rem = M;
+    while (rem % 4 == 0) { radix.push_back(4); rem /= 4; }
+    while (rem % 2 == 0) { radix.push_back(2); rem /= 2; }
+    while (rem % 3 == 0) { radix.push_back(3); rem /= 3; }
+    if (rem != 1) return fail(REXI_EINVAL, "swe_create: nlon/2 must be of the form 2^a 3^b");
+    ctx->npass = static_cast<int>(radix.size());
+    if ((rc = upload(&ctx->d_radix, radix.data(), radix.size())) != REXI_OK) return rc;
+    std::vector<double> tw, twr;
+    build_twiddles(M, tw);
+    build_twiddles(ctx->nlon, twr);
+    twr.resize(2 * static_cast<size_t>(M));
+    if ((rc = upload(&ctx->d_tw, tw.data(), tw.size())) != REXI_OK) return rc;
+    if ((rc = upload(&ctx->d_twr, twr.data(), twr.size())) != REXI_OK) return rc;
+    const size_t st = static_cast<size_t>(6) * ctx->modes;
+    REXI_HIP(hipMalloc(&ctx->d_ustar, sizeof(double) * st));
+    REXI_HIP(hipMalloc(&ctx->d_n0, sizeof(double) * st));
+    REXI_HIP(hipMalloc(&ctx->d_tmpA, sizeof(double) * st));
+    REXI_HIP(hipMalloc(&ctx->d_tmpB, sizeof(double) * st));
+    return sht_configure_kernels(ctx);
+}
+
+// Makes both Fourier buffers hold at least nf fields.
+int reserve_fourier(swe_ctx* ctx, int nf) {
+    if (static_cast<size_t>(nf) <= ctx->four_cap) return REXI_OK;
+    if (ctx->d_fin) REXI_HIP(hipFree(ctx->d_fin));
+    if (ctx->d_fout) REXI_HIP(hipFree(ctx->d_fout));
+    ctx->d_fin = ctx->d_fout = nullptr;
+    ctx->four_cap = 0;
+    const size_t bytes = sizeof(double) * 2 * static_cast<size_t>(nf) * (ctx->L + 1) * ctx->nlat;
+    if (hipMalloc(&ctx->d_fin, bytes) != hipSuccess || hipMalloc(&ctx->d_fout, bytes) != hipSuccess)
+        return fail(REXI_ENOMEM, "cannot allocate Fourier workspace");
+    ctx->four_cap = static_cast<size_t>(nf);
+    return REXI_OK;
+}
+
+// One Heun step dU/dt = N(U) over tau on `stream`.
+int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
+    int rc;
+    if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
+    // stage 1: U* = U0 + tau N(U0), keep N(U0)
+    if ((rc = launch_legendre_synth(ctx, 1, U0, ctx->d_fin, 3, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0,
+                                   stream)) != REXI_OK)
+        return rc;
+    // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
+    if ((rc = launch_legendre_synth(ctx, 1, ctx->d_ustar, ctx->d_fin, 3, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    return launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau,
+                                stream);
+}
+
 }  // namespace
 
 int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream) {
@@ -180,6 +255,14 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
         swe_destroy(ctx);
         return hip_fail(e, "swe_create: uploading operator tables");
     }
+    if (!linear_only) {
+        const int rc = setup_sht(ctx);
+        if (rc != REXI_OK) {
+            const std::string msg = rexi_last_error();
+            swe_destroy(ctx);
+            return fail(rc, msg);
+        }
+    }
     *out = ctx;
     return REXI_OK;
 }
@@ -191,6 +274,11 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_coef) (void)hipFree(ctx->d_coef);
     if (ctx->d_poles) (void)hipFree(ctx->d_poles);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+    void* sht_bufs[] = {ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w, ctx->d_seed_m,
+                        ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_fin, ctx->d_fout,
+                        ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB};
+    for (void* p : sht_bufs)
+        if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {
         for (int i = 0; ctx->prof.start[k] && i < Profiler::kCap; ++i) {
             if (ctx->prof.start[k][i]) (void)hipEventDestroy(ctx->prof.start[k][i]);
@@ -232,28 +320,49 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int 
 }
 
 int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStream_t stream) {
-    (void)spec; (void)grid; (void)nf; (void)stream;
     if (!ctx) return fail(REXI_EINVAL, "sh_synthesis: NULL context");
-    return fail(REXI_ENOTSUP, "sh_synthesis: not available");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "sh_synthesis: linear-only context (no grid)");
+    if (!spec || !grid || nf < 1 || nf > 64) return fail(REXI_EINVAL, "sh_synthesis: bad pointer or nf");
+    DeviceGuard guard(ctx->device);
+    int rc;
+    if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
+    if ((rc = launch_legendre_synth(ctx, 0, spec, ctx->d_fin, nf, stream)) != REXI_OK) return rc;
+    return launch_ring(ctx, 0, ctx->d_fin, nullptr, nullptr, grid, nf, stream);
 }
 
 int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStream_t stream) {
-    (void)spec; (void)grid; (void)nf; (void)stream;
     if (!ctx) return fail(REXI_EINVAL, "sh_analysis: NULL context");
-    return fail(REXI_ENOTSUP, "sh_analysis: not available");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "sh_analysis: linear-only context (no grid)");
+    if (!spec || !grid || nf < 1 || nf > 64) return fail(REXI_EINVAL, "sh_analysis: bad pointer or nf");
+    DeviceGuard guard(ctx->device);
+    int rc;
+    if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 1, nullptr, ctx->d_fout, grid, nullptr, nf, stream)) != REXI_OK) return rc;
+    return launch_legendre_anal(ctx, 0, ctx->d_fout, spec, nf, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, stream);
 }
 
 int swe_nonlinear_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
-    (void)tau; (void)U0; (void)U1; (void)stream;
     if (!ctx) return fail(REXI_EINVAL, "swe_nonlinear_step: NULL context");
-    return fail(REXI_ENOTSUP, "swe_nonlinear_step: not available");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_nonlinear_step: linear-only context (no grid)");
+    if (!U0 || !U1) return fail(REXI_EINVAL, "swe_nonlinear_step: NULL state");
+    if (!std::isfinite(tau)) return fail(REXI_EINVAL, "swe_nonlinear_step: tau must be finite");
+    DeviceGuard guard(ctx->device);
+    return heun_step(ctx, tau, U0, U1, stream);
 }
 
 int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
                     const double* U0, double* U1, hipStream_t stream) {
-    (void)alpha; (void)beta; (void)N; (void)dt; (void)U0; (void)U1; (void)stream;
     if (!ctx) return fail(REXI_EINVAL, "swe_strang_step: NULL context");
-    return fail(REXI_ENOTSUP, "swe_strang_step: not available");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_strang_step: linear-only context (no grid)");
+    if (!alpha || !beta || !U0 || !U1) return fail(REXI_EINVAL, "swe_strang_step: NULL pointer");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "swe_strang_step: N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_strang_step: dt must be positive");
+    DeviceGuard guard(ctx->device);
+    int rc;
+    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
+    if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
+    return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
 }
 
 int swe_profile(swe_ctx* ctx, int enable) {

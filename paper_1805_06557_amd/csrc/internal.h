@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "rexi_swe.h"
 
@@ -58,6 +59,27 @@ double min_distance_to_segment(const PoleData* pd, int N, double rho);
 int coefficients(int fn, int N, double p0, double y, double* alpha, double* beta,
                  double* r, double* mu);
 
+// Three-term recurrence of the normalised associated Legendre functions for
+// degree l of order m:  Pbar_{l+1} = A mu Pbar_l - B Pbar_{l-1}  (A = 1/eps_{l+1},
+// B = eps_l/eps_{l+1}), and H_l = (1 - mu^2) dPbar_l/dmu = hA Pbar_{l+1} + hB Pbar_{l-1}
+// (hA = -l eps_{l+1}, hB = (l+1) eps_l).
+struct LegCoef {
+    double A, B, hA, hB;
+};
+
+struct ShtHost {
+    int half = 0;                          // nlat / 2
+    std::vector<double> mu, sint, w;       // northern nodes (mu descending), sin(theta), weights
+    std::vector<LegCoef> rec;              // [modes]
+    std::vector<double> a_over_n;          // [L+2]: a / (l(l+1)), 0 for l = 0
+    std::vector<double> n_over_a2;         // [L+2]: l(l+1) / a^2
+    std::vector<double> seed_m;            // [L+1][half] mantissa of Pbar_mm(mu_j)
+    std::vector<int> seed_e;               // [L+1][half] base-2 exponent (<= 0)
+};
+
+void build_legendre_tables(int L, int nlat, double a, ShtHost& out);
+void build_twiddles(int M, std::vector<double>& tw);
+
 // ------------------------------------------------------------- context --
 struct Profiler {
     static constexpr int kCap = 4096;
@@ -98,6 +120,27 @@ struct swe_ctx {
     // partial sums over pole blocks: [npb][3][modes] complex
     double* d_partial = nullptr;
     size_t partial_cap = 0;   // in doubles
+
+    // spherical-harmonic transforms (grid contexts only)
+    rexi::LegCoef* d_rec = nullptr;   // [modes]
+    double* d_aon = nullptr;          // [L+2]
+    double* d_noa2 = nullptr;         // [L+2]
+    double* d_mu = nullptr;           // [nlat/2]
+    double* d_sint = nullptr;         // [nlat/2]
+    double* d_w = nullptr;            // [nlat/2]
+    double* d_seed_m = nullptr;       // [L+1][nlat/2]
+    int* d_seed_e = nullptr;          // [L+1][nlat/2]
+    double* d_tw = nullptr;           // [nlon/2] complex
+    double* d_twr = nullptr;          // [nlon/2] complex
+    int* d_radix = nullptr;
+    int npass = 0;
+    double* d_fin = nullptr;          // Fourier coefficients [nf][L+1][nlat] complex
+    double* d_fout = nullptr;
+    size_t four_cap = 0;              // fields each Fourier buffer can hold
+    double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
+    double* d_n0 = nullptr;           // first tendency [3][modes]
+    double* d_tmpA = nullptr;         // Strang intermediates [3][modes]
+    double* d_tmpB = nullptr;
 };
 
 namespace rexi {
@@ -105,5 +148,18 @@ namespace rexi {
 // Launches the chain solve + reduction for one REXI stage on `stream`.
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
                       hipStream_t stream);
+
+// Spherical-harmonic transform stages (sht.hip).  kind 0: nf scalar fields;
+// kind 1: the non-linear set (synthesis: h, zeta, U, V from a state;
+// analysis: the tendency from hU, hV, zU, zV, KE with the Runge-Kutta update
+// out = U0 + c0 N + c1 Nprev and, if Nsave, a copy of N).
+int sht_configure_kernels(swe_ctx* ctx);
+int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* four, int nf, hipStream_t stream);
+int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
+                         const double* Nprev, double* Nsave, double* out, double c0, double c1,
+                         hipStream_t stream);
+// mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
+int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
+                hipStream_t stream);
 
 }  // namespace rexi
