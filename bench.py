@@ -49,20 +49,32 @@ def solve_flops(L, N):
     return N * n_modes(L) * (FLOPS_DELTA_ROW + FLOPS_ZETA_ROW)
 
 
-def cpu_baseline(w, seconds: float):
-    """Time the oracle's REXI stage on a bounded sample of zonal orders and
-    scale by the fraction of pole-rows it covers."""
+def cpu_baseline(w, seconds: float, full: bool):
+    """Time the oracle on a bounded sample of the workload.
+
+    REXI stage: the oracle's banded solves on a sample of zonal orders (taken
+    from the short end of the chain-length range), run over a process pool and
+    scaled by the fraction of pole-rows covered.  Non-linear stage (full steps
+    only): two Heun steps of the oracle timed whole, in-process."""
     import concurrent.futures as cf
 
-    import numpy as np
-
-    from oracle import linear, rexi
-    from oracle.operator import Params
+    from oracle import rexi
     from paper_1805_06557_amd.inputs import jet_state
 
     alpha, beta, _, _ = rexi.coefficients(rexi.FN_EXP, w.N, w.p0, w.y)
     U0 = jet_state(w.L, w.seed)
     cores = min(len(os.sched_getaffinity(0)), 16)
+    t_nl = 0.0
+    if full:
+        from oracle import nonlinear
+        from oracle.operator import Params
+        from oracle.sht import Grid
+        g = Grid(w.L, w.nlat, w.nlon, Params())
+        nonlinear.tendency(g, U0)                 # builds the Legendre tables (not timed)
+        t0 = time.perf_counter()
+        U = nonlinear.heun(g, U0, 0.5 * w.dt)
+        nonlinear.heun(g, U, 0.5 * w.dt)
+        t_nl = time.perf_counter() - t0
     # calibrate on one middle order, model the cost of order m as ~ (L - m + 1)^2
     # (the oracle assembles dense matrices), take orders from the short end
     mc = w.L // 2
@@ -84,13 +96,18 @@ def cpu_baseline(w, seconds: float):
     elapsed = time.perf_counter() - t0
     rows = sum(w.L - m + 1 for m in orders)
     frac = rows / n_modes(w.L)
+    t_rexi = elapsed / frac
+    sample = (f"REXI stage: zonal orders {min(orders)}..{max(orders)} ({len(orders)} of {w.L + 1}, "
+              f"{100 * frac:.1f}% of the pole-rows) in {elapsed:.1f} s over {cores} processes, "
+              f"scaled to {t_rexi:.1f} s per stage")
+    if full:
+        sample += f"; non-linear stage: two oracle Heun steps timed whole, {t_nl:.2f} s"
     return {
-        "value": w.N * frac / elapsed,
+        "value": w.N / (t_rexi + t_nl),
         "unit": "term-solves/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"REXI stage, zonal orders {min(orders)}..{max(orders)} ({len(orders)} of {w.L + 1}, "
-                  f"{100 * frac:.1f}% of the pole-rows), {elapsed:.1f} s wall over {cores} processes",
+        "sample": sample,
     }
 
 
@@ -158,8 +175,15 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(stop)
-    solve_ms, solve_n = ctx.profile_read(api.KERNEL_SOLVE)
-    red_ms, red_n = ctx.profile_read(api.KERNEL_REDUCE)
+    stage_ms = {}
+    for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, "sum_partials_kernel"),
+                      (api.KERNEL_LEG_SYNTH, "legendre_synth_kernel"), (api.KERNEL_RING, "ring_kernel"),
+                      (api.KERNEL_LEG_ANAL, "legendre_anal_kernel")]:
+        ms, n = ctx.profile_read(kid)
+        stage_ms[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+                          "ms_per_launch": ms / max(n, 1)}
+    solve_ms = stage_ms["rexi_chain_kernel"]["ms_per_step"] * args.steps
+    solve_n = int(round(stage_ms["rexi_chain_kernel"]["launches_per_step"] * args.steps))
     ctx.profile(False)
     if not torch.isfinite(torch.view_as_real(U)).all():
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
@@ -188,7 +212,8 @@ def main():
             "workload": f"{w.name}: {stage}, T{w.L}"
                         + (f" on {w.nlon}x{w.nlat} Gauss grid" if full else "")
                         + f", dt={w.dt:g} s, N={w.N} poles (p0={w.p0:g}, y={w.y:.4g}), "
-                        + ("FP32 banded solves + FP64 beta sum" if fp32 else "FP64"),
+                        + ("FP32 banded solves + FP64 beta sum" if fp32 else "FP64 solves")
+                        + (", FP64 transforms" if full else ""),
             "L": w.L, "N": w.N, "dt": w.dt, "stage": stage,
         },
         "sim_time_per_wall": w.dt / (ms_per_step * 1e-3),
@@ -205,10 +230,10 @@ def main():
             "launches": solve_n,
             "algorithmic_flops_per_launch": solve_flops(w.L, w.N),
         },
-        "other_kernels_ms_per_launch": {"sum_partials_kernel": red_ms / max(red_n, 1)},
+        "kernels": stage_ms,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, full)
     print(json.dumps(out))
 
 

@@ -90,41 +90,64 @@ struct SynArgs {
     double2* __restrict__ four;         // [nfo][L+1][nlat]
 };
 
+// Per-degree data of one order m staged in LDS (double2 slots per degree):
+// KIND 0: {A, B}, coefficient;  KIND 1: {A, B}, {hA, hB}, h, zeta, delta, {a/N, m a/N}.
+template <int KIND>
+struct SynStage {
+    static constexpr int SLOTS = KIND == 0 ? 2 : 6;
+};
+
 template <int KIND>
 __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
+    extern __shared__ __align__(16) double2 stg[];
+    constexpr int SL = SynStage<KIND>::SLOTS;
     const LegArgs& A = S.g;
     const int m = blockIdx.x;
+    const int Lm = A.L - m + 1;
     const int jt = blockIdx.z * WAVE + threadIdx.x;
     const bool valid = jt < A.half;
     const int j = valid ? jt : A.half - 1;
     const double mu = A.mu[j];
     const int base = m * (2 * A.L + 3 - m) / 2;
-    const LegCoef* rc = A.rec + base;
+    const double dm = static_cast<double>(m);
+    {
+        const double2* sp0 = S.spec + static_cast<size_t>(KIND == 0 ? blockIdx.y : 0) * A.modes + base;
+        for (int i = threadIdx.x; i < Lm; i += WAVE) {
+            const LegCoef c = A.rec[base + i];
+            stg[i * SL + 0] = make_double2(c.A, c.B);
+            if constexpr (KIND == 0) {
+                stg[i * SL + 1] = sp0[i];
+            } else {
+                const double aon = A.aon[m + i];
+                stg[i * SL + 1] = make_double2(c.hA, c.hB);
+                stg[i * SL + 2] = sp0[i];
+                stg[i * SL + 3] = sp0[i + A.modes];
+                stg[i * SL + 4] = sp0[i + 2 * A.modes];
+                stg[i * SL + 5] = make_double2(aon, dm * aon);
+            }
+        }
+    }
+    __syncthreads();
     constexpr int NACC = KIND == 0 ? 1 : 4;
     double2 E[NACC], O[NACC];
 #pragma unroll
     for (int f = 0; f < NACC; ++f) E[f] = O[f] = make_double2(0.0, 0.0);
-    const double2* sp0 = S.spec + static_cast<size_t>(KIND == 0 ? blockIdx.y : 0) * A.modes + base;
-    const double2* sp1 = sp0 + A.modes;
-    const double2* sp2 = sp1 + A.modes;
     Rec r = rec_start(A, m, j);
-    const double dm = static_cast<double>(m);
 
-    auto degree = [&](int l, auto odd) {
+    auto degree = [&](int i, auto odd) {
         constexpr bool ODD = decltype(odd)::value;
-        const int i = l - m;
-        double pn, h;
-        rec_step(rc[i], mu, r, pn, h);
+        const double2* st = stg + i * SL;
+        const double2 ab = st[0];
+        const double pn = __builtin_fma(ab.x * mu, r.p, -(ab.y * r.pm));
         const double p = r.p;
         if constexpr (KIND == 0) {
-            const double2 c = sp0[i];
-            if (ODD) caxpy(O[0], c, p); else caxpy(E[0], c, p);
+            if (ODD) caxpy(O[0], st[1], p); else caxpy(E[0], st[1], p);
         } else {
-            const double2 ch = sp0[i], cz = sp1[i], cd = sp2[i];
-            const double aon = A.aon[l];
-            const double hp = aon * h;          // (a/N) H
-            const double pp = dm * aon * p;     // (m a/N) Pbar
-            // h, zeta: P pass
+            const double2 hab = st[1];
+            const double h = __builtin_fma(hab.x, pn, hab.y * r.pm);
+            const double2 ch = st[2], cz = st[3], cd = st[4], fac = st[5];
+            const double hp = fac.x * h;         // (a/N) H
+            const double pp = fac.y * p;         // (m a/N) Pbar
             if (ODD) { caxpy(O[0], ch, p); caxpy(O[1], cz, p); }
             else     { caxpy(E[0], ch, p); caxpy(E[1], cz, p); }
             // U: i m chi Pbar / a = -i delta P'  (parity of P);  -psi H / a = zeta H'  (parity of H)
@@ -145,10 +168,12 @@ __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
         r.p = pn;
     };
 
-    int l = m;
-    for (; l + 1 <= A.L; l += 2) {
-        degree(l, std::integral_constant<bool, false>{});
-        degree(l + 1, std::integral_constant<bool, true>{});
+    int i = 0;
+    for (; i + 3 < Lm; i += 4) {
+        degree(i, std::integral_constant<bool, false>{});
+        degree(i + 1, std::integral_constant<bool, true>{});
+        degree(i + 2, std::integral_constant<bool, false>{});
+        degree(i + 3, std::integral_constant<bool, true>{});
         if (r.e < 0 && fabs(r.p) > kBig) {
             const int sh = min(400, -r.e);
             r.p = ldexp(r.p, -sh);
@@ -161,10 +186,12 @@ __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
             }
         }
     }
-    if (l <= A.L) degree(l, std::integral_constant<bool, false>{});
+    for (; i < Lm; ++i) {
+        if ((i & 1) == 0) degree(i, std::integral_constant<bool, false>{});
+        else degree(i, std::integral_constant<bool, true>{});
+    }
     if (!valid) return;
-    const int nfo = NACC;
-    for (int f = 0; f < nfo; ++f) {
+    for (int f = 0; f < NACC; ++f) {
         const size_t row = (static_cast<size_t>(KIND == 0 ? blockIdx.y : f) * (A.L + 1) + m) * A.nlat;
         const double2 n = make_double2(ldexp(E[f].x + O[f].x, r.e), ldexp(E[f].y + O[f].y, r.e));
         const double2 s = make_double2(ldexp(E[f].x - O[f].x, r.e), ldexp(E[f].y - O[f].y, r.e));
@@ -218,22 +245,36 @@ __device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, int 
     }
 }
 
+constexpr int RED_STRIDE = 72;   // doubles per staged output row (64 lanes + pad: 4-cycle LDS reads)
+
 template <int KIND, int D>
 __global__ __launch_bounds__(512) void legendre_anal_kernel(AnaArgs P) {
-    extern __shared__ __align__(16) double red[];       // [nwaves][D * NC][64]
+    extern __shared__ __align__(16) double smem[];
     constexpr int NC = AnaTraits<KIND>::NC;
     constexpr int NIN = AnaTraits<KIND>::NIN;
     constexpr int NO = D * NC;                           // outputs per chunk
+    constexpr int SL = KIND == 0 ? 1 : 3;                // staged double2 per degree
     const LegArgs& A = P.g;
     const int m = blockIdx.x;
+    const int Lm = A.L - m + 1;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1), wv = tid / WAVE;
     const int nthreads = blockDim.x;
+    const int nw = nthreads / WAVE;
     const bool valid = tid < A.half;
     const int j = valid ? tid : A.half - 1;
     const double mu = A.mu[j];
     const int base = m * (2 * A.L + 3 - m) / 2;
-    const LegCoef* rc = A.rec + base;
+    double* red = smem;                                                   // [nw][NO][RED_STRIDE]
+    double2* stg = reinterpret_cast<double2*>(smem + static_cast<size_t>(nw) * NO * RED_STRIDE);
+    for (int i = tid; i < Lm; i += nthreads) {
+        const LegCoef c = A.rec[base + i];
+        stg[i * SL] = make_double2(c.A, c.B);
+        if constexpr (KIND == 1) {
+            stg[i * SL + 1] = make_double2(c.hA, c.hB);
+            stg[i * SL + 2] = make_double2(A.noa2[m + i], 0.0);
+        }
+    }
     Rec r = rec_start(A, m, j);
     double2 Sv[NIN], Dv[NIN];
     load_folded<KIND>(P, m, j, r.e, Sv, Dv);
@@ -242,37 +283,41 @@ __global__ __launch_bounds__(512) void legendre_anal_kernel(AnaArgs P) {
         for (int f = 0; f < NIN; ++f) Sv[f] = Dv[f] = make_double2(0.0, 0.0);
     }
     const double dm = static_cast<double>(m);
-    // reduction layout: threads t -> output o = t / G, part g = t % G
+    // reduction: thread t -> output o = t / G, part g = t % G
     int G = 1;
-    while (G * 2 * NO <= nthreads && G < 8) G *= 2;
+    while (G * 2 * NO <= nthreads && G < 16) G *= 2;
     const int o_red = tid / G, g_red = tid % G;
     const int nvals = nthreads;                          // values per output
-    double* myred = red + static_cast<size_t>(wv) * NO * WAVE;
+    double* myred = red + static_cast<size_t>(wv) * NO * RED_STRIDE;
+    __syncthreads();
 
-    for (int l0 = m; l0 <= A.L; l0 += D) {
+    for (int i0 = 0; i0 < Lm; i0 += D) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const int l = l0 + d;
+            const int i = i0 + d;
             double c[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) c[k] = 0.0;
-            if (l <= A.L) {
-                double pn, h;
-                rec_step(rc[l - m], mu, r, pn, h);
+            if (i < Lm) {
+                const double2* st = stg + i * SL;
+                const double2 ab = st[0];
+                const double pn = __builtin_fma(ab.x * mu, r.p, -(ab.y * r.pm));
                 const double p = r.p;
-                const bool odd = d & 1;                  // (l - m) is l0 - m + d, l0 - m a multiple of D
+                const bool odd = d & 1;                  // l - m = i0 + d with i0 a multiple of D
                 if constexpr (KIND == 0) {
                     const double2 x = odd ? Dv[0] : Sv[0];
                     c[0] = x.x * p;
                     c[1] = x.y * p;
                 } else {
+                    const double2 hab = st[1];
+                    const double h = __builtin_fma(hab.x, pn, hab.y * r.pm);
                     // P terms take the fold of P's parity, H terms the opposite one
                     const double2 hU = odd ? Dv[0] : Sv[0], zU = odd ? Dv[2] : Sv[2];
                     const double2 zV = odd ? Dv[3] : Sv[3], ke = odd ? Dv[4] : Sv[4];
                     const double2 hVh = odd ? Sv[1] : Dv[1], zVh = odd ? Sv[3] : Dv[3];
                     const double2 zUh = odd ? Sv[2] : Dv[2];
                     const double pm2 = dm * p;                 // m Pbar
-                    const double pk = A.noa2[l] * p;           // l(l+1)/a^2 Pbar
+                    const double pk = st[2].x * p;             // l(l+1)/a^2 Pbar
                     // N_h = -(i m hU P - hV H)
                     c[0] = __builtin_fma(hU.y, pm2, hVh.x * h);
                     c[1] = __builtin_fma(-hU.x, pm2, hVh.y * h);
@@ -287,7 +332,7 @@ __global__ __launch_bounds__(512) void legendre_anal_kernel(AnaArgs P) {
                 r.p = pn;
             }
 #pragma unroll
-            for (int k = 0; k < NC; ++k) myred[(d * NC + k) * WAVE + lane] = c[k];
+            for (int k = 0; k < NC; ++k) myred[(d * NC + k) * RED_STRIDE + lane] = c[k];
         }
         // renormalise lanes whose recurrence has grown back into range
         if (r.e < 0 && fabs(r.p) > kBig) {
@@ -304,15 +349,15 @@ __global__ __launch_bounds__(512) void legendre_anal_kernel(AnaArgs P) {
         __syncthreads();
         if (o_red < NO) {
             double s = 0.0;
-            for (int i = g_red; i < nvals; i += G) {
-                const int w2 = i / WAVE, ln = i % WAVE;
-                s += red[(static_cast<size_t>(w2) * NO + o_red) * WAVE + ln];
+            for (int v = g_red; v < nvals; v += G) {
+                const int w2 = v / WAVE, ln = v % WAVE;
+                s += red[(static_cast<size_t>(w2) * NO + o_red) * RED_STRIDE + ln];
             }
             for (int msk = 1; msk < G; msk <<= 1) s += __shfl_xor(s, msk, G);
             const int d = o_red / NC, k = o_red % NC;
-            const int l = l0 + d;
-            if (g_red == 0 && l <= A.L) {
-                const size_t idx = static_cast<size_t>(base) + (l - m);
+            const int i = i0 + d;
+            if (g_red == 0 && i < Lm) {
+                const size_t idx = static_cast<size_t>(base) + i;
                 if constexpr (KIND == 0) {
                     double* dst = reinterpret_cast<double*>(P.spec + static_cast<size_t>(blockIdx.y) * A.modes + idx);
                     dst[k] = s;
@@ -560,19 +605,41 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     return r;
 }
 
+// LDS of the analysis kernel: staged reduction rows + staged per-degree coefficients.
+static size_t anal_lds_bytes(const swe_ctx* ctx, int kind) {
+    const int nw = (ctx->nlat / 2 + WAVE - 1) / WAVE;
+    const int D = kind == 0 ? 8 : (nw <= 3 ? 4 : 2);
+    const int NC = kind == 0 ? AnaTraits<0>::NC : AnaTraits<1>::NC;
+    const int SL = kind == 0 ? 1 : 3;
+    return sizeof(double) * nw * D * NC * RED_STRIDE + sizeof(double2) * SL * (ctx->L + 1);
+}
+
 static int ring_lds_bytes(const swe_ctx* ctx, int mode) {
     const int M = ctx->nlon / 2;
     const int arrays = mode == 2 ? 7 : 2;
     return arrays * M * static_cast<int>(sizeof(double2));
 }
 
-int sht_configure_kernels(swe_ctx* ctx) {
-    const int lds = ring_lds_bytes(ctx, 2);
-    if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_kernel<2>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
-            return fail(REXI_ENOTSUP, "swe_create: the longitude FFT of this grid needs more LDS than available");
+static int allow_lds(const void* fn, size_t bytes, const char* what) {
+    if (bytes <= 64 * 1024) return REXI_OK;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(REXI_ENOTSUP, std::string("swe_create: ") + what + " of this grid needs more LDS than available");
     }
+    return REXI_OK;
+}
+
+int sht_configure_kernels(swe_ctx* ctx) {
+    int rc;
+    if ((rc = allow_lds(reinterpret_cast<const void*>(&ring_kernel<2>), ring_lds_bytes(ctx, 2),
+                        "the longitude FFT")) != REXI_OK)
+        return rc;
+    if ((rc = allow_lds(reinterpret_cast<const void*>(&legendre_anal_kernel<1, 2>), anal_lds_bytes(ctx, 1),
+                        "the Legendre analysis")) != REXI_OK)
+        return rc;
+    if ((rc = allow_lds(reinterpret_cast<const void*>(&legendre_anal_kernel<1, 4>), anal_lds_bytes(ctx, 1),
+                        "the Legendre analysis")) != REXI_OK)
+        return rc;
     return REXI_OK;
 }
 
@@ -584,9 +651,11 @@ int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* fo
     const int tiles = (ctx->nlat / 2 + WAVE - 1) / WAVE;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_SYNTH, stream);
     if (kind == 0) {
-        hipLaunchKernelGGL(legendre_synth_kernel<0>, dim3(ctx->L + 1, nf, tiles), dim3(WAVE), 0, stream, S);
+        const size_t lds = sizeof(double2) * SynStage<0>::SLOTS * (ctx->L + 1);
+        hipLaunchKernelGGL(legendre_synth_kernel<0>, dim3(ctx->L + 1, nf, tiles), dim3(WAVE), lds, stream, S);
     } else {
-        hipLaunchKernelGGL(legendre_synth_kernel<1>, dim3(ctx->L + 1, 1, tiles), dim3(WAVE), 0, stream, S);
+        const size_t lds = sizeof(double2) * SynStage<1>::SLOTS * (ctx->L + 1);
+        hipLaunchKernelGGL(legendre_synth_kernel<1>, dim3(ctx->L + 1, 1, tiles), dim3(WAVE), lds, stream, S);
     }
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_SYNTH, slot, stream);
@@ -610,14 +679,16 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
     const int nw = (half + WAVE - 1) / WAVE;
     const int threads = nw * WAVE;
     if (threads > 512) return fail(REXI_ENOTSUP, "Legendre analysis: more than 512 northern latitudes");
-    constexpr int D = 2;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
     if (kind == 0) {
-        const size_t lds = sizeof(double) * nw * D * AnaTraits<0>::NC * WAVE;
-        hipLaunchKernelGGL((legendre_anal_kernel<0, D>), dim3(ctx->L + 1, nf), dim3(threads), lds, stream, P);
+        const size_t lds = anal_lds_bytes(ctx, 0);
+        hipLaunchKernelGGL((legendre_anal_kernel<0, 8>), dim3(ctx->L + 1, nf), dim3(threads), lds, stream, P);
+    } else if (nw <= 3) {
+        const size_t lds = anal_lds_bytes(ctx, 1);
+        hipLaunchKernelGGL((legendre_anal_kernel<1, 4>), dim3(ctx->L + 1, 1), dim3(threads), lds, stream, P);
     } else {
-        const size_t lds = sizeof(double) * nw * D * AnaTraits<1>::NC * WAVE;
-        hipLaunchKernelGGL((legendre_anal_kernel<1, D>), dim3(ctx->L + 1, 1), dim3(threads), lds, stream, P);
+        const size_t lds = anal_lds_bytes(ctx, 1);
+        hipLaunchKernelGGL((legendre_anal_kernel<1, 2>), dim3(ctx->L + 1, 1), dim3(threads), lds, stream, P);
     }
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
