@@ -73,11 +73,22 @@ struct ShtHost {
     std::vector<LegCoef> rec;              // [modes]
     std::vector<double> a_over_n;          // [L+2]: a / (l(l+1)), 0 for l = 0
     std::vector<double> n_over_a2;         // [L+2]: l(l+1) / a^2
-    std::vector<double> seed_m;            // [L+1][half] mantissa of Pbar_mm(mu_j)
-    std::vector<int> seed_e;               // [L+1][half] base-2 exponent (<= 0)
+    std::vector<long double> mu_ld, sint_ld;  // the same nodes in 80-bit
+};
+
+// Degree segments: the degrees l = m..L of every order are cut into runs of
+// seg_len; each run restarts the recurrence from (Pbar_{k0-1}, Pbar_{k0}) at
+// its first degree k0, stored as mantissas times 2^e (e <= 0, shared by the pair).
+struct SegHost {
+    int seg_len = 0, nseg = 0;
+    std::vector<int> seg_m, seg_i0, seg_n;  // order, first degree offset l - m, degree count
+    std::vector<int> segbase;               // [L+2] first segment of order m
+    std::vector<double> seed_pm, seed_p;    // [nseg][half]
+    std::vector<int> seed_e;                // [nseg][half]
 };
 
 void build_legendre_tables(int L, int nlat, double a, ShtHost& out);
+void build_segments(int L, int seg_len, const ShtHost& sh, SegHost& out);
 void build_twiddles(int M, std::vector<double>& tw);
 
 // ------------------------------------------------------------- context --
@@ -128,14 +139,21 @@ struct swe_ctx {
     double* d_mu = nullptr;           // [nlat/2]
     double* d_sint = nullptr;         // [nlat/2]
     double* d_w = nullptr;            // [nlat/2]
-    double* d_seed_m = nullptr;       // [L+1][nlat/2]
-    int* d_seed_e = nullptr;          // [L+1][nlat/2]
+    int nseg = 0;                     // degree segments over all orders
+    int* d_seg_m = nullptr;           // [nseg]
+    int* d_seg_i0 = nullptr;          // [nseg]
+    int* d_seg_n = nullptr;           // [nseg]
+    int* d_segbase = nullptr;         // [L+2]
+    double* d_seed_pm = nullptr;      // [nseg][nlat/2]
+    double* d_seed_p = nullptr;       // [nseg][nlat/2]
+    int* d_seed_e = nullptr;          // [nseg][nlat/2]
+    double* d_part = nullptr;         // synthesis partial sums [nf][nseg][nlat] complex
+    size_t part_cap = 0;              // fields the partial buffer can hold
     double* d_tw = nullptr;           // [nlon/2] complex
     double* d_twr = nullptr;          // [nlon/2] complex
     int* d_radix = nullptr;
     int npass = 0;
-    double* d_fin = nullptr;          // Fourier coefficients [nf][L+1][nlat] complex
-    double* d_fout = nullptr;
+    double* d_fout = nullptr;         // Fourier coefficients of forward FFTs [nf][L+1][nlat] complex
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
@@ -154,7 +172,7 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
 // analysis: the tendency from hU, hV, zU, zV, KE with the Runge-Kutta update
 // out = U0 + c0 N + c1 Nprev and, if Nsave, a copy of N).
 int sht_configure_kernels(swe_ctx* ctx);
-int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* four, int nf, hipStream_t stream);
+int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* part, int nf, hipStream_t stream);
 int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                          const double* Nprev, double* Nsave, double* out, double c0, double c1,
                          hipStream_t stream);

@@ -52,155 +52,193 @@ struct LegArgs {
     const double* __restrict__ mu;      // [half]
     const double* __restrict__ sint;    // [half]
     const double* __restrict__ w;       // [half]
-    const double* __restrict__ seed_m;  // [L+1][half]
-    const int* __restrict__ seed_e;     // [L+1][half]
-    int L, nlat, half, modes;
+    const int* __restrict__ seg_m;      // [nseg]
+    const int* __restrict__ seg_i0;     // [nseg]
+    const int* __restrict__ seg_n;      // [nseg]
+    const double* __restrict__ seed_pm; // [nseg][half]
+    const double* __restrict__ seed_p;  // [nseg][half]
+    const int* __restrict__ seed_e;     // [nseg][half]
+    int L, nlat, half, modes, nseg;
     double a;
 };
 
-// Recurrence state of one lane: Pbar_{l-1}, Pbar_l in units of 2^e.
+// Recurrence state of one latitude: Pbar_{l-1}, Pbar_l in units of 2^e.
 struct Rec {
     double pm, p;
     int e;
 };
 
-__device__ __forceinline__ Rec rec_start(const LegArgs& A, int m, int j) {
+__device__ __forceinline__ Rec rec_start(const LegArgs& A, int gs, int j) {
+    const size_t k = static_cast<size_t>(gs) * A.half + j;
     Rec r;
-    r.pm = 0.0;
-    r.p = A.seed_m[static_cast<size_t>(m) * A.half + j];
-    r.e = A.seed_e[static_cast<size_t>(m) * A.half + j];
+    r.pm = A.seed_pm[k];
+    r.p = A.seed_p[k];
+    r.e = A.seed_e[k];
     return r;
-}
-
-// Advances to degree l+1; returns Pbar_{l+1} and H_l (both in units of 2^e).
-__device__ __forceinline__ void rec_step(const LegCoef& c, double mu, Rec& r, double& pn, double& h) {
-    pn = __builtin_fma(c.A * mu, r.p, -(c.B * r.pm));
-    h = __builtin_fma(c.hA, pn, c.hB * r.pm);
 }
 
 constexpr double kBig = 0x1p400;
 
+// Renormalises a recurrence that has grown back into double range; returns the shift.
+__device__ __forceinline__ int rec_renorm(Rec& r) {
+    if (r.e < 0 && fabs(r.p) > kBig) {
+        const int sh = min(400, -r.e);
+        r.p = ldexp(r.p, -sh);
+        r.pm = ldexp(r.pm, -sh);
+        r.e += sh;
+        return sh;
+    }
+    return 0;
+}
+
 // ================================================== Legendre synthesis ==
+// One wave per (degree segment, latitude tile); each lane carries NJ northern
+// latitudes (independent recurrences: instruction-level parallelism).  Every
+// segment writes a partial Fourier coefficient; the ring kernel adds the
+// partials of an order in segment order.
 // KIND 0: one scalar field per block row (blockIdx.y = field), P pass only.
 // KIND 1: the non-linear set: h, zeta (P pass) and U, V from psi, chi
 //         (psi = -a^2 zeta / N, chi = -a^2 delta / N) -> 4 output fields.
 struct SynArgs {
     LegArgs g;
     const double2* __restrict__ spec;   // KIND 0: [nf][modes]; KIND 1: state [3][modes]
-    double2* __restrict__ four;         // [nfo][L+1][nlat]
+    double2* __restrict__ part;         // [nfo][nseg][nlat]
 };
 
-// Per-degree data of one order m staged in LDS (double2 slots per degree):
+// Per-degree data staged in LDS (double2 slots per degree):
 // KIND 0: {A, B}, coefficient;  KIND 1: {A, B}, {hA, hB}, h, zeta, delta, {a/N, m a/N}.
 template <int KIND>
 struct SynStage {
     static constexpr int SLOTS = KIND == 0 ? 2 : 6;
 };
 
-template <int KIND>
+template <int KIND, int NJ>
 __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
-    extern __shared__ __align__(16) double2 stg[];
+    __shared__ double2 stg[64 * SynStage<KIND>::SLOTS];
     constexpr int SL = SynStage<KIND>::SLOTS;
+    constexpr int NACC = KIND == 0 ? 1 : 4;
     const LegArgs& A = S.g;
-    const int m = blockIdx.x;
-    const int Lm = A.L - m + 1;
-    const int jt = blockIdx.z * WAVE + threadIdx.x;
-    const bool valid = jt < A.half;
-    const int j = valid ? jt : A.half - 1;
-    const double mu = A.mu[j];
+    const int gs = blockIdx.x;
+    const int m = A.seg_m[gs], i0 = A.seg_i0[gs], n = A.seg_n[gs];
     const int base = m * (2 * A.L + 3 - m) / 2;
     const double dm = static_cast<double>(m);
     {
         const double2* sp0 = S.spec + static_cast<size_t>(KIND == 0 ? blockIdx.y : 0) * A.modes + base;
-        for (int i = threadIdx.x; i < Lm; i += WAVE) {
+        for (int d = threadIdx.x; d < n; d += WAVE) {
+            const int i = i0 + d;
             const LegCoef c = A.rec[base + i];
-            stg[i * SL + 0] = make_double2(c.A, c.B);
+            stg[d * SL + 0] = make_double2(c.A, c.B);
             if constexpr (KIND == 0) {
-                stg[i * SL + 1] = sp0[i];
+                stg[d * SL + 1] = sp0[i];
             } else {
                 const double aon = A.aon[m + i];
-                stg[i * SL + 1] = make_double2(c.hA, c.hB);
-                stg[i * SL + 2] = sp0[i];
-                stg[i * SL + 3] = sp0[i + A.modes];
-                stg[i * SL + 4] = sp0[i + 2 * A.modes];
-                stg[i * SL + 5] = make_double2(aon, dm * aon);
+                stg[d * SL + 1] = make_double2(c.hA, c.hB);
+                stg[d * SL + 2] = sp0[i];
+                stg[d * SL + 3] = sp0[i + A.modes];
+                stg[d * SL + 4] = sp0[i + 2 * A.modes];
+                stg[d * SL + 5] = make_double2(aon, dm * aon);
             }
         }
+    }
+    double mu[NJ];
+    int jq[NJ];
+    Rec r[NJ];
+    double2 E[NJ][NACC], O[NJ][NACC];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        jq[q] = (blockIdx.z * NJ + q) * WAVE + threadIdx.x;
+        const int j = jq[q] < A.half ? jq[q] : A.half - 1;
+        mu[q] = A.mu[j];
+        r[q] = rec_start(A, gs, j);
+#pragma unroll
+        for (int f = 0; f < NACC; ++f) E[q][f] = O[q][f] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    constexpr int NACC = KIND == 0 ? 1 : 4;
-    double2 E[NACC], O[NACC];
-#pragma unroll
-    for (int f = 0; f < NACC; ++f) E[f] = O[f] = make_double2(0.0, 0.0);
-    Rec r = rec_start(A, m, j);
 
-    auto degree = [&](int i, auto odd) {
+    auto degree = [&](int d, auto odd) {
         constexpr bool ODD = decltype(odd)::value;
-        const double2* st = stg + i * SL;
+        const double2* st = stg + d * SL;
         const double2 ab = st[0];
-        const double pn = __builtin_fma(ab.x * mu, r.p, -(ab.y * r.pm));
-        const double p = r.p;
         if constexpr (KIND == 0) {
-            if (ODD) caxpy(O[0], st[1], p); else caxpy(E[0], st[1], p);
+            const double2 c = st[1];
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const double pn = __builtin_fma(ab.x * mu[q], r[q].p, -(ab.y * r[q].pm));
+                const double p = r[q].p;
+                if (ODD) caxpy(O[q][0], c, p); else caxpy(E[q][0], c, p);
+                r[q].pm = p;
+                r[q].p = pn;
+            }
         } else {
-            const double2 hab = st[1];
-            const double h = __builtin_fma(hab.x, pn, hab.y * r.pm);
-            const double2 ch = st[2], cz = st[3], cd = st[4], fac = st[5];
-            const double hp = fac.x * h;         // (a/N) H
-            const double pp = fac.y * p;         // (m a/N) Pbar
-            if (ODD) { caxpy(O[0], ch, p); caxpy(O[1], cz, p); }
-            else     { caxpy(E[0], ch, p); caxpy(E[1], cz, p); }
-            // U: i m chi Pbar / a = -i delta P'  (parity of P);  -psi H / a = zeta H'  (parity of H)
-            // V: i m psi Pbar / a = -i zeta P'   (parity of P);   chi H / a = -delta H' (parity of H)
-            const double2 up = make_double2(cd.y * pp, -cd.x * pp);
-            const double2 vp = make_double2(cz.y * pp, -cz.x * pp);
-            const double2 uh = make_double2(cz.x * hp, cz.y * hp);
-            const double2 vh = make_double2(-cd.x * hp, -cd.y * hp);
-            if (ODD) {
-                O[2] = cadd(O[2], up); E[2] = cadd(E[2], uh);
-                O[3] = cadd(O[3], vp); E[3] = cadd(E[3], vh);
-            } else {
-                E[2] = cadd(E[2], up); O[2] = cadd(O[2], uh);
-                E[3] = cadd(E[3], vp); O[3] = cadd(O[3], vh);
+            const double2 hab = st[1], ch = st[2], cz = st[3], cd = st[4], fac = st[5];
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const double pn = __builtin_fma(ab.x * mu[q], r[q].p, -(ab.y * r[q].pm));
+                const double p = r[q].p;
+                const double h = __builtin_fma(hab.x, pn, hab.y * r[q].pm);
+                const double hp = fac.x * h;         // (a/N) H
+                const double pp = fac.y * p;         // (m a/N) Pbar
+                double2* Pp = ODD ? O[q] : E[q];     // accumulators with the parity of Pbar
+                double2* Hp = ODD ? E[q] : O[q];     // accumulators with the parity of H
+                caxpy(Pp[0], ch, p);
+                caxpy(Pp[1], cz, p);
+                // U: i m chi Pbar / a = -i delta P' (P parity); -psi H / a = zeta H' (H parity)
+                Pp[2].x = __builtin_fma(cd.y, pp, Pp[2].x);
+                Pp[2].y = __builtin_fma(-cd.x, pp, Pp[2].y);
+                caxpy(Hp[2], cz, hp);
+                // V: i m psi Pbar / a = -i zeta P' (P parity); chi H / a = -delta H' (H parity)
+                Pp[3].x = __builtin_fma(cz.y, pp, Pp[3].x);
+                Pp[3].y = __builtin_fma(-cz.x, pp, Pp[3].y);
+                Hp[3].x = __builtin_fma(-cd.x, hp, Hp[3].x);
+                Hp[3].y = __builtin_fma(-cd.y, hp, Hp[3].y);
+                r[q].pm = p;
+                r[q].p = pn;
             }
         }
-        r.pm = r.p;
-        r.p = pn;
     };
 
-    int i = 0;
-    for (; i + 3 < Lm; i += 4) {
-        degree(i, std::integral_constant<bool, false>{});
-        degree(i + 1, std::integral_constant<bool, true>{});
-        degree(i + 2, std::integral_constant<bool, false>{});
-        degree(i + 3, std::integral_constant<bool, true>{});
-        if (r.e < 0 && fabs(r.p) > kBig) {
-            const int sh = min(400, -r.e);
-            r.p = ldexp(r.p, -sh);
-            r.pm = ldexp(r.pm, -sh);
-            r.e += sh;
+    // i0 is a multiple of the (even) segment length: the parity of l - m is that of d
+    int d = 0;
+    for (; d + 3 < n; d += 4) {
+        degree(d, std::integral_constant<bool, false>{});
+        degree(d + 1, std::integral_constant<bool, true>{});
+        degree(d + 2, std::integral_constant<bool, false>{});
+        degree(d + 3, std::integral_constant<bool, true>{});
 #pragma unroll
-            for (int f = 0; f < NACC; ++f) {
-                E[f] = make_double2(ldexp(E[f].x, -sh), ldexp(E[f].y, -sh));
-                O[f] = make_double2(ldexp(O[f].x, -sh), ldexp(O[f].y, -sh));
+        for (int q = 0; q < NJ; ++q) {
+            const int sh = rec_renorm(r[q]);
+            if (sh) {
+#pragma unroll
+                for (int f = 0; f < NACC; ++f) {
+                    E[q][f] = make_double2(ldexp(E[q][f].x, -sh), ldexp(E[q][f].y, -sh));
+                    O[q][f] = make_double2(ldexp(O[q][f].x, -sh), ldexp(O[q][f].y, -sh));
+                }
             }
         }
     }
-    for (; i < Lm; ++i) {
-        if ((i & 1) == 0) degree(i, std::integral_constant<bool, false>{});
-        else degree(i, std::integral_constant<bool, true>{});
+    for (; d < n; ++d) {
+        if ((d & 1) == 0) degree(d, std::integral_constant<bool, false>{});
+        else degree(d, std::integral_constant<bool, true>{});
     }
-    if (!valid) return;
-    for (int f = 0; f < NACC; ++f) {
-        const size_t row = (static_cast<size_t>(KIND == 0 ? blockIdx.y : f) * (A.L + 1) + m) * A.nlat;
-        const double2 n = make_double2(ldexp(E[f].x + O[f].x, r.e), ldexp(E[f].y + O[f].y, r.e));
-        const double2 s = make_double2(ldexp(E[f].x - O[f].x, r.e), ldexp(E[f].y - O[f].y, r.e));
-        S.four[row + jt] = n;
-        S.four[row + (A.nlat - 1 - jt)] = s;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        if (jq[q] >= A.half) continue;
+#pragma unroll
+        for (int f = 0; f < NACC; ++f) {
+            const size_t row = (static_cast<size_t>(KIND == 0 ? blockIdx.y : f) * A.nseg + gs) * A.nlat;
+            const double2 nn = make_double2(ldexp(E[q][f].x + O[q][f].x, r[q].e), ldexp(E[q][f].y + O[q][f].y, r[q].e));
+            const double2 ss = make_double2(ldexp(E[q][f].x - O[q][f].x, r[q].e), ldexp(E[q][f].y - O[q][f].y, r[q].e));
+            S.part[row + jq[q]] = nn;
+            S.part[row + (A.nlat - 1 - jq[q])] = ss;
+        }
     }
 }
 
 // ==================================================== Legendre analysis ==
+// One workgroup per degree segment; NW waves, each lane carries NJ northern
+// latitudes (latitude j = (q NW + wave) 64 + lane).  Per chunk of D degrees a
+// lane adds the contributions of its latitudes, the workgroup sums the lanes
+// through LDS (lane-major write, transposed read), and the sums are written.
 // KIND 0: one scalar field per block row: f_lm = sum_j w_j Pbar_lm F_m.
 // KIND 1: the non-linear tendency from the Fourier coefficients of
 //         hU, hV, zU, zV, KE (fields 0..4):
@@ -222,150 +260,159 @@ template <int KIND>
 struct AnaTraits {
     static constexpr int NC = KIND == 0 ? 2 : 6;       // doubles contributed per (l, j)
     static constexpr int NIN = KIND == 0 ? 1 : 5;      // complex input fields
+    static constexpr int D = KIND == 0 ? 16 : 8;       // degrees per reduction chunk
 };
 
-// Folded, weighted inputs of one lane (units of 2^e): for each field,
-// S = F(mu) + F(-mu) and D = F(mu) - F(-mu).
+// Folded, weighted inputs of one latitude (units of 2^e): for each field,
+// S = F(mu) + F(-mu) and D = F(mu) - F(-mu); zero for padding latitudes.
 template <int KIND>
-__device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, int e, double2* Sv, double2* Dv) {
+__device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, bool valid, int e, double2* Sv,
+                                            double2* Dv) {
     const LegArgs& A = P.g;
     constexpr int NIN = AnaTraits<KIND>::NIN;
-    const double sc = ldexp(1.0, e);
+    const double sc = valid ? ldexp(1.0, e) : 0.0;
     const double wj = A.w[j];
     const double wdiv = wj / (A.a * A.sint[j] * A.sint[j]);
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
         const int fld = KIND == 0 ? blockIdx.y : f;
         const size_t row = (static_cast<size_t>(fld) * (A.L + 1) + m) * A.nlat;
-        const double2 n = P.four[row + j];
-        const double2 s = P.four[row + (A.nlat - 1 - j)];
+        const double2 nn = P.four[row + j];
+        const double2 ss = P.four[row + (A.nlat - 1 - j)];
         const double wt = (KIND == 0 || f == 4) ? wj : wdiv;
-        Sv[f] = scale2(cadd(n, s), wt * sc);
-        Dv[f] = scale2(csub(n, s), wt * sc);
+        Sv[f] = scale2(cadd(nn, ss), wt * sc);
+        Dv[f] = scale2(csub(nn, ss), wt * sc);
     }
 }
 
-constexpr int RED_STRIDE = 72;   // doubles per staged output row (64 lanes + pad: 4-cycle LDS reads)
+constexpr int RED_STRIDE = 72;   // doubles per staged output row (64 lanes + pad)
 
-template <int KIND, int D>
-__global__ __launch_bounds__(512) void legendre_anal_kernel(AnaArgs P) {
-    extern __shared__ __align__(16) double smem[];
+template <int KIND, int NJ, int NW>
+__global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
     constexpr int NC = AnaTraits<KIND>::NC;
     constexpr int NIN = AnaTraits<KIND>::NIN;
+    constexpr int D = AnaTraits<KIND>::D;
     constexpr int NO = D * NC;                           // outputs per chunk
     constexpr int SL = KIND == 0 ? 1 : 3;                // staged double2 per degree
+    constexpr int T = NW * WAVE;
+    __shared__ double red[NW * NO * RED_STRIDE];
+    __shared__ double2 stg[64 * SL];
     const LegArgs& A = P.g;
-    const int m = blockIdx.x;
-    const int Lm = A.L - m + 1;
+    const int gs = blockIdx.x;
+    const int m = A.seg_m[gs], i0 = A.seg_i0[gs], n = A.seg_n[gs];
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1), wv = tid / WAVE;
-    const int nthreads = blockDim.x;
-    const int nw = nthreads / WAVE;
-    const bool valid = tid < A.half;
-    const int j = valid ? tid : A.half - 1;
-    const double mu = A.mu[j];
     const int base = m * (2 * A.L + 3 - m) / 2;
-    double* red = smem;                                                   // [nw][NO][RED_STRIDE]
-    double2* stg = reinterpret_cast<double2*>(smem + static_cast<size_t>(nw) * NO * RED_STRIDE);
-    for (int i = tid; i < Lm; i += nthreads) {
-        const LegCoef c = A.rec[base + i];
-        stg[i * SL] = make_double2(c.A, c.B);
+    for (int d = tid; d < n; d += T) {
+        const LegCoef c = A.rec[base + i0 + d];
+        stg[d * SL] = make_double2(c.A, c.B);
         if constexpr (KIND == 1) {
-            stg[i * SL + 1] = make_double2(c.hA, c.hB);
-            stg[i * SL + 2] = make_double2(A.noa2[m + i], 0.0);
+            stg[d * SL + 1] = make_double2(c.hA, c.hB);
+            stg[d * SL + 2] = make_double2(A.noa2[m + i0 + d], 0.0);
         }
     }
-    Rec r = rec_start(A, m, j);
-    double2 Sv[NIN], Dv[NIN];
-    load_folded<KIND>(P, m, j, r.e, Sv, Dv);
-    if (!valid) {
+    double mu[NJ];
+    int jq[NJ];
+    Rec r[NJ];
+    double2 Sv[NJ][NIN], Dv[NJ][NIN];
 #pragma unroll
-        for (int f = 0; f < NIN; ++f) Sv[f] = Dv[f] = make_double2(0.0, 0.0);
+    for (int q = 0; q < NJ; ++q) {
+        jq[q] = (q * NW + wv) * WAVE + lane;
+        const bool valid = jq[q] < A.half;
+        const int j = valid ? jq[q] : A.half - 1;
+        mu[q] = A.mu[j];
+        r[q] = rec_start(A, gs, j);
+        load_folded<KIND>(P, m, j, valid, r[q].e, Sv[q], Dv[q]);
     }
     const double dm = static_cast<double>(m);
     // reduction: thread t -> output o = t / G, part g = t % G
-    int G = 1;
-    while (G * 2 * NO <= nthreads && G < 16) G *= 2;
+    constexpr int G = (T >= 8 * NO) ? 8 : (T >= 4 * NO) ? 4 : (T >= 2 * NO) ? 2 : 1;
+    constexpr int NV = T / G;                            // values summed by one thread
     const int o_red = tid / G, g_red = tid % G;
-    const int nvals = nthreads;                          // values per output
-    double* myred = red + static_cast<size_t>(wv) * NO * RED_STRIDE;
+    double* myred = red + wv * NO * RED_STRIDE;
     __syncthreads();
 
-    for (int i0 = 0; i0 < Lm; i0 += D) {
+    for (int c0 = 0; c0 < n; c0 += D) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int i = i0 + d;
+        for (int dd = 0; dd < D; ++dd) {
+            const int d = c0 + dd;
             double c[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) c[k] = 0.0;
-            if (i < Lm) {
-                const double2* st = stg + i * SL;
+            if (d < n) {
+                const double2* st = stg + d * SL;
                 const double2 ab = st[0];
-                const double pn = __builtin_fma(ab.x * mu, r.p, -(ab.y * r.pm));
-                const double p = r.p;
-                const bool odd = d & 1;                  // l - m = i0 + d with i0 a multiple of D
-                if constexpr (KIND == 0) {
-                    const double2 x = odd ? Dv[0] : Sv[0];
-                    c[0] = x.x * p;
-                    c[1] = x.y * p;
-                } else {
-                    const double2 hab = st[1];
-                    const double h = __builtin_fma(hab.x, pn, hab.y * r.pm);
-                    // P terms take the fold of P's parity, H terms the opposite one
-                    const double2 hU = odd ? Dv[0] : Sv[0], zU = odd ? Dv[2] : Sv[2];
-                    const double2 zV = odd ? Dv[3] : Sv[3], ke = odd ? Dv[4] : Sv[4];
-                    const double2 hVh = odd ? Sv[1] : Dv[1], zVh = odd ? Sv[3] : Dv[3];
-                    const double2 zUh = odd ? Sv[2] : Dv[2];
-                    const double pm2 = dm * p;                 // m Pbar
-                    const double pk = st[2].x * p;             // l(l+1)/a^2 Pbar
-                    // N_h = -(i m hU P - hV H)
-                    c[0] = __builtin_fma(hU.y, pm2, hVh.x * h);
-                    c[1] = __builtin_fma(-hU.x, pm2, hVh.y * h);
-                    // N_zeta = -(i m zU P - zV H)
-                    c[2] = __builtin_fma(zU.y, pm2, zVh.x * h);
-                    c[3] = __builtin_fma(-zU.x, pm2, zVh.y * h);
-                    // N_delta = i m zV P + zU H + l(l+1)/a^2 KE P
-                    c[4] = __builtin_fma(-zV.y, pm2, __builtin_fma(zUh.x, h, ke.x * pk));
-                    c[5] = __builtin_fma(zV.x, pm2, __builtin_fma(zUh.y, h, ke.y * pk));
+                const bool odd = dd & 1;                 // l - m = i0 + c0 + dd, i0 and c0 even
+#pragma unroll
+                for (int q = 0; q < NJ; ++q) {
+                    const double pn = __builtin_fma(ab.x * mu[q], r[q].p, -(ab.y * r[q].pm));
+                    const double p = r[q].p;
+                    if constexpr (KIND == 0) {
+                        const double2 x = odd ? Dv[q][0] : Sv[q][0];
+                        c[0] = __builtin_fma(x.x, p, c[0]);
+                        c[1] = __builtin_fma(x.y, p, c[1]);
+                    } else {
+                        const double2 hab = st[1];
+                        const double h = __builtin_fma(hab.x, pn, hab.y * r[q].pm);
+                        // P terms take the fold of P's parity, H terms the opposite one
+                        const double2 hU = odd ? Dv[q][0] : Sv[q][0], zU = odd ? Dv[q][2] : Sv[q][2];
+                        const double2 zV = odd ? Dv[q][3] : Sv[q][3], ke = odd ? Dv[q][4] : Sv[q][4];
+                        const double2 hVh = odd ? Sv[q][1] : Dv[q][1], zVh = odd ? Sv[q][3] : Dv[q][3];
+                        const double2 zUh = odd ? Sv[q][2] : Dv[q][2];
+                        const double pm2 = dm * p;               // m Pbar
+                        const double pk = st[2].x * p;           // l(l+1)/a^2 Pbar
+                        // N_h = -(i m hU P - hV H)
+                        c[0] = __builtin_fma(hU.y, pm2, __builtin_fma(hVh.x, h, c[0]));
+                        c[1] = __builtin_fma(-hU.x, pm2, __builtin_fma(hVh.y, h, c[1]));
+                        // N_zeta = -(i m zU P - zV H)
+                        c[2] = __builtin_fma(zU.y, pm2, __builtin_fma(zVh.x, h, c[2]));
+                        c[3] = __builtin_fma(-zU.x, pm2, __builtin_fma(zVh.y, h, c[3]));
+                        // N_delta = i m zV P + zU H + l(l+1)/a^2 KE P
+                        c[4] = __builtin_fma(-zV.y, pm2, __builtin_fma(zUh.x, h, __builtin_fma(ke.x, pk, c[4])));
+                        c[5] = __builtin_fma(zV.x, pm2, __builtin_fma(zUh.y, h, __builtin_fma(ke.y, pk, c[5])));
+                    }
+                    r[q].pm = p;
+                    r[q].p = pn;
                 }
-                r.pm = r.p;
-                r.p = pn;
             }
 #pragma unroll
-            for (int k = 0; k < NC; ++k) myred[(d * NC + k) * RED_STRIDE + lane] = c[k];
+            for (int k = 0; k < NC; ++k) myred[(dd * NC + k) * RED_STRIDE + lane] = c[k];
         }
-        // renormalise lanes whose recurrence has grown back into range
-        if (r.e < 0 && fabs(r.p) > kBig) {
-            const int sh = min(400, -r.e);
-            r.p = ldexp(r.p, -sh);
-            r.pm = ldexp(r.pm, -sh);
-            r.e += sh;
-            load_folded<KIND>(P, m, j, r.e, Sv, Dv);
-            if (!valid) {
+        // renormalise latitudes whose recurrence has grown back into range
 #pragma unroll
-                for (int f = 0; f < NIN; ++f) Sv[f] = Dv[f] = make_double2(0.0, 0.0);
+        for (int q = 0; q < NJ; ++q) {
+            if (rec_renorm(r[q])) {
+                const bool valid = jq[q] < A.half;
+                load_folded<KIND>(P, m, valid ? jq[q] : A.half - 1, valid, r[q].e, Sv[q], Dv[q]);
             }
         }
         __syncthreads();
         if (o_red < NO) {
-            double s = 0.0;
-            for (int v = g_red; v < nvals; v += G) {
-                const int w2 = v / WAVE, ln = v % WAVE;
-                s += red[(static_cast<size_t>(w2) * NO + o_red) * RED_STRIDE + ln];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; v += 4) {
+#define RED_AT(vv) red[(((g_red + (vv) * G) / WAVE) * NO + o_red) * RED_STRIDE + ((g_red + (vv) * G) % WAVE)]
+                s0 += RED_AT(v);
+                if (v + 1 < NV) s1 += RED_AT(v + 1);
+                if (v + 2 < NV) s2 += RED_AT(v + 2);
+                if (v + 3 < NV) s3 += RED_AT(v + 3);
+#undef RED_AT
             }
+            double s = (s0 + s1) + (s2 + s3);
+#pragma unroll
             for (int msk = 1; msk < G; msk <<= 1) s += __shfl_xor(s, msk, G);
-            const int d = o_red / NC, k = o_red % NC;
-            const int i = i0 + d;
-            if (g_red == 0 && i < Lm) {
-                const size_t idx = static_cast<size_t>(base) + i;
+            const int dd = o_red / NC, k = o_red % NC;
+            const int d = c0 + dd;
+            if (g_red == 0 && d < n) {
+                const size_t idx = static_cast<size_t>(base) + i0 + d;
                 if constexpr (KIND == 0) {
                     double* dst = reinterpret_cast<double*>(P.spec + static_cast<size_t>(blockIdx.y) * A.modes + idx);
                     dst[k] = s;
                 } else {
                     const int f = k >> 1, part = k & 1;
                     const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-                    double v = reinterpret_cast<const double*>(P.U0)[e2] + P.c0 * s;
-                    if (P.Nprev) v += P.c1 * reinterpret_cast<const double*>(P.Nprev)[e2];
+                    double v = __builtin_fma(P.c0, s, reinterpret_cast<const double*>(P.U0)[e2]);
+                    if (P.Nprev) v = __builtin_fma(P.c1, reinterpret_cast<const double*>(P.Nprev)[e2], v);
                     if (P.Nsave) reinterpret_cast<double*>(P.Nsave)[e2] = s;
                     reinterpret_cast<double*>(P.out)[e2] = v;
                 }
@@ -382,7 +429,9 @@ struct RingArgs {
     const double* __restrict__ sint;   // [half]
     const int* __restrict__ radix;     // [npass]
     int npass, L, nlat, nlon, half;
-    const double2* __restrict__ fin;   // [nf_in][L+1][nlat]
+    const double2* __restrict__ fin;   // synthesis partials [nf_in][nseg][nlat]
+    const int* __restrict__ segbase;   // [L+2] first segment of each order
+    int nseg;
     double2* __restrict__ fout;        // [nf_out][L+1][nlat]
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
@@ -457,16 +506,25 @@ __device__ double2* fft_lds(double2* a, double2* scratch, const RingArgs& A, boo
     return src;
 }
 
-// Loads F_m (m <= L) of one latitude and builds the half-length spectrum Z of
-// the inverse real FFT:  Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/nlon} (X_k - conj X_{M-k}),
+// Sum of the synthesis partials of order k at one latitude.
+__device__ __forceinline__ double2 fourier_coeff(const double2* fin_col, int k, const RingArgs& A) {
+    double2 acc = make_double2(0.0, 0.0);
+    const int s1 = A.segbase[k + 1];
+    for (int g = A.segbase[k]; g < s1; ++g) acc = cadd(acc, fin_col[static_cast<size_t>(g) * A.nlat]);
+    return acc;
+}
+
+// Loads F_m (m <= L) of one latitude (adding the segment partials) and builds
+// the half-length spectrum Z of the inverse real FFT:
+//   Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/nlon} (X_k - conj X_{M-k}),
 // X_0 taken real, X_k = 0 for k > L.
-__device__ void load_inverse(const double2* fin_row, int nlat_stride, double2* z, const RingArgs& A) {
+__device__ void load_inverse(const double2* fin_col, double2* z, const RingArgs& A) {
     const int M = A.nlon / 2;
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double2 xk = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
-        if (k <= A.L) xk = fin_row[static_cast<size_t>(k) * nlat_stride];
+        if (k <= A.L) xk = fourier_coeff(fin_col, k, A);
         const int kr = M - k;                      // 1..M
-        if (kr <= A.L && kr < M) xr = fin_row[static_cast<size_t>(kr) * nlat_stride];
+        if (kr <= A.L && kr < M) xr = fourier_coeff(fin_col, kr, A);
         if (k == 0) xk.y = 0.0;
         const double2 xrc = conj2(xr);
         const double2 s = cadd(xk, xrc);
@@ -503,12 +561,13 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
     extern __shared__ __align__(16) double2 lds[];
     const int M = A.nlon / 2;
     const int j = blockIdx.x;
-    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;
+    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // forward outputs
+    const size_t pstride = static_cast<size_t>(A.nseg) * A.nlat;    // synthesis partials
     double2* scratch = lds;
     if constexpr (MODE == 0) {
         double2* a = lds + M;
         for (int f = 0; f < A.nf; ++f) {
-            load_inverse(A.fin + f * fstride + j, A.nlat, a, A);
+            load_inverse(A.fin + f * pstride + j, a, A);
             __syncthreads();
             double2* res = fft_lds(a, scratch, A, true);
             double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
@@ -532,7 +591,7 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
         for (int i = 0; i < 6; ++i) arr[i] = lds + (i + 1) * M;
         double2* grid[4];
         for (int f = 0; f < 4; ++f) {
-            load_inverse(A.fin + f * fstride + j, A.nlat, arr[f], A);
+            load_inverse(A.fin + f * pstride + j, arr[f], A);
             __syncthreads();
             double2* res = fft_lds(arr[f], scratch, A, true);
             if (res != arr[f]) {
@@ -581,8 +640,13 @@ static LegArgs leg_args(const swe_ctx* ctx) {
     g.mu = ctx->d_mu;
     g.sint = ctx->d_sint;
     g.w = ctx->d_w;
-    g.seed_m = ctx->d_seed_m;
+    g.seg_m = ctx->d_seg_m;
+    g.seg_i0 = ctx->d_seg_i0;
+    g.seg_n = ctx->d_seg_n;
+    g.seed_pm = ctx->d_seed_pm;
+    g.seed_p = ctx->d_seed_p;
     g.seed_e = ctx->d_seed_e;
+    g.nseg = ctx->nseg;
     g.L = ctx->L;
     g.nlat = ctx->nlat;
     g.half = ctx->nlat / 2;
@@ -597,21 +661,14 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     r.twr = ctx->d_twr;
     r.sint = ctx->d_sint;
     r.radix = ctx->d_radix;
+    r.segbase = ctx->d_segbase;
+    r.nseg = ctx->nseg;
     r.npass = ctx->npass;
     r.L = ctx->L;
     r.nlat = ctx->nlat;
     r.nlon = ctx->nlon;
     r.half = ctx->nlat / 2;
     return r;
-}
-
-// LDS of the analysis kernel: staged reduction rows + staged per-degree coefficients.
-static size_t anal_lds_bytes(const swe_ctx* ctx, int kind) {
-    const int nw = (ctx->nlat / 2 + WAVE - 1) / WAVE;
-    const int D = kind == 0 ? 8 : (nw <= 3 ? 4 : 2);
-    const int NC = kind == 0 ? AnaTraits<0>::NC : AnaTraits<1>::NC;
-    const int SL = kind == 0 ? 1 : 3;
-    return sizeof(double) * nw * D * NC * RED_STRIDE + sizeof(double2) * SL * (ctx->L + 1);
 }
 
 static int ring_lds_bytes(const swe_ctx* ctx, int mode) {
@@ -634,32 +691,48 @@ int sht_configure_kernels(swe_ctx* ctx) {
     if ((rc = allow_lds(reinterpret_cast<const void*>(&ring_kernel<2>), ring_lds_bytes(ctx, 2),
                         "the longitude FFT")) != REXI_OK)
         return rc;
-    if ((rc = allow_lds(reinterpret_cast<const void*>(&legendre_anal_kernel<1, 2>), anal_lds_bytes(ctx, 1),
-                        "the Legendre analysis")) != REXI_OK)
-        return rc;
-    if ((rc = allow_lds(reinterpret_cast<const void*>(&legendre_anal_kernel<1, 4>), anal_lds_bytes(ctx, 1),
-                        "the Legendre analysis")) != REXI_OK)
-        return rc;
     return REXI_OK;
 }
 
-int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* four, int nf, hipStream_t stream) {
+// Latitudes per lane for the Legendre stages: enough to cover the hemisphere
+// with one (synthesis) or at most two (analysis) waves, up to three.
+static int lat_per_lane(const swe_ctx* ctx) {
+    const int half = ctx->nlat / 2;
+    return half <= WAVE ? 1 : (half <= 2 * WAVE ? 2 : 3);
+}
+
+int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* part, int nf, hipStream_t stream) {
     SynArgs S;
     S.g = leg_args(ctx);
     S.spec = reinterpret_cast<const double2*>(spec);
-    S.four = reinterpret_cast<double2*>(four);
-    const int tiles = (ctx->nlat / 2 + WAVE - 1) / WAVE;
+    S.part = reinterpret_cast<double2*>(part);
+    const int NJ = lat_per_lane(ctx);
+    const int tiles = (ctx->nlat / 2 + NJ * WAVE - 1) / (NJ * WAVE);
+    const dim3 grid(ctx->nseg, kind == 0 ? nf : 1, tiles);
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_SYNTH, stream);
     if (kind == 0) {
-        const size_t lds = sizeof(double2) * SynStage<0>::SLOTS * (ctx->L + 1);
-        hipLaunchKernelGGL(legendre_synth_kernel<0>, dim3(ctx->L + 1, nf, tiles), dim3(WAVE), lds, stream, S);
+        if (NJ == 1) hipLaunchKernelGGL((legendre_synth_kernel<0, 1>), grid, dim3(WAVE), 0, stream, S);
+        else if (NJ == 2) hipLaunchKernelGGL((legendre_synth_kernel<0, 2>), grid, dim3(WAVE), 0, stream, S);
+        else hipLaunchKernelGGL((legendre_synth_kernel<0, 3>), grid, dim3(WAVE), 0, stream, S);
     } else {
-        const size_t lds = sizeof(double2) * SynStage<1>::SLOTS * (ctx->L + 1);
-        hipLaunchKernelGGL(legendre_synth_kernel<1>, dim3(ctx->L + 1, 1, tiles), dim3(WAVE), lds, stream, S);
+        if (NJ == 1) hipLaunchKernelGGL((legendre_synth_kernel<1, 1>), grid, dim3(WAVE), 0, stream, S);
+        else if (NJ == 2) hipLaunchKernelGGL((legendre_synth_kernel<1, 2>), grid, dim3(WAVE), 0, stream, S);
+        else hipLaunchKernelGGL((legendre_synth_kernel<1, 3>), grid, dim3(WAVE), 0, stream, S);
     }
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_SYNTH, slot, stream);
     return REXI_OK;
+}
+
+template <int KIND>
+static void launch_anal_shape(int NJ, int NW, dim3 grid, const AnaArgs& P, hipStream_t stream) {
+    if (NW == 1) {
+        if (NJ == 1) hipLaunchKernelGGL((legendre_anal_kernel<KIND, 1, 1>), grid, dim3(WAVE), 0, stream, P);
+        else if (NJ == 2) hipLaunchKernelGGL((legendre_anal_kernel<KIND, 2, 1>), grid, dim3(WAVE), 0, stream, P);
+        else hipLaunchKernelGGL((legendre_anal_kernel<KIND, 3, 1>), grid, dim3(WAVE), 0, stream, P);
+    } else {
+        hipLaunchKernelGGL((legendre_anal_kernel<KIND, 3, 2>), grid, dim3(2 * WAVE), 0, stream, P);
+    }
 }
 
 int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
@@ -676,20 +749,13 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
     P.c0 = c0;
     P.c1 = c1;
     const int half = ctx->nlat / 2;
-    const int nw = (half + WAVE - 1) / WAVE;
-    const int threads = nw * WAVE;
-    if (threads > 512) return fail(REXI_ENOTSUP, "Legendre analysis: more than 512 northern latitudes");
+    const int NJ = lat_per_lane(ctx);
+    const int NW = (half + NJ * WAVE - 1) / (NJ * WAVE);
+    if (NW > 2) return fail(REXI_ENOTSUP, "Legendre analysis: more than 384 northern latitudes");
+    const dim3 grid(ctx->nseg, kind == 0 ? nf : 1);
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
-    if (kind == 0) {
-        const size_t lds = anal_lds_bytes(ctx, 0);
-        hipLaunchKernelGGL((legendre_anal_kernel<0, 8>), dim3(ctx->L + 1, nf), dim3(threads), lds, stream, P);
-    } else if (nw <= 3) {
-        const size_t lds = anal_lds_bytes(ctx, 1);
-        hipLaunchKernelGGL((legendre_anal_kernel<1, 4>), dim3(ctx->L + 1, 1), dim3(threads), lds, stream, P);
-    } else {
-        const size_t lds = anal_lds_bytes(ctx, 1);
-        hipLaunchKernelGGL((legendre_anal_kernel<1, 2>), dim3(ctx->L + 1, 1), dim3(threads), lds, stream, P);
-    }
+    if (kind == 0) launch_anal_shape<0>(NJ, NW, grid, P, stream);
+    else launch_anal_shape<1>(NJ, NW, grid, P, stream);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
     return REXI_OK;

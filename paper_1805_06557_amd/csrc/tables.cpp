@@ -2,6 +2,7 @@
 // Gauss-Legendre nodes and weights, the three-term recurrence coefficients of
 // the normalised associated Legendre functions, their seeds Pbar_mm(mu_j) split
 // into mantissa and base-2 exponent, and the FFT twiddle factors.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -73,6 +74,8 @@ void build_legendre_tables(int L, int nlat, double a, ShtHost& out) {
     out.mu.resize(half);
     out.sint.resize(half);
     out.w.resize(half);
+    out.mu_ld = mu;
+    out.sint_ld = sint;
     for (int j = 0; j < half; ++j) {
         out.mu[j] = static_cast<double>(mu[j]);
         out.sint[j] = static_cast<double>(sint[j]);
@@ -101,23 +104,59 @@ void build_legendre_tables(int L, int nlat, double a, ShtHost& out) {
         out.a_over_n[l] = static_cast<double>(static_cast<long double>(a) / N);
         out.n_over_a2[l] = static_cast<double>(N / (static_cast<long double>(a) * a));
     }
-    // seeds Pbar_mm(mu_j) = c_m sin(theta_j)^m, c_0 = 1/sqrt(2), c_m = c_{m-1} sqrt((2m+1)/(2m)),
-    // stored as mantissa * 2^exponent with exponent <= 0 only when the value is below 2^-960
-    out.seed_m.assign(static_cast<size_t>(L + 1) * half, 0.0);
-    out.seed_e.assign(static_cast<size_t>(L + 1) * half, 0);
+}
+
+void build_segments(int L, int seg_len, const ShtHost& sh, SegHost& out) {
+    const int half = sh.half;
+    out.seg_len = seg_len;
+    out.segbase.assign(L + 2, 0);
+    out.seg_m.clear();
+    out.seg_i0.clear();
+    out.seg_n.clear();
+    for (int m = 0; m <= L; ++m) {
+        out.segbase[m] = static_cast<int>(out.seg_m.size());
+        const int Lm = L - m + 1;
+        for (int i0 = 0; i0 < Lm; i0 += seg_len) {
+            out.seg_m.push_back(m);
+            out.seg_i0.push_back(i0);
+            out.seg_n.push_back(std::min(seg_len, Lm - i0));
+        }
+    }
+    out.nseg = static_cast<int>(out.seg_m.size());
+    out.segbase[L + 1] = out.nseg;
+    out.seed_pm.assign(static_cast<size_t>(out.nseg) * half, 0.0);
+    out.seed_p.assign(static_cast<size_t>(out.nseg) * half, 0.0);
+    out.seed_e.assign(static_cast<size_t>(out.nseg) * half, 0);
+    // 80-bit recurrence from Pbar_mm = c_m sin^m (representable in long double even
+    // where it underflows double), recording (Pbar_{k0-1}, Pbar_{k0}) at each segment start
     long double log2c = -0.5L;
     for (int m = 0; m <= L; ++m) {
         if (m > 0) log2c += 0.5L * std::log2((2.0L * m + 1.0L) / (2.0L * m));
+        const int Lm = L - m + 1;
+        std::vector<long double> A(Lm), B(Lm);
+        for (int i = 0; i < Lm; ++i) {
+            const int l = m + i;
+            const long double e1 = eps_lm(l + 1, m), e0 = eps_lm(l, m);
+            A[i] = 1.0L / e1;
+            B[i] = e0 / e1;
+        }
         for (int j = 0; j < half; ++j) {
-            const long double lg = log2c + m * std::log2(sint[j]);
-            const size_t i = static_cast<size_t>(m) * half + j;
-            if (lg >= -960.0L) {
-                out.seed_m[i] = static_cast<double>(std::exp2(lg));
-                out.seed_e[i] = 0;
-            } else {
-                const long double e = std::floor(lg) + 1.0L;
-                out.seed_m[i] = static_cast<double>(std::exp2(lg - e));
-                out.seed_e[i] = static_cast<int>(e);
+            const long double mu = sh.mu_ld[j];
+            long double pm = 0.0L;
+            long double p = std::exp2(log2c + m * std::log2(sh.sint_ld[j]));
+            for (int i = 0; i < Lm; ++i) {
+                if (i % seg_len == 0) {
+                    const size_t k = static_cast<size_t>(out.segbase[m] + i / seg_len) * half + j;
+                    const long double big = std::max(std::fabs(pm), std::fabs(p));
+                    int e = 0;
+                    if (big > 0.0L && big < 0x1p-960L) e = std::ilogb(big) + 1;
+                    out.seed_pm[k] = static_cast<double>(std::ldexp(pm, -e));
+                    out.seed_p[k] = static_cast<double>(std::ldexp(p, -e));
+                    out.seed_e[k] = e;
+                }
+                const long double pn = A[i] * mu * p - B[i] * pm;
+                pm = p;
+                p = pn;
             }
         }
     }
