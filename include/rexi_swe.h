@@ -180,7 +180,8 @@ enum {
     REXI_KERNEL_LEG_SYNTH = 2,   /* Legendre synthesis (spectral -> Fourier) */
     REXI_KERNEL_RING = 3,        /* longitude FFTs and pointwise products */
     REXI_KERNEL_LEG_ANAL = 4,    /* Legendre analysis (Fourier -> spectral) */
-    REXI_KERNEL_COUNT = 5
+    REXI_KERNEL_GATHER = 5,      /* sum of segment partials + transpose */
+    REXI_KERNEL_COUNT = 6
 };
 int swe_profile(swe_ctx* ctx, int enable);
 int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches);

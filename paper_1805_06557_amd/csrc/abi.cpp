@@ -159,12 +159,14 @@ int setup_sht(swe_ctx* ctx) {
 int reserve_fourier(swe_ctx* ctx, int nf) {
     if (static_cast<size_t>(nf) <= ctx->four_cap) return REXI_OK;
     if (ctx->d_part) REXI_HIP(hipFree(ctx->d_part));
+    if (ctx->d_fin) REXI_HIP(hipFree(ctx->d_fin));
     if (ctx->d_fout) REXI_HIP(hipFree(ctx->d_fout));
-    ctx->d_part = ctx->d_fout = nullptr;
+    ctx->d_part = ctx->d_fin = ctx->d_fout = nullptr;
     ctx->four_cap = 0;
     const size_t pbytes = sizeof(double) * 2 * static_cast<size_t>(nf) * ctx->nseg * ctx->nlat;
     const size_t fbytes = sizeof(double) * 2 * static_cast<size_t>(nf) * (ctx->L + 1) * ctx->nlat;
-    if (hipMalloc(&ctx->d_part, pbytes) != hipSuccess || hipMalloc(&ctx->d_fout, fbytes) != hipSuccess)
+    if (hipMalloc(&ctx->d_part, pbytes) != hipSuccess || hipMalloc(&ctx->d_fin, fbytes) != hipSuccess ||
+        hipMalloc(&ctx->d_fout, fbytes) != hipSuccess)
         return fail(REXI_ENOMEM, "cannot allocate Fourier workspace");
     ctx->four_cap = static_cast<size_t>(nf);
     return REXI_OK;
@@ -176,13 +178,15 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
     if ((rc = launch_legendre_synth(ctx, 1, U0, ctx->d_part, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_part, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, 4, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
     if ((rc = launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0,
                                    stream)) != REXI_OK)
         return rc;
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
     if ((rc = launch_legendre_synth(ctx, 1, ctx->d_ustar, ctx->d_part, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_part, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, 4, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
     return launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau,
                                 stream);
 }
@@ -284,7 +288,7 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_coef) (void)hipFree(ctx->d_coef);
     if (ctx->d_poles) (void)hipFree(ctx->d_poles);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
-    void* sht_bufs[] = {ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
+    void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB};
@@ -338,7 +342,8 @@ int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStre
     int rc;
     if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
     if ((rc = launch_legendre_synth(ctx, 0, spec, ctx->d_part, nf, stream)) != REXI_OK) return rc;
-    return launch_ring(ctx, 0, ctx->d_part, nullptr, nullptr, grid, nf, stream);
+    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, nf, stream)) != REXI_OK) return rc;
+    return launch_ring(ctx, 0, ctx->d_fin, nullptr, nullptr, grid, nf, stream);
 }
 
 int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStream_t stream) {

@@ -153,7 +153,8 @@ struct swe_ctx {
     double* d_twr = nullptr;          // [nlon/2] complex
     int* d_radix = nullptr;
     int npass = 0;
-    double* d_fout = nullptr;         // Fourier coefficients of forward FFTs [nf][L+1][nlat] complex
+    double* d_fin = nullptr;          // Fourier coefficients for the inverse FFTs [nf][nlat][L+1] complex
+    double* d_fout = nullptr;         // Fourier coefficients of the forward FFTs [nf][nlat][L+1] complex
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
@@ -176,6 +177,8 @@ int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* pa
 int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                          const double* Nprev, double* Nsave, double* out, double c0, double c1,
                          hipStream_t stream);
+// Sums segment partials and transposes them to [nf][nlat][L+1].
+int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
                 hipStream_t stream);

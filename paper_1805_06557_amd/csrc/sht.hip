@@ -246,7 +246,7 @@ __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
 //   followed by the Runge-Kutta update out = U0 + c0 N (+ c1 Nprev), and Nsave = N.
 struct AnaArgs {
     LegArgs g;
-    const double2* __restrict__ four;   // [nf][L+1][nlat]
+    const double2* __restrict__ four;   // [nf][nlat][L+1]
     double2* __restrict__ spec;         // KIND 0: [nf][modes]
     // KIND 1 epilogue
     const double2* __restrict__ U0;     // [3][modes]
@@ -276,9 +276,9 @@ __device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, bool
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
         const int fld = KIND == 0 ? blockIdx.y : f;
-        const size_t row = (static_cast<size_t>(fld) * (A.L + 1) + m) * A.nlat;
-        const double2 nn = P.four[row + j];
-        const double2 ss = P.four[row + (A.nlat - 1 - j)];
+        const size_t fb = static_cast<size_t>(fld) * A.nlat;
+        const double2 nn = P.four[(fb + j) * (A.L + 1) + m];
+        const double2 ss = P.four[(fb + A.nlat - 1 - j) * (A.L + 1) + m];
         const double wt = (KIND == 0 || f == 4) ? wj : wdiv;
         Sv[f] = scale2(cadd(nn, ss), wt * sc);
         Dv[f] = scale2(csub(nn, ss), wt * sc);
@@ -429,27 +429,31 @@ struct RingArgs {
     const double* __restrict__ sint;   // [half]
     const int* __restrict__ radix;     // [npass]
     int npass, L, nlat, nlon, half;
-    const double2* __restrict__ fin;   // synthesis partials [nf_in][nseg][nlat]
-    const int* __restrict__ segbase;   // [L+2] first segment of each order
-    int nseg;
-    double2* __restrict__ fout;        // [nf_out][L+1][nlat]
+    const double2* __restrict__ fin;   // Fourier coefficients [nf_in][nlat][L+1]
+    double2* __restrict__ fout;        // Fourier coefficients [nf_out][nlat][L+1]
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
     int nf;
 };
 
-// One Stockham pass of radix R over M complex points: src -> dst.
+// One Stockham pass of radix R over M complex points, for narr arrays at once
+// (one barrier per pass for all of them): src[a] -> dst[a].
 template <int R>
-__device__ __forceinline__ void fft_pass(const double2* src, double2* dst, int M, int Ns, const double* tw,
-                                         bool inverse) {
+__device__ __forceinline__ void fft_pass(double2* const* src, double2* const* dst, int narr, int M, int Ns,
+                                         const double* tw, bool inverse) {
     const int nb = M / R;
     const int twstep = M / (Ns * R);
-    for (int jb = threadIdx.x; jb < nb; jb += blockDim.x) {
+    const int total = nb * narr;
+    for (int x = threadIdx.x; x < total; x += blockDim.x) {
+        const int a = x / nb;
+        const int jb = x - a * nb;
+        const double2* sa = src[a];
+        double2* da = dst[a];
         const int k = jb % Ns;
         double2 v[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            v[t] = src[jb + t * nb];
+            v[t] = sa[jb + t * nb];
             if (t > 0) {
                 const int ti = (t * k * twstep) % M;
                 double2 wv = make_double2(tw[2 * ti], tw[2 * ti + 1]);
@@ -458,9 +462,9 @@ __device__ __forceinline__ void fft_pass(const double2* src, double2* dst, int M
             }
         }
         if constexpr (R == 2) {
-            const double2 a = v[0], b = v[1];
-            v[0] = cadd(a, b);
-            v[1] = csub(a, b);
+            const double2 a0 = v[0], b0 = v[1];
+            v[0] = cadd(a0, b0);
+            v[1] = csub(a0, b0);
         } else if constexpr (R == 4) {
             const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
             const double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
@@ -482,49 +486,130 @@ __device__ __forceinline__ void fft_pass(const double2* src, double2* dst, int M
         }
         const int base = (jb / Ns) * Ns * R + k;
 #pragma unroll
-        for (int t = 0; t < R; ++t) dst[base + t * Ns] = v[t];
+        for (int t = 0; t < R; ++t) da[base + t * Ns] = v[t];
     }
 }
 
-// Complex FFT of length M in LDS; returns the buffer holding the result.
-__device__ double2* fft_lds(double2* a, double2* scratch, const RingArgs& A, bool inverse) {
+constexpr int MAXB = 4;   // arrays transformed together
+
+// Complex FFTs of length M of narr (<= MAXB) arrays in LDS, ping-ponging with
+// the scratch arrays; res[a] receives the buffer holding the result of array a.
+__device__ void fft_lds(double2* const* a, double2* const* scratch, int narr, const RingArgs& A, bool inverse,
+                        double2** res) {
     const int M = A.nlon / 2;
     int Ns = 1;
-    double2* src = a;
-    double2* dst = scratch;
+    double2* src[MAXB];
+    double2* dst[MAXB];
+    for (int i = 0; i < MAXB; ++i) {
+        src[i] = i < narr ? a[i] : a[0];
+        dst[i] = i < narr ? scratch[i] : scratch[0];
+    }
     for (int p = 0; p < A.npass; ++p) {
         const int R = A.radix[p];
-        if (R == 4) fft_pass<4>(src, dst, M, Ns, A.tw, inverse);
-        else if (R == 2) fft_pass<2>(src, dst, M, Ns, A.tw, inverse);
-        else fft_pass<3>(src, dst, M, Ns, A.tw, inverse);
+        if (R == 4) fft_pass<4>(src, dst, narr, M, Ns, A.tw, inverse);
+        else if (R == 2) fft_pass<2>(src, dst, narr, M, Ns, A.tw, inverse);
+        else fft_pass<3>(src, dst, narr, M, Ns, A.tw, inverse);
         __syncthreads();
         Ns *= R;
-        double2* t = src;
-        src = dst;
-        dst = t;
+        for (int i = 0; i < MAXB; ++i) {
+            double2* t = src[i];
+            src[i] = dst[i];
+            dst[i] = t;
+        }
     }
-    return src;
+    for (int i = 0; i < narr; ++i) res[i] = src[i];
 }
 
-// Sum of the synthesis partials of order k at one latitude.
-__device__ __forceinline__ double2 fourier_coeff(const double2* fin_col, int k, const RingArgs& A) {
-    double2 acc = make_double2(0.0, 0.0);
-    const int s1 = A.segbase[k + 1];
-    for (int g = A.segbase[k]; g < s1; ++g) acc = cadd(acc, fin_col[static_cast<size_t>(g) * A.nlat]);
-    return acc;
+// Compile-time-length variant: the pass sequence (radix 4, then 2, then 3) is
+// fixed by M, every index division is by a constant, and the twiddles are read
+// from LDS.  The result is in `a` after an even number of passes, else in `scratch`.
+template <int R, int M, int NS, bool INV>
+__device__ __forceinline__ void fft_pass_ct(double2* const* src, double2* const* dst, int narr, const double2* tw) {
+    constexpr int nb = M / R;
+    constexpr int twstep = M / (NS * R);
+    const int total = nb * narr;
+    for (int x = threadIdx.x; x < total; x += blockDim.x) {
+        const int a = x / nb;
+        const int jb = x - a * nb;
+        const double2* sa = src[a];
+        double2* da = dst[a];
+        const int k = jb % NS;
+        double2 v[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            v[t] = sa[jb + t * nb];
+            if (t > 0) {
+                double2 wv = tw[t * k * twstep];
+                if (INV) wv.y = -wv.y;
+                v[t] = cmul(v[t], wv);
+            }
+        }
+        if constexpr (R == 2) {
+            const double2 a0 = v[0], b0 = v[1];
+            v[0] = cadd(a0, b0);
+            v[1] = csub(a0, b0);
+        } else if constexpr (R == 4) {
+            const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+            const double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+            const double2 b1r = INV ? make_double2(-b1.y, b1.x) : make_double2(b1.y, -b1.x);
+            v[0] = cadd(a0, b0);
+            v[2] = csub(a0, b0);
+            v[1] = cadd(a1, b1r);
+            v[3] = csub(a1, b1r);
+        } else {
+            constexpr double c = -0.5;
+            constexpr double s = INV ? 0.86602540378443864676 : -0.86602540378443864676;
+            const double2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+            const double2 m1 = make_double2(__builtin_fma(c, t1.x, v[0].x), __builtin_fma(c, t1.y, v[0].y));
+            const double2 m2 = make_double2(-s * t2.y, s * t2.x);
+            v[0] = cadd(v[0], t1);
+            v[1] = cadd(m1, m2);
+            v[2] = csub(m1, m2);
+        }
+        const int base = (jb / NS) * NS * R + k;
+#pragma unroll
+        for (int t = 0; t < R; ++t) da[base + t * NS] = v[t];
+    }
 }
 
-// Loads F_m (m <= L) of one latitude (adding the segment partials) and builds
-// the half-length spectrum Z of the inverse real FFT:
+template <int M, int NS, bool INV>
+__device__ __forceinline__ int fft_passes_ct(double2* const* src, double2* const* dst, int narr, const double2* tw) {
+    if constexpr (NS >= M) {
+        return 0;
+    } else {
+        constexpr int rem = M / NS;
+        constexpr int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
+        static_assert(rem % R == 0, "FFT length must be 2^a 3^b");
+        fft_pass_ct<R, M, NS, INV>(src, dst, narr, tw);
+        __syncthreads();
+        return 1 + fft_passes_ct<M, NS * R, INV>(dst, src, narr, tw);
+    }
+}
+
+template <int M, bool INV>
+__device__ __forceinline__ void fft_lds_ct(double2* const* a, double2* const* scratch, int narr, const double2* tw,
+                                           double2** res) {
+    double2* src[MAXB];
+    double2* dst[MAXB];
+    for (int i = 0; i < MAXB; ++i) {
+        src[i] = i < narr ? a[i] : a[0];
+        dst[i] = i < narr ? scratch[i] : scratch[0];
+    }
+    const int np = fft_passes_ct<M, 1, INV>(src, dst, narr, tw);
+    for (int i = 0; i < narr; ++i) res[i] = (np & 1) ? dst[i] : src[i];
+}
+
+// Loads F_m (m <= L) of one latitude (a contiguous row) and builds the
+// half-length spectrum Z of the inverse real FFT:
 //   Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/nlon} (X_k - conj X_{M-k}),
 // X_0 taken real, X_k = 0 for k > L.
-__device__ void load_inverse(const double2* fin_col, double2* z, const RingArgs& A) {
+__device__ void load_inverse(const double2* frow, double2* z, const RingArgs& A) {
     const int M = A.nlon / 2;
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double2 xk = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
-        if (k <= A.L) xk = fourier_coeff(fin_col, k, A);
+        if (k <= A.L) xk = frow[k];
         const int kr = M - k;                      // 1..M
-        if (kr <= A.L && kr < M) xr = fourier_coeff(fin_col, kr, A);
+        if (kr <= A.L && kr < M) xr = frow[kr];
         if (k == 0) xk.y = 0.0;
         const double2 xrc = conj2(xr);
         const double2 s = cadd(xk, xrc);
@@ -537,7 +622,7 @@ __device__ void load_inverse(const double2* fin_col, double2* z, const RingArgs&
 
 // From Z = FFT_M(x viewed as complex), the coefficients F_m = X_m / nlon, m <= L:
 // X_m = (Z_m + conj Z_{M-m})/2 - (i/2) e^{-2 pi i m/nlon} (Z_m - conj Z_{M-m}).
-__device__ void store_forward(const double2* Z, double2* fout_row, int nlat_stride, const RingArgs& A) {
+__device__ void store_forward(const double2* Z, double2* frow, const RingArgs& A) {
     const int M = A.nlon / 2;
     const double inv = 1.0 / static_cast<double>(A.nlon);
     for (int k = threadIdx.x; k <= A.L; k += blockDim.x) {
@@ -549,66 +634,90 @@ __device__ void store_forward(const double2* Z, double2* fout_row, int nlat_stri
         const double2 t = cmul(wk, d);
         // X = s/2 - i t/2
         const double2 X = make_double2(0.5 * (s.x + t.y), 0.5 * (s.y - t.x));
-        fout_row[static_cast<size_t>(k) * nlat_stride] = scale2(X, inv);
+        frow[k] = scale2(X, inv);
     }
 }
 
-// MODE 0: inverse only (Fourier -> grid), nf fields.
-// MODE 1: forward only (grid -> Fourier), nf fields.
-// MODE 2: non-linear products: inverse of h, zeta, U, V; forward of hU, hV, zU, zV, KE.
-template <int MODE>
+// MODE 0: inverse only (Fourier -> grid), nf fields, MAXB at a time.
+// MODE 1: forward only (grid -> Fourier), nf fields, MAXB at a time.
+// MODE 2: non-linear products: inverse of h, zeta, U, V; pointwise
+//         hU, hV, zU, zV, KE = (U^2 + V^2) / (2 cos^2 phi); forward of those five.
+// LDS: 2 MAXB arrays of nlon/2 complex values.
+// Transforms of `narr` arrays: compile-time length MC when nonzero, else runtime.
+template <int MC>
+__device__ __forceinline__ void ring_fft(double2* const* a, double2* const* scratch, int narr, const RingArgs& A,
+                                         const double2* twl, bool inverse, double2** res) {
+    if constexpr (MC > 0) {
+        if (inverse) fft_lds_ct<MC, true>(a, scratch, narr, twl, res);
+        else fft_lds_ct<MC, false>(a, scratch, narr, twl, res);
+    } else {
+        fft_lds(a, scratch, narr, A, inverse, res);
+    }
+}
+
+template <int MODE, int MC>
 __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
     extern __shared__ __align__(16) double2 lds[];
     const int M = A.nlon / 2;
     const int j = blockIdx.x;
-    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // forward outputs
-    const size_t pstride = static_cast<size_t>(A.nseg) * A.nlat;    // synthesis partials
-    double2* scratch = lds;
+    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // one field of [nlat][L+1]
+    const size_t row = static_cast<size_t>(j) * (A.L + 1);
+    double2* arr[2 * MAXB];
+#pragma unroll
+    for (int i = 0; i < 2 * MAXB; ++i) arr[i] = lds + i * M;
+    double2* res[MAXB];
+    double2* twl = lds + 2 * MAXB * M;               // twiddles (compile-time lengths only)
+    if constexpr (MC > 0) {
+        for (int k = threadIdx.x; k < M; k += blockDim.x) twl[k] = make_double2(A.tw[2 * k], A.tw[2 * k + 1]);
+    }
     if constexpr (MODE == 0) {
-        double2* a = lds + M;
-        for (int f = 0; f < A.nf; ++f) {
-            load_inverse(A.fin + f * pstride + j, a, A);
+        for (int f0 = 0; f0 < A.nf; f0 += MAXB) {
+            const int nb = min(MAXB, A.nf - f0);
+            for (int b = 0; b < nb; ++b) load_inverse(A.fin + (f0 + b) * fstride + row, arr[b], A);
             __syncthreads();
-            double2* res = fft_lds(a, scratch, A, true);
-            double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
-            for (int k = threadIdx.x; k < M; k += blockDim.x) g[k] = res[k];
+            ring_fft<MC>(arr, arr + MAXB, nb, A, twl, true, res);
+            for (int b = 0; b < nb; ++b) {
+                double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f0 + b) * A.nlat + j) * A.nlon);
+                for (int k = threadIdx.x; k < M; k += blockDim.x) g[k] = res[b][k];
+            }
             __syncthreads();
         }
     } else if constexpr (MODE == 1) {
-        double2* a = lds + M;
-        for (int f = 0; f < A.nf; ++f) {
-            const double2* g = reinterpret_cast<const double2*>(A.gin + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
-            for (int k = threadIdx.x; k < M; k += blockDim.x) a[k] = g[k];
+        for (int f0 = 0; f0 < A.nf; f0 += MAXB) {
+            const int nb = min(MAXB, A.nf - f0);
+            for (int b = 0; b < nb; ++b) {
+                const double2* g =
+                    reinterpret_cast<const double2*>(A.gin + (static_cast<size_t>(f0 + b) * A.nlat + j) * A.nlon);
+                for (int k = threadIdx.x; k < M; k += blockDim.x) arr[b][k] = g[k];
+            }
             __syncthreads();
-            double2* res = fft_lds(a, scratch, A, false);
-            store_forward(res, A.fout + f * fstride + j, A.nlat, A);
+            ring_fft<MC>(arr, arr + MAXB, nb, A, twl, false, res);
+            for (int b = 0; b < nb; ++b) store_forward(res[b], A.fout + (f0 + b) * fstride + row, A);
             __syncthreads();
         }
     } else {
-        // arrays: 0 h, 1 zeta, 2 U, 3 V, 4 KE, 5 hV; scratch
-        double2* arr[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) arr[i] = lds + (i + 1) * M;
-        double2* grid[4];
-        for (int f = 0; f < 4; ++f) {
-            load_inverse(A.fin + f * pstride + j, arr[f], A);
-            __syncthreads();
-            double2* res = fft_lds(arr[f], scratch, A, true);
-            if (res != arr[f]) {
-                for (int k = threadIdx.x; k < M; k += blockDim.x) arr[f][k] = res[k];
-                __syncthreads();
+        for (int f = 0; f < 4; ++f) load_inverse(A.fin + f * fstride + row, arr[f], A);
+        __syncthreads();
+        ring_fft<MC>(arr, arr + MAXB, 4, A, twl, true, res);
+        // the four arrays not holding results are free
+        double2* freea[MAXB];
+        {
+            int nfree = 0;
+            for (int i = 0; i < 2 * MAXB; ++i) {
+                bool used = false;
+                for (int b = 0; b < MAXB; ++b) used |= (arr[i] == res[b]);
+                if (!used) freea[nfree++] = arr[i];
             }
-            grid[f] = arr[f];
         }
         const int jn = j < A.half ? j : A.nlat - 1 - j;
-        const double s = A.sint[jn];
-        const double kefac = 0.5 / (s * s);
-        double* h = reinterpret_cast<double*>(arr[0]);
-        double* z = reinterpret_cast<double*>(arr[1]);
-        const double* U = reinterpret_cast<const double*>(arr[2]);
-        double* V = reinterpret_cast<double*>(arr[3]);
-        double* ke = reinterpret_cast<double*>(arr[4]);
-        double* hv = reinterpret_cast<double*>(arr[5]);
+        const double sn = A.sint[jn];
+        const double kefac = 0.5 / (sn * sn);
+        double* h = reinterpret_cast<double*>(res[0]);
+        double* z = reinterpret_cast<double*>(res[1]);
+        const double* U = reinterpret_cast<const double*>(res[2]);
+        double* V = reinterpret_cast<double*>(res[3]);
+        double* ke = reinterpret_cast<double*>(freea[0]);
+        double* hv = reinterpret_cast<double*>(freea[1]);
         for (int k = threadIdx.x; k < A.nlon; k += blockDim.x) {
             const double u = U[k], v = V[k], hh = h[k], zz = z[k];
             ke[k] = __builtin_fma(u, u, v * v) * kefac;
@@ -618,18 +727,72 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
             z[k] = zz * u;          // zeta U
         }
         __syncthreads();
-        // forward transforms: hU (arr0) -> field 0, hV (arr5) -> 1, zU (arr1) -> 2, zV (arr3) -> 3, KE (arr4) -> 4
-        const int src[5] = {0, 5, 1, 3, 4};
-        for (int f = 0; f < 5; ++f) {
-            double2* res = fft_lds(arr[src[f]], scratch, A, false);
-            store_forward(res, A.fout + f * fstride + j, A.nlat, A);
-            __syncthreads();
+        // forward transforms in two batches: (hU, hV, zU) then (zV, KE);
+        // output fields 0 hU, 1 hV, 2 zU, 3 zV, 4 KE
+        {
+            double2* in3[MAXB] = {res[0], freea[1], res[1], res[1]};
+            double2* sc3[MAXB] = {res[2], freea[2], freea[3], freea[3]};
+            double2* out3[MAXB];
+            ring_fft<MC>(in3, sc3, 3, A, twl, false, out3);
+            store_forward(out3[0], A.fout + 0 * fstride + row, A);
+            store_forward(out3[1], A.fout + 1 * fstride + row, A);
+            store_forward(out3[2], A.fout + 2 * fstride + row, A);
         }
-        (void)grid;
+        __syncthreads();   // batch 1 outputs are read before their arrays become scratch
+        {
+            double2* in2[MAXB] = {res[3], freea[0], res[3], res[3]};
+            double2* sc2[MAXB] = {res[2], freea[2], res[2], res[2]};
+            double2* out2[MAXB];
+            ring_fft<MC>(in2, sc2, 2, A, twl, false, out2);
+            store_forward(out2[0], A.fout + 3 * fstride + row, A);
+            store_forward(out2[1], A.fout + 4 * fstride + row, A);
+        }
+    }
+}
+
+// Sums the synthesis partials of each order over its degree segments and
+// transposes [nf][nseg][nlat] -> [nf][nlat][L+1] through LDS, so that the ring
+// kernel reads one contiguous row per latitude.  Block: (field, 16 orders,
+// 64 latitudes), 256 threads.
+constexpr int GM = 16, GJ = 64;
+__global__ __launch_bounds__(256) void gather_fourier_kernel(const double2* __restrict__ part,
+                                                             double2* __restrict__ four,
+                                                             const int* __restrict__ segbase, int L, int nlat,
+                                                             int nseg) {
+    __shared__ double2 tile[GM][GJ + 1];
+    const int f = blockIdx.z;
+    const int m0 = blockIdx.y * GM, j0 = blockIdx.x * GJ;
+    const double2* pf = part + static_cast<size_t>(f) * nseg * nlat;
+    for (int x = threadIdx.x; x < GM * GJ; x += blockDim.x) {
+        const int mi = x / GJ, jj = x % GJ;
+        const int m = m0 + mi, j = j0 + jj;
+        double2 acc = make_double2(0.0, 0.0);
+        if (m <= L && j < nlat) {
+            const int g1 = segbase[m + 1];
+            for (int g = segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * nlat + j]);
+        }
+        tile[mi][jj] = acc;
+    }
+    __syncthreads();
+    double2* ff = four + static_cast<size_t>(f) * nlat * (L + 1);
+    for (int x = threadIdx.x; x < GM * GJ; x += blockDim.x) {
+        const int jj = x / GM, mi = x % GM;
+        const int m = m0 + mi, j = j0 + jj;
+        if (m <= L && j < nlat) ff[static_cast<size_t>(j) * (L + 1) + m] = tile[mi][jj];
     }
 }
 
 }  // namespace
+
+int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream) {
+    const dim3 grid((ctx->nlat + GJ - 1) / GJ, (ctx->L + 1 + GM - 1) / GM, nf);
+    const int slot = prof_begin(ctx, REXI_KERNEL_GATHER, stream);
+    hipLaunchKernelGGL(gather_fourier_kernel, grid, dim3(256), 0, stream, reinterpret_cast<const double2*>(part),
+                       reinterpret_cast<double2*>(four), ctx->d_segbase, ctx->L, ctx->nlat, ctx->nseg);
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_GATHER, slot, stream);
+    return REXI_OK;
+}
 
 // ------------------------------------------------------------ launchers --
 static LegArgs leg_args(const swe_ctx* ctx) {
@@ -661,8 +824,6 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     r.twr = ctx->d_twr;
     r.sint = ctx->d_sint;
     r.radix = ctx->d_radix;
-    r.segbase = ctx->d_segbase;
-    r.nseg = ctx->nseg;
     r.npass = ctx->npass;
     r.L = ctx->L;
     r.nlat = ctx->nlat;
@@ -671,10 +832,21 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     return r;
 }
 
-static int ring_lds_bytes(const swe_ctx* ctx, int mode) {
+static int ring_lds_bytes(const swe_ctx* ctx, int /*mode*/) {
     const int M = ctx->nlon / 2;
-    const int arrays = mode == 2 ? 7 : 2;
-    return arrays * M * static_cast<int>(sizeof(double2));
+    return (2 * MAXB + 1) * M * static_cast<int>(sizeof(double2));
+}
+
+template <int MODE>
+static const void* ring_fn(int M) {
+    switch (M) {
+        case 48: return reinterpret_cast<const void*>(&ring_kernel<MODE, 48>);
+        case 96: return reinterpret_cast<const void*>(&ring_kernel<MODE, 96>);
+        case 192: return reinterpret_cast<const void*>(&ring_kernel<MODE, 192>);
+        case 384: return reinterpret_cast<const void*>(&ring_kernel<MODE, 384>);
+        case 768: return reinterpret_cast<const void*>(&ring_kernel<MODE, 768>);
+        default: return reinterpret_cast<const void*>(&ring_kernel<MODE, 0>);
+    }
 }
 
 static int allow_lds(const void* fn, size_t bytes, const char* what) {
@@ -688,9 +860,10 @@ static int allow_lds(const void* fn, size_t bytes, const char* what) {
 
 int sht_configure_kernels(swe_ctx* ctx) {
     int rc;
-    if ((rc = allow_lds(reinterpret_cast<const void*>(&ring_kernel<2>), ring_lds_bytes(ctx, 2),
-                        "the longitude FFT")) != REXI_OK)
-        return rc;
+    const int M = ctx->nlon / 2;
+    if ((rc = allow_lds(ring_fn<0>(M), ring_lds_bytes(ctx, 0), "the longitude FFT")) != REXI_OK) return rc;
+    if ((rc = allow_lds(ring_fn<1>(M), ring_lds_bytes(ctx, 1), "the longitude FFT")) != REXI_OK) return rc;
+    if ((rc = allow_lds(ring_fn<2>(M), ring_lds_bytes(ctx, 2), "the longitude FFT")) != REXI_OK) return rc;
     return REXI_OK;
 }
 
@@ -771,9 +944,10 @@ int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const d
     R.nf = nf;
     const size_t lds = static_cast<size_t>(ring_lds_bytes(ctx, mode));
     const int slot = prof_begin(ctx, REXI_KERNEL_RING, stream);
-    if (mode == 0) hipLaunchKernelGGL(ring_kernel<0>, dim3(ctx->nlat), dim3(256), lds, stream, R);
-    else if (mode == 1) hipLaunchKernelGGL(ring_kernel<1>, dim3(ctx->nlat), dim3(256), lds, stream, R);
-    else hipLaunchKernelGGL(ring_kernel<2>, dim3(ctx->nlat), dim3(256), lds, stream, R);
+    const int M = ctx->nlon / 2;
+    const void* fn = mode == 0 ? ring_fn<0>(M) : (mode == 1 ? ring_fn<1>(M) : ring_fn<2>(M));
+    void* kargs[] = {&R};
+    REXI_HIP(hipLaunchKernel(fn, dim3(ctx->nlat), dim3(256), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_RING, slot, stream);
     return REXI_OK;
