@@ -130,6 +130,11 @@ def main():
     ap.add_argument("--stage", choices=["auto", "rexi"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solver", choices=["default", "fused", "stream", "hybrid"], default="default",
+                    help="REXI chain-solve schedule")
+    ap.add_argument("--seg-rows", type=int, default=0, help="REXI solve segment length (16, 32; 0 = default)")
+    ap.add_argument("--waves", type=int, default=0, help="REXI solve waves per workgroup (1, 2, 4; 0 = default)")
+    ap.add_argument("--ppl", type=int, default=0, help="REXI solve poles per lane (1, 2; 0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed but not built "
@@ -146,6 +151,10 @@ def main():
     alpha, beta, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
     full = args.stage == "auto" and w.nlat > 0
     ctx = api.SWE(w.L, w.nlat if full else 0, w.nlon if full else 0, prec=w.prec)
+    solver = {"default": 0, "fused": api.SOLVER_FUSED, "stream": api.SOLVER_STREAM,
+              "hybrid": api.SOLVER_HYBRID}[args.solver]
+    if solver or args.seg_rows or args.waves or args.ppl:
+        ctx.set_tuning(solver=solver, seg_rows=args.seg_rows, waves=args.waves, poles_per_lane=args.ppl)
     U = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
     V = torch.empty_like(U)
     stream = torch.cuda.current_stream()
@@ -156,13 +165,15 @@ def main():
         else:
             ctx.rexi_linear_step(alpha, beta, w.dt, src, dst, stream)
 
+    ctx.profile(True)
     for i in range(args.warmup):
         step(U, V)
         U, V = V, U
     torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read(api.KERNEL_SOLVE)
-    ctx.profile_read(api.KERNEL_REDUCE)
+    # the factorization of the streaming schedules is built by the first call
+    fact_ms, fact_n = ctx.profile_read(api.KERNEL_FACTOR)
+    for kid in range(api.KERNEL_FACTOR):
+        ctx.profile_read(kid)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -231,6 +242,7 @@ def main():
             "algorithmic_flops_per_launch": solve_flops(w.L, w.N),
         },
         "kernels": stage_ms,
+        "setup": {"rexi_factor_kernel_ms": fact_ms / max(fact_n, 1), "launches": fact_n},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, full)

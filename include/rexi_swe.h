@@ -106,8 +106,12 @@ int swe_destroy(swe_ctx* ctx);
  * each zonal order m: every (pole, m) system is banded and is solved on the
  * device as two complex tridiagonal chains after eliminating h.
  * alpha, beta: host arrays of 2N doubles; they are copied to the device and
- * cached inside the context (keyed by their contents and dt).  U0, U1: device
- * states [3][modes] complex128; they must not overlap.
+ * cached inside the context (keyed by their contents and dt), together with
+ * the chain factorization when a streaming schedule is selected
+ * (swe_set_tuning); the cache is written on the stream of the call that
+ * rebuilds it, so a later call on another stream must be ordered after that
+ * call by the caller.  U0, U1: device states [3][modes] complex128; they must
+ * not overlap.
  * Before enqueueing, the host checks that the polygon of the poles -alpha_n
  * winds once around the segment i[-rho, rho], rho = dt (sqrt(g H L(L+1))/a +
  * 2 Omega), which bounds the spectrum of dt L; otherwise REXI_ENUMERIC.
@@ -181,18 +185,39 @@ enum {
     REXI_KERNEL_RING = 3,        /* longitude FFTs and pointwise products */
     REXI_KERNEL_LEG_ANAL = 4,    /* Legendre analysis (Fourier -> spectral) */
     REXI_KERNEL_GATHER = 5,      /* sum of segment partials + transpose */
-    REXI_KERNEL_COUNT = 6
+    REXI_KERNEL_FACTOR = 6,      /* pivots of the chain factorization (once per coefficient set and dt) */
+    REXI_KERNEL_COUNT = 7
 };
 int swe_profile(swe_ctx* ctx, int enable);
 int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches);
 
 /*
- * swe_set_tuning -- choose the launch shape of the REXI solve kernel:
- * seg_rows = rows per register-resident segment of the chain sweep (8, 16 or
- * 32), waves = waves per workgroup (1, 2 or 4).  0 keeps the current value.
+ * Schedules of the REXI chain solve.  All three give bit-identical results.
+ *   REXI_SOLVER_FUSED:  the pivots are recomputed in both sweeps; nothing but
+ *                       the state and the tables is read (arithmetic bound).
+ *   REXI_SOLVER_STREAM: the pivots of every (pole, chain row) are computed
+ *                       once per coefficient set and dt into a cache held by
+ *                       the context (2 modes x N x 8 B in FP32, 16 B in FP64)
+ *                       and read by both sweeps (HBM bound).
+ *   REXI_SOLVER_HYBRID: the forward sweep reads the cached pivots, the backward
+ *                       pass recomputes them.
+ * The cache is rebuilt when alpha, beta, N, dt or the solve precision change.
+ */
+enum { REXI_SOLVER_FUSED = 1, REXI_SOLVER_STREAM = 2, REXI_SOLVER_HYBRID = 3 };
+
+/*
+ * swe_set_tuning -- choose the schedule and launch shape of the REXI solve:
+ * solver = REXI_SOLVER_*, seg_rows = rows per register-resident segment of
+ * the chain sweep, waves = waves per workgroup (1, 2 or 4), poles_per_lane =
+ * poles whose sweeps one lane interleaves (1 or 2).  seg_rows is 16 or 32 with
+ * one pole per lane and 8 or 16 with two; another pairing makes the next
+ * solve fail with REXI_ENOTSUP.
+ * 0 keeps the current value.  The schedule, seg_rows and waves never change
+ * the result bits; poles_per_lane regroups the pole sum (results agree to
+ * rounding).
  * Errors: REXI_EINVAL for an unsupported value.
  */
-int swe_set_tuning(swe_ctx* ctx, int seg_rows, int waves);
+int swe_set_tuning(swe_ctx* ctx, int solver, int seg_rows, int waves, int poles_per_lane);
 
 #ifdef __cplusplus
 }

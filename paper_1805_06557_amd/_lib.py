@@ -24,7 +24,7 @@ SIGNATURES = {
     "swe_strang_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "swe_sync": (_c_int, [_vp]),
     "rexi_last_error": (ctypes.c_char_p, []),
-    "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int]),
+    "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
     "swe_profile": (_c_int, [_vp, _c_int]),
     "swe_profile_read": (_c_int, [_vp, _c_int, _dp, ctypes.POINTER(_c_int)]),
 }

@@ -15,7 +15,8 @@ from . import _lib
 REXI_OK, REXI_EINVAL, REXI_ENOMEM, REXI_EDEVICE, REXI_ENOTSUP, REXI_ENUMERIC = 0, -1, -2, -3, -4, -5
 FN_EXP, FN_PSI1, FN_PSI2 = 0, 1, 2
 PREC_FP64, PREC_FP32_SOLVE, PREC_BF16_SPLIT, PREC_FP16_SPLIT = 0, 1, 2, 4
-KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_GATHER = 0, 1, 2, 3, 4, 5
+KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_GATHER, KERNEL_FACTOR = range(7)
+SOLVER_FUSED, SOLVER_STREAM, SOLVER_HYBRID = 1, 2, 3
 EARTH = dict(a=6.37122e6, g=9.80616, H=1.0e4, Omega=7.292e-5)
 
 
@@ -107,8 +108,9 @@ class SWE:
     def handle(self):
         return self._h
 
-    def set_tuning(self, seg_rows: int = 0, waves: int = 0) -> None:
-        _check(self._lib.swe_set_tuning(self._h, seg_rows, waves), "swe_set_tuning")
+    def set_tuning(self, solver: int = 0, seg_rows: int = 0, waves: int = 0, poles_per_lane: int = 0) -> None:
+        """Schedule (SOLVER_*) and launch shape of the REXI solve; 0 keeps a value."""
+        _check(self._lib.swe_set_tuning(self._h, solver, seg_rows, waves, poles_per_lane), "swe_set_tuning")
 
     def rexi_linear_step(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
         a = _host_coeffs(alpha)

@@ -61,6 +61,8 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     key = fnv1a(&N, sizeof(N), key);
     if (ctx->poles_valid && key == ctx->poles_key && N == ctx->poles_n && dt == ctx->poles_dt)
         return REXI_OK;
+    ctx->poles_valid = false;
+    ctx->fact_valid = false;
 
     std::vector<PoleData> pd(N);
     build_pole_data(alpha, beta, N, pd.data());
@@ -250,6 +252,11 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     ctx->nlat = nlat;
     ctx->nlon = nlon;
     ctx->prec = prec;
+    // measured defaults at T255 / N = 800 (the autotuner refines them per problem)
+    ctx->tune.solver = REXI_SOLVER_FUSED;
+    ctx->tune.poles_per_lane = 1;
+    ctx->tune.seg_rows = 16;
+    ctx->tune.waves = (prec & REXI_PREC_FP32_SOLVE) ? 4 : 2;
     ctx->a = a;
     ctx->g = g;
     ctx->H = H;
@@ -288,6 +295,9 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_coef) (void)hipFree(ctx->d_coef);
     if (ctx->d_poles) (void)hipFree(ctx->d_poles);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
+    if (ctx->d_rows) (void)hipFree(ctx->d_rows);
+    if (ctx->d_fact) (void)hipFree(ctx->d_fact);
+    if (ctx->d_ckpt) (void)hipFree(ctx->d_ckpt);
     void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
@@ -306,12 +316,18 @@ int swe_destroy(swe_ctx* ctx) {
     return REXI_OK;
 }
 
-int swe_set_tuning(swe_ctx* ctx, int seg_rows, int waves) {
+int swe_set_tuning(swe_ctx* ctx, int solver, int seg_rows, int waves, int poles_per_lane) {
     if (!ctx) return fail(REXI_EINVAL, "swe_set_tuning: NULL context");
+    if (solver && solver != REXI_SOLVER_FUSED && solver != REXI_SOLVER_STREAM && solver != REXI_SOLVER_HYBRID)
+        return fail(REXI_EINVAL, "swe_set_tuning: unknown solver schedule");
     if (seg_rows && seg_rows != 8 && seg_rows != 16 && seg_rows != 32)
         return fail(REXI_EINVAL, "swe_set_tuning: seg_rows must be 8, 16 or 32");
     if (waves && waves != 1 && waves != 2 && waves != 4)
         return fail(REXI_EINVAL, "swe_set_tuning: waves must be 1, 2 or 4");
+    if (poles_per_lane && poles_per_lane != 1 && poles_per_lane != 2)
+        return fail(REXI_EINVAL, "swe_set_tuning: poles_per_lane must be 1 or 2");
+    if (solver) ctx->tune.solver = solver;
+    if (poles_per_lane) ctx->tune.poles_per_lane = poles_per_lane;
     if (seg_rows) ctx->tune.seg_rows = seg_rows;
     if (waves) ctx->tune.waves = waves;
     return REXI_OK;

@@ -105,8 +105,10 @@ int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream);
 void prof_end(swe_ctx* ctx, int kernel, int slot, hipStream_t stream);
 
 struct Tuning {
-    int seg_rows = 16;   // rows per register-resident segment (8, 16, 32)
-    int waves = 1;       // waves per workgroup (1, 2, 4)
+    int solver = REXI_SOLVER_FUSED;   // sweep schedule (REXI_SOLVER_*)
+    int seg_rows = 16;                // rows per register-resident segment (8, 16, 32)
+    int waves = 4;                    // waves per workgroup (1, 2, 4)
+    int poles_per_lane = 1;           // poles swept together by one lane (1, 2)
 };
 
 }  // namespace rexi
@@ -127,6 +129,19 @@ struct swe_ctx {
     uint64_t poles_key = 0;
     double poles_dt = 0;
     bool poles_valid = false;
+
+    // chain-ordered row records of the REXI solve, rebuilt per call [2 modes]
+    void* d_rows = nullptr;
+    // cached factorization: pivots of every chain row for every pole,
+    // [2 modes][N rounded to 64] complex (FP32 or FP64), valid for the cached
+    // coefficient set and dt
+    void* d_fact = nullptr;
+    size_t fact_cap = 0;
+    bool fact_valid = false;
+    int fact_prec = 0;          // 1: FP32 pivots, 2: FP64 pivots
+    // segment-start states of the chain sweeps (per launch)
+    void* d_ckpt = nullptr;
+    size_t ckpt_cap = 0;
 
     // partial sums over pole blocks: [npb][3][modes] complex
     double* d_partial = nullptr;

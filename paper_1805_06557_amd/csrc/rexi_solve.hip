@@ -12,18 +12,22 @@
 // Chain c = 0 holds (delta_m, zeta_{m+1}, delta_{m+2}, ...), chain c = 1 holds
 // (zeta_m, delta_{m+1}, ...).
 //
-// Mapping: one wave per (m, chain, block of 64 poles); lane = pole, so every
-// table value and right-hand side is wave-uniform (scalar loads) and the
-// per-lane work is a sequential sweep over l.  The chain is cut into segments
-// of S rows: a first forward sweep keeps only the state entering each segment
-// (a checkpoint in LDS); the backward pass then re-sweeps one segment at a
-// time into registers and back-substitutes through it.  The sum over the
-// 64 poles of a wave is formed in LDS (write lane-major, read transposed,
-// finish with a 3-step butterfly), in FP64, in a fixed order.  Blocks of
-// poles write partial sums that a second kernel adds in pole-block order,
-// so results are bit-reproducible.  The file is compiled without automatic
-// FMA contraction and every fused multiply-add is written out, so all inlined
-// copies of a step perform the same rounding.
+// Mapping: one wave per (m, chain, block of 64 P poles); lane l carries P
+// poles, so every table value and right-hand side is wave-uniform (read by
+// broadcast from the chain's row records, staged once per workgroup in LDS)
+// and the per-lane work is a sequential sweep over l.  The chain is cut into
+// segments of S rows: a first forward sweep keeps only the state entering each
+// segment (a checkpoint in a global workspace, read back once); the backward
+// pass then re-sweeps one segment at a time into registers and back-substitutes
+// through it.  The pivots of the re-sweep are recomputed (FUSED) or read from a
+// factorization cached per coefficient set and dt (STREAM, HYBRID); every
+// schedule performs the same operations on each (pole, row), so all agree bit
+// for bit.  The sum over the poles of a wave is formed in FP64 in a fixed order:
+// lane-local over its P poles, then in LDS (write lane-major, read transposed,
+// finish with a 3-step butterfly).  Pole waves write partial sums that a second
+// kernel adds in pole-wave order, so results are bit-reproducible.  The file is
+// compiled without automatic FMA contraction and every fused multiply-add is
+// written out, so all inlined copies of a step perform the same rounding.
 #include <type_traits>
 #include <utility>
 
@@ -33,7 +37,6 @@ namespace rexi {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int RED_SLOTS = 8;  // staging slots per reduction round (6 used)
 
 template <typename T>
 struct Cx {
@@ -57,6 +60,14 @@ __device__ __forceinline__ float rcp_refined(float n) {
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Orders the LDS accesses of one wave (its lanes exchange data through a
+// wave-private LDS region): LDS operations of a wave complete in order, so a
+// compiler-level fence plus a wave barrier suffices.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
     if constexpr (I < N) {
@@ -65,76 +76,166 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Uniform data of one chain row, in chain order (record 2 base(m) + c Lm + j),
+// rebuilt for every call by rexi_rows_kernel from the state, dt and the
+// per-mode coefficients, so that the solve reads one contiguous record per row
+// (two scalar loads) and does no wave-uniform arithmetic.
+struct RowRec {
+    double a, c;       // couplings to rows j-1 and j+1, signed for the row type, times dt
+    double dts;        // dt m q_k
+    double g2;         // dt^2 H g k(k+1)/a^2  (delta rows; 0 for zeta rows)
+    double tx, ty;     // dt g k(k+1)/a^2 r_h   (delta rows; 0 for zeta rows)
+    double rx, ry;     // right-hand side r_delta or r_zeta
+    double hx, hy;     // r_h (delta rows)
+    float af, cf;      // a, c rounded to FP32
+    float rfx, rfy;    // r rounded to FP32
+};
+static_assert(sizeof(RowRec) == 96, "RowRec layout");
+
+__global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
+                                                        RowRec* __restrict__ rec, int L, int modes, double dt,
+                                                        double H) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= modes) return;
+    // recover (m, k) from the m-major index
+    int m = 0;
+    while (m < L && (m + 1) * (2 * L + 3 - (m + 1)) / 2 <= idx) ++m;
+    const int base = m * (2 * L + 3 - m) / 2;
+    const int j = idx - base;
+    const int Lm = L - m + 1;
+    const ModeCoef cf = coef[idx];
+    const double2 rh = U0[idx], rz = U0[modes + idx], rd = U0[2 * modes + idx];
+    const int cd = j & 1;                                   // chain in which row j is a delta row
+    RowRec d;
+    d.a = -dt * cf.cm;
+    d.c = -dt * cf.cp;
+    d.dts = dt * cf.s;
+    d.g2 = dt * dt * H * cf.gN;
+    d.tx = dt * cf.gN * rh.x;
+    d.ty = dt * cf.gN * rh.y;
+    d.rx = rd.x;
+    d.ry = rd.y;
+    d.hx = rh.x;
+    d.hy = rh.y;
+    d.af = static_cast<float>(d.a);
+    d.cf = static_cast<float>(d.c);
+    d.rfx = static_cast<float>(rd.x);
+    d.rfy = static_cast<float>(rd.y);
+    rec[2 * base + cd * Lm + j] = d;
+    RowRec z;
+    z.a = dt * cf.cm;
+    z.c = dt * cf.cp;
+    z.dts = dt * cf.s;
+    z.g2 = 0.0;
+    z.tx = z.ty = 0.0;
+    z.rx = rz.x;
+    z.ry = rz.y;
+    z.hx = z.hy = 0.0;
+    z.af = static_cast<float>(z.a);
+    z.cf = static_cast<float>(z.c);
+    z.rfx = static_cast<float>(rz.x);
+    z.rfy = static_cast<float>(rz.y);
+    rec[2 * base + (1 - cd) * Lm + j] = z;
+}
+
 struct SolveArgs {
-    const double2* __restrict__ U0;     // [3][modes]
-    double2* __restrict__ out;          // [npb][3][modes]
+    const RowRec* __restrict__ rec;     // [2 modes] chain-ordered row records
+    double2* __restrict__ out;          // [pole waves][3][modes] partial sums (one per wave of 64 poles)
     const PoleData* __restrict__ poles; // [N]
-    const ModeCoef* __restrict__ coef;  // [modes]
-    int L, modes, N, npb;
-    double dt, dt2H, dtH;
+    const void* __restrict__ fact;      // cached pivots [2 modes][npad] complex T (STREAM, HYBRID)
+    void* __restrict__ ckpt;            // segment-start states [tasks][pole waves][nck_max][CKW][P][64] complex T
+    int L, modes, N, npb, npad;         // npb: workgroups per chain; npad: N rounded up to 64 P
+    int nck_max, rec_bytes;             // per-wave checkpoints; LDS bytes of the records
+    double dtH;
 };
 
 struct Lane {
     PoleData p;
     double wzr, wzi;   // w / z
+    float zrf, zif;    // z in FP32
 };
 
-// One forward Thomas step on row j (degree k = m + j) of a chain.
+// Right-hand side d = r + t/z of a row, formed in FP64 and rounded once to T
+// (zeta rows have t = 0 and use the record's own rounding of r).
 template <typename T, bool DELTA>
-__device__ __forceinline__ void forward_row(const SolveArgs& A, const Lane& ln, const ModeCoef* cf,
-                                            const double2* uh, const double2* uz, const double2* ud,
-                                            int j, Cx<T>& cp, Cx<T>& dp) {
-    const ModeCoef c = cf[j];
-    const double sgn = DELTA ? -A.dt : A.dt;
-    const double a = sgn * c.cm;
-    const double cc = sgn * c.cp;
-    double br = ln.p.zr;
-    double bi = __builtin_fma(-A.dt, c.s, ln.p.zi);
-    double dr, di;
+__device__ __forceinline__ void row_rhs(const RowRec& R, const Lane& ln, T& dR, T& dI) {
     if constexpr (DELTA) {
-        const double2 rh = uh[j];
-        const double2 rd = ud[j];
-        const double g2 = A.dt2H * c.gN;
-        br = __builtin_fma(g2, ln.p.zir, br);
-        bi = __builtin_fma(g2, ln.p.zii, bi);
-        const double g1 = A.dt * c.gN;
-        const double tr = __builtin_fma(ln.p.zir, rh.x, -(ln.p.zii * rh.y));
-        const double ti = __builtin_fma(ln.p.zir, rh.y, ln.p.zii * rh.x);
-        dr = __builtin_fma(g1, tr, rd.x);
-        di = __builtin_fma(g1, ti, rd.y);
+        dR = static_cast<T>(__builtin_fma(ln.p.zir, R.tx, __builtin_fma(-ln.p.zii, R.ty, R.rx)));
+        dI = static_cast<T>(__builtin_fma(ln.p.zir, R.ty, __builtin_fma(ln.p.zii, R.tx, R.ry)));
+    } else if constexpr (std::is_same<T, float>::value) {
+        dR = R.rfx;
+        dI = R.rfy;
     } else {
-        const double2 rz = uz[j];
-        dr = rz.x;
-        di = rz.y;
+        dR = R.rx;
+        dI = R.ry;
     }
-    const T ta = static_cast<T>(a);
-    const T wr = fmaT(-ta, cp.x, static_cast<T>(br));
-    const T wi = fmaT(-ta, cp.y, static_cast<T>(bi));
+}
+
+template <typename T>
+__device__ __forceinline__ T coupling_a(const RowRec& R) {
+    if constexpr (std::is_same<T, float>::value) return R.af; else return R.a;
+}
+template <typename T>
+__device__ __forceinline__ T coupling_c(const RowRec& R) {
+    if constexpr (std::is_same<T, float>::value) return R.cf; else return R.c;
+}
+
+// Pivot of a row: p = 1/(b - a c'_prev), then c' = c p.  The diagonal
+// b = z + g2/z - i dts is formed in FP64 for delta rows (where it can be much
+// smaller than its terms) and rounded once to T; for zeta rows |b| ~ |z| and it
+// is formed in T.  Used by the factorization and by both sweeps of the fused
+// schedule, so cached and recomputed pivots agree bit for bit.
+template <typename T, bool DELTA>
+__device__ __forceinline__ Cx<T> pivot_row(const RowRec& R, const Lane& ln, Cx<T>& cp) {
+    T bR, bI;
+    if constexpr (DELTA) {
+        bR = static_cast<T>(__builtin_fma(R.g2, ln.p.zir, ln.p.zr));
+        bI = static_cast<T>(__builtin_fma(R.g2, ln.p.zii, ln.p.zi) - R.dts);
+    } else if constexpr (std::is_same<T, float>::value) {
+        bR = ln.zrf;
+        bI = ln.zif - static_cast<float>(R.dts);
+    } else {
+        bR = ln.p.zr;
+        bI = ln.p.zi - R.dts;
+    }
+    const T ta = coupling_a<T>(R), tc = coupling_c<T>(R);
+    const T wr = fmaT(-ta, cp.x, bR);
+    const T wi = fmaT(-ta, cp.y, bI);
     const T inv = rcp_refined(fmaT(wr, wr, wi * wi));
-    const T pr = wr * inv, pi = -wi * inv;
-    const T ur = fmaT(-ta, dp.x, static_cast<T>(dr));
-    const T ui = fmaT(-ta, dp.y, static_cast<T>(di));
-    const T tc = static_cast<T>(cc);
-    cp.x = tc * pr;
-    cp.y = tc * pi;
-    dp.x = fmaT(ur, pr, -(ui * pi));
-    dp.y = fmaT(ur, pi, ui * pr);
+    const Cx<T> p{wr * inv, -wi * inv};
+    cp.x = tc * p.x;
+    cp.y = tc * p.y;
+    return p;
+}
+
+// The right-hand-side part of a forward step with pivot p: d' = (d - a d'_prev) p.
+template <typename T, bool DELTA>
+__device__ __forceinline__ void forward_rhs(const RowRec& R, const Lane& ln, Cx<T> p, Cx<T>& dp) {
+    T dR, dI;
+    row_rhs<T, DELTA>(R, ln, dR, dI);
+    const T ta = coupling_a<T>(R);
+    const T ur = fmaT(-ta, dp.x, dR);
+    const T ui = fmaT(-ta, dp.y, dI);
+    dp.x = fmaT(ur, p.x, -(ui * p.y));
+    dp.y = fmaT(ur, p.y, ui * p.x);
 }
 
 // Sums the 6 staged slots over the 64 lanes of the wave and writes them.
-// red: [RED_SLOTS][64] double2.  Slot s < 4: chain row 4g + s; slots 4, 5: h of
-// the two delta rows of the group.
+// red: [6][64] double2.  Slot s < 4: chain row 4g + s; slots 4, 5: h of the two
+// delta rows of the group.
 template <int C>
-__device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, int lane, int pb,
-                                             int base, int j0g, int Lm) {
-    __syncthreads();
+__device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, int lane, int pw, int base,
+                                             int j0g, int Lm) {
+    wave_sync();
     const int slot = lane >> 3, part = lane & 7;
     double sx = 0.0, sy = 0.0;
+    if (slot < 6) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const double2 v = red[slot * WAVE + i * 8 + part];
-        sx += v.x;
-        sy += v.y;
+        for (int i = 0; i < 8; ++i) {
+            const double2 v = red[slot * WAVE + i * 8 + part];
+            sx += v.x;
+            sy += v.y;
+        }
     }
 #pragma unroll
     for (int msk = 1; msk < 8; msk <<= 1) {
@@ -151,27 +252,18 @@ __device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, i
             field = 0;
         }
         const int j = j0g + q;
-        if (j < Lm) A.out[(pb * 3 + field) * A.modes + base + j] = make_double2(sx, sy);
+        if (j < Lm) A.out[(pw * 3 + field) * A.modes + base + j] = make_double2(sx, sy);
     }
-    __syncthreads();
+    wave_sync();
 }
 
-template <typename T, int S, int C>
-__device__ __forceinline__ void solve_segment(const SolveArgs& A, const Lane& ln, const ModeCoef* cf,
-                                              const double2* uh, const double2* uz, const double2* ud,
-                                              int seg, int Lm, int base, int pb, int lane, Cx<T> cp,
-                                              Cx<T> dp, Cx<T>& vnext, double2* red) {
-    Cx<T> cs[S], ds[S];
-    const int j0 = seg * S;
-    static_for<0, S>([&](auto Q) {
-        constexpr int jj = decltype(Q)::value;
-        constexpr bool DELTA = ((jj + C) & 1) == 0;
-        if (j0 + jj < Lm) {
-            forward_row<T, DELTA>(A, ln, cf, uh, uz, ud, j0 + jj, cp, dp);
-            cs[jj] = cp;
-            ds[jj] = dp;
-        }
-    });
+// Back-substitution through one segment whose pivots ps and d' values ds are in
+// registers: x_j = d'_j - c_j p_j x_{j+1}; the weighted outputs of the lane's
+// P poles are added in pole order, then summed over the wave.
+template <typename T, int S, int C, int P>
+__device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln, const RowRec* rc, int j0, int Lm,
+                                             int base, int pw, int lane, const Cx<T> (*ps)[S],
+                                             const Cx<T> (*ds)[S], Cx<T>* vnext, double2* red) {
     static_for<0, S / 4>([&](auto G) {
         constexpr int g = S / 4 - 1 - decltype(G)::value;
         static_for<0, 4>([&](auto Qi) {
@@ -179,90 +271,248 @@ __device__ __forceinline__ void solve_segment(const SolveArgs& A, const Lane& ln
             constexpr int jj = 4 * g + q;
             constexpr bool DELTA = ((jj + C) & 1) == 0;
             const int j = j0 + jj;
-            Cx<T> v{T(0), T(0)};
-            if (j < Lm) {
-                v.x = ds[jj].x - fmaT(cs[jj].x, vnext.x, -(cs[jj].y * vnext.y));
-                v.y = ds[jj].y - fmaT(cs[jj].x, vnext.y, cs[jj].y * vnext.x);
-                vnext = v;
-            }
-            const double vx = static_cast<double>(v.x), vy = static_cast<double>(v.y);
-            red[q * WAVE + lane] = make_double2(__builtin_fma(ln.p.wr, vx, -(ln.p.wi * vy)),
-                                                __builtin_fma(ln.p.wr, vy, ln.p.wi * vx));
-            if constexpr (DELTA) {
-                double hx = 0.0, hy = 0.0;
-                if (j < Lm) {
-                    const double2 rh = uh[j];
-                    const double tx = __builtin_fma(-A.dtH, vx, rh.x);
-                    const double ty = __builtin_fma(-A.dtH, vy, rh.y);
-                    hx = __builtin_fma(ln.wzr, tx, -(ln.wzi * ty));
-                    hy = __builtin_fma(ln.wzr, ty, ln.wzi * tx);
+            const bool live = j < Lm;
+            double sx = 0.0, sy = 0.0, hx = 0.0, hy = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                Cx<T> v{T(0), T(0)};
+                if (live) {
+                    const T tc = coupling_c<T>(rc[j]);
+                    const Cx<T> cpj{tc * ps[k][jj].x, tc * ps[k][jj].y};
+                    v.x = ds[k][jj].x - fmaT(cpj.x, vnext[k].x, -(cpj.y * vnext[k].y));
+                    v.y = ds[k][jj].y - fmaT(cpj.x, vnext[k].y, cpj.y * vnext[k].x);
+                    vnext[k] = v;
                 }
-                red[(4 + (q >> 1)) * WAVE + lane] = make_double2(hx, hy);
+                const double vx = static_cast<double>(v.x), vy = static_cast<double>(v.y);
+                const double ox = __builtin_fma(ln[k].p.wr, vx, -(ln[k].p.wi * vy));
+                const double oy = __builtin_fma(ln[k].p.wr, vy, ln[k].p.wi * vx);
+                sx = k ? sx + ox : ox;
+                sy = k ? sy + oy : oy;
+                if constexpr (DELTA) {
+                    if (live) {
+                        const double tx = __builtin_fma(-A.dtH, vx, rc[j].hx);
+                        const double ty = __builtin_fma(-A.dtH, vy, rc[j].hy);
+                        const double gx = __builtin_fma(ln[k].wzr, tx, -(ln[k].wzi * ty));
+                        const double gy = __builtin_fma(ln[k].wzr, ty, ln[k].wzi * tx);
+                        hx = k ? hx + gx : gx;
+                        hy = k ? hy + gy : gy;
+                    }
+                }
             }
+            red[q * WAVE + lane] = make_double2(sx, sy);
+            if constexpr (DELTA) red[(4 + (q >> 1)) * WAVE + lane] = make_double2(hx, hy);
         });
-        reduce_group<C>(A, red, lane, pb, base, j0 + 4 * g, Lm);
+        reduce_group<C>(A, red, lane, pw, base, j0 + 4 * g, Lm);
     });
 }
 
-template <typename T, int S, int C>
-__device__ __forceinline__ void solve_chain(const SolveArgs& A, int m, int pb, unsigned char* smem) {
-    const int lane = threadIdx.x;
-    const int n = pb * WAVE + lane;
-    Lane ln;
-    ln.p = A.poles[n < A.N ? n : 0];
-    if (n >= A.N) ln.p.wr = ln.p.wi = 0.0;   // padding lanes add nothing
-    ln.wzr = __builtin_fma(ln.p.wr, ln.p.zir, -(ln.p.wi * ln.p.zii));
-    ln.wzi = __builtin_fma(ln.p.wr, ln.p.zii, ln.p.wi * ln.p.zir);
+// Schedules of the two sweeps.  FUSED: both sweeps compute the pivots (the
+// forward sweep keeps c' and d' at segment starts; the backward pass recomputes
+// each segment from them).  STREAM: both sweeps read the pivots of the cached
+// factorization.  HYBRID: the forward sweep reads them and keeps c' = c p at
+// segment starts; the backward pass recomputes each segment's pivots.
+enum Sched { FUSED = 0, STREAM = 1, HYBRID = 2 };
 
+template <int SCHED>
+constexpr int ckpt_words() { return SCHED == STREAM ? 1 : 2; }
+
+// One wave solves one chain for 64 P poles: lane l carries poles 64 P pw + 64 k + l,
+// k < P, whose sweeps share every row record and are interleaved row by row.
+template <typename T, int S, int C, int SCHED, int P>
+__device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m, int pb, unsigned char* smem) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    const int pw = pb * nw + wv;                 // pole wave: poles 64 P pw .. 64 P (pw + 1) - 1
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
-    const ModeCoef* cf = A.coef + base;
-    const double2* uh = A.U0 + base;
-    const double2* uz = uh + A.modes;
-    const double2* ud = uz + A.modes;
     const int nseg = (Lm + S - 1) / S;
+    constexpr int CKW = ckpt_words<SCHED>();
 
-    Cx<T>* ck = reinterpret_cast<Cx<T>*>(smem);             // [nseg - 2][2][64]
-    const int nck = nseg > 2 ? nseg - 2 : 0;
-    double2* red = reinterpret_cast<double2*>(smem + sizeof(Cx<T>) * 2 * WAVE * nck);
+    // the chain's row records, shared by all waves of the block
+    RowRec* rc = reinterpret_cast<RowRec*>(smem);
+    {
+        const double4* src = reinterpret_cast<const double4*>(A.rec + 2 * base + C * Lm);
+        double4* dst = reinterpret_cast<double4*>(rc);
+        const int nq = Lm * static_cast<int>(sizeof(RowRec) / sizeof(double4));
+        for (int i = threadIdx.x; i < nq; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    // whole waves of padding poles have nothing to do
+    if (pw * WAVE * P >= A.N) return;
 
-    Cx<T> cp{T(0), T(0)}, dp{T(0), T(0)};
+    Lane ln[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int n = (pw * P + k) * WAVE + lane;
+        ln[k].p = A.poles[n < A.N ? n : 0];
+        if (n >= A.N) ln[k].p.wr = ln[k].p.wi = 0.0;   // padding lanes add nothing
+        ln[k].wzr = __builtin_fma(ln[k].p.wr, ln[k].p.zir, -(ln[k].p.wi * ln[k].p.zii));
+        ln[k].wzi = __builtin_fma(ln[k].p.wr, ln[k].p.zii, ln[k].p.wi * ln[k].p.zir);
+        ln[k].zrf = static_cast<float>(ln[k].p.zr);
+        ln[k].zif = static_cast<float>(ln[k].p.zi);
+    }
+
+    double2* red = reinterpret_cast<double2*>(smem + static_cast<size_t>(A.rec_bytes) +
+                                              static_cast<size_t>(wv) * sizeof(double2) * 6 * WAVE);
+    // segment-start states of this wave: [nck_max][CKW][P][64]
+    Cx<T>* ck = reinterpret_cast<Cx<T>*>(A.ckpt) +
+                (static_cast<size_t>(task) * A.npb * nw + pw) * A.nck_max * CKW * P * WAVE + lane;
+    // cached pivots of this chain: row j, pole n at fact[(row0 + j) npad + n]
+    const Cx<T>* fact = reinterpret_cast<const Cx<T>*>(A.fact) + static_cast<size_t>(2 * base + C * Lm) * A.npad +
+                        pw * P * WAVE + lane;
+
+    Cx<T> cp[P], dp[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) cp[k] = dp[k] = Cx<T>{T(0), T(0)};
+    Cx<T> ps[P][S], ds[P][S];
+    // forward sweep over the full segments, keeping the state entering each later one
     for (int seg = 0; seg < nseg - 1; ++seg) {
         if (seg > 0) {
-            ck[(2 * (seg - 1)) * WAVE + lane] = cp;
-            ck[(2 * (seg - 1) + 1) * WAVE + lane] = dp;
+            Cx<T>* c0 = ck + static_cast<size_t>((seg - 1) * CKW) * P * WAVE;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                c0[k * WAVE] = dp[k];
+                if constexpr (CKW == 2) c0[(P + k) * WAVE] = cp[k];
+            }
         }
-        const int j0 = seg * S;
+        const RowRec* rs = rc + seg * S;
+        if constexpr (SCHED == FUSED) {
+            static_for<0, S>([&](auto Q) {
+                constexpr int jj = decltype(Q)::value;
+                constexpr bool DELTA = ((jj + C) & 1) == 0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const Cx<T> p = pivot_row<T, DELTA>(rs[jj], ln[k], cp[k]);
+                    forward_rhs<T, DELTA>(rs[jj], ln[k], p, dp[k]);
+                }
+            });
+        } else {
+            const Cx<T>* fseg = fact + static_cast<size_t>(seg * S) * A.npad;
+            static_for<0, S>([&](auto Q) {
+                constexpr int jj = decltype(Q)::value;
+#pragma unroll
+                for (int k = 0; k < P; ++k) ps[k][jj] = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
+            });
+            static_for<0, S>([&](auto Q) {
+                constexpr int jj = decltype(Q)::value;
+                constexpr bool DELTA = ((jj + C) & 1) == 0;
+#pragma unroll
+                for (int k = 0; k < P; ++k) forward_rhs<T, DELTA>(rs[jj], ln[k], ps[k][jj], dp[k]);
+            });
+            if constexpr (SCHED == HYBRID) {
+                const T tc = coupling_c<T>(rs[S - 1]);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    cp[k].x = tc * ps[k][S - 1].x;
+                    cp[k].y = tc * ps[k][S - 1].y;
+                }
+            }
+        }
+    }
+    // the last segment is swept into registers and back-substituted at once
+    Cx<T> vnext[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) vnext[k] = Cx<T>{T(0), T(0)};
+    {
+        const int j0 = (nseg - 1) * S;
+        const Cx<T>* fseg = fact + static_cast<size_t>(j0) * A.npad;
         static_for<0, S>([&](auto Q) {
             constexpr int jj = decltype(Q)::value;
             constexpr bool DELTA = ((jj + C) & 1) == 0;
-            forward_row<T, DELTA>(A, ln, cf, uh, uz, ud, j0 + jj, cp, dp);
+            if (j0 + jj < Lm) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    if constexpr (SCHED == STREAM)
+                        ps[k][jj] = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
+                    else
+                        ps[k][jj] = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], cp[k]);
+                    forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], dp[k]);
+                    ds[k][jj] = dp[k];
+                }
+            }
         });
+        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, red);
     }
-    Cx<T> vnext{T(0), T(0)};
-    solve_segment<T, S, C>(A, ln, cf, uh, uz, ud, nseg - 1, Lm, base, pb, lane, cp, dp, vnext, red);
+    // earlier segments: rebuild pivots and d' from the checkpoint, then back-substitute
     for (int seg = nseg - 2; seg >= 0; --seg) {
-        if (seg > 0) {
-            cp = ck[(2 * (seg - 1)) * WAVE + lane];
-            dp = ck[(2 * (seg - 1) + 1) * WAVE + lane];
-        } else {
-            cp = Cx<T>{T(0), T(0)};
-            dp = Cx<T>{T(0), T(0)};
+        const int j0 = seg * S;
+        Cx<T> d[P], c[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            d[k] = c[k] = Cx<T>{T(0), T(0)};
+            if (seg > 0) {
+                const Cx<T>* c0 = ck + static_cast<size_t>((seg - 1) * CKW) * P * WAVE;
+                d[k] = c0[k * WAVE];
+                if constexpr (CKW == 2) c[k] = c0[(P + k) * WAVE];
+            }
         }
-        solve_segment<T, S, C>(A, ln, cf, uh, uz, ud, seg, Lm, base, pb, lane, cp, dp, vnext, red);
+        if constexpr (SCHED == STREAM) {
+            const Cx<T>* fseg = fact + static_cast<size_t>(j0) * A.npad;
+            static_for<0, S>([&](auto Q) {
+                constexpr int jj = decltype(Q)::value;
+#pragma unroll
+                for (int k = 0; k < P; ++k) ps[k][jj] = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
+            });
+        }
+        static_for<0, S>([&](auto Q) {
+            constexpr int jj = decltype(Q)::value;
+            constexpr bool DELTA = ((jj + C) & 1) == 0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                if constexpr (SCHED != STREAM) ps[k][jj] = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], c[k]);
+                forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], d[k]);
+                ds[k][jj] = d[k];
+            }
+        });
+        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, red);
     }
 }
 
-template <typename T, int S>
-__global__ __launch_bounds__(WAVE) void rexi_chain_kernel(SolveArgs A) {
+// Waves per SIMD the register allocation must allow: two where the segment
+// registers (pivot and d' of S rows for P poles) take at most 128 VGPRs.
+template <typename T, int S, int P>
+constexpr int chain_occupancy() { return sizeof(T) * S * P <= 128 ? 2 : 1; }
+
+template <typename T, int S, int SCHED, int P>
+__global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(chain_occupancy<T, S, P>())))
+void rexi_chain_kernel(SolveArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int task = blockIdx.x / A.npb;      // task = 2 m + chain: longest chains first
     const int pb = blockIdx.x - task * A.npb;
     const int m = task >> 1;
     if (task & 1)
-        solve_chain<T, S, 1>(A, m, pb, smem);
+        solve_chain<T, S, 1, SCHED, P>(A, task, m, pb, smem);
     else
-        solve_chain<T, S, 0>(A, m, pb, smem);
+        solve_chain<T, S, 0, SCHED, P>(A, task, m, pb, smem);
+}
+
+// Factorization: the pivots of every chain row for every pole (padding lanes up
+// to npad use pole 0), stored at fact[(chain row) npad + pole].  One thread per
+// pole, one workgroup per (task, block of poles); depends on z, dt and the
+// operator only, so it is reused while they stay the same.
+template <typename T>
+__global__ __launch_bounds__(256) void rexi_factor_kernel(const RowRec* __restrict__ rec,
+                                                          const PoleData* __restrict__ poles, Cx<T>* __restrict__ fact,
+                                                          int L, int N, int npad, int fpb) {
+    const int task = blockIdx.x / fpb;
+    const int n = (blockIdx.x - task * fpb) * blockDim.x + threadIdx.x;
+    if (n >= npad) return;
+    const int m = task >> 1, C = task & 1;
+    const int Lm = L - m + 1;
+    const int base = m * (2 * L + 3 - m) / 2;
+    Lane ln;
+    ln.p = poles[n < N ? n : 0];
+    ln.zrf = static_cast<float>(ln.p.zr);
+    ln.zif = static_cast<float>(ln.p.zi);
+    const RowRec* rc = rec + 2 * base + C * Lm;
+    Cx<T>* out = fact + static_cast<size_t>(2 * base + C * Lm) * npad + n;
+    Cx<T> cp{T(0), T(0)};
+    for (int j = 0; j < Lm; ++j) {
+        const RowRec R = rc[j];
+        const Cx<T> p = ((j + C) & 1) == 0 ? pivot_row<T, true>(R, ln, cp) : pivot_row<T, false>(R, ln, cp);
+        out[static_cast<size_t>(j) * npad] = p;
+    }
 }
 
 // U1[i] = sum over pole blocks of part[pb][i], in block order, compensated.
@@ -283,44 +533,128 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __rest
     U1[i] = make_double2(sx + cx, sy + cy);
 }
 
-template <typename T, int S>
-size_t lds_bytes(int L) {
-    const int nseg = (L + 1 + S - 1) / S;
-    const int nck = nseg > 2 ? nseg - 2 : 0;
-    return sizeof(Cx<T>) * 2 * WAVE * nck + sizeof(double2) * RED_SLOTS * WAVE;
+template <typename T>
+int ensure_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
+    const int tprec = std::is_same<T, float>::value ? 1 : 2;
+    if (ctx->fact_valid && ctx->fact_prec == tprec) return REXI_OK;
+    const size_t bytes = sizeof(Cx<T>) * 2 * static_cast<size_t>(A.modes) * A.npad;
+    if (bytes > ctx->fact_cap) {
+        if (ctx->d_fact) REXI_HIP(hipFree(ctx->d_fact));
+        ctx->d_fact = nullptr;
+        ctx->fact_cap = 0;
+        if (hipMalloc(&ctx->d_fact, bytes) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi solve: cannot allocate the factorization cache");
+        ctx->fact_cap = bytes;
+    }
+    const int threads = 256;
+    const int fpb = (A.npad + threads - 1) / threads;
+    const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * fpb);
+    const int slot = prof_begin(ctx, REXI_KERNEL_FACTOR, stream);
+    hipLaunchKernelGGL((rexi_factor_kernel<T>), dim3(blocks), dim3(threads), 0, stream, A.rec, A.poles,
+                       reinterpret_cast<Cx<T>*>(ctx->d_fact), A.L, A.N, A.npad, fpb);
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_FACTOR, slot, stream);
+    ctx->fact_valid = true;
+    ctx->fact_prec = tprec;
+    return REXI_OK;
 }
 
-template <typename T, int S>
-int launch_typed(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
-    const size_t lds = lds_bytes<T, S>(A.L);
-    if (lds > 64 * 1024) return fail(REXI_ENOTSUP, "rexi solve: segment checkpoints exceed LDS; raise seg_rows");
+template <typename T, int S, int SCHED, int P>
+int launch_typed(swe_ctx* ctx, SolveArgs A, int waves, hipStream_t stream) {
+    const int nseg = (A.L + 1 + S - 1) / S;
+    A.nck_max = nseg > 2 ? nseg - 2 : 0;
+    A.rec_bytes = static_cast<int>(sizeof(RowRec)) * (A.L + 1);
+    A.npb = (A.N + WAVE * P * waves - 1) / (WAVE * P * waves);
+    constexpr int CKW = ckpt_words<SCHED>();
+    if (SCHED != FUSED) {
+        const int rc = ensure_factors<T>(ctx, A, stream);
+        if (rc != REXI_OK) return rc;
+        A.fact = ctx->d_fact;
+    }
+    // segment-start states: one slot per (task, pole wave, checkpoint)
+    const size_t ck_bytes = sizeof(Cx<T>) * 2 * static_cast<size_t>(A.L + 1) * A.npb * waves *
+                            static_cast<size_t>(A.nck_max > 0 ? A.nck_max : 1) * CKW * P * WAVE;
+    if (ck_bytes > ctx->ckpt_cap) {
+        if (ctx->d_ckpt) REXI_HIP(hipFree(ctx->d_ckpt));
+        ctx->d_ckpt = nullptr;
+        ctx->ckpt_cap = 0;
+        if (hipMalloc(&ctx->d_ckpt, ck_bytes) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi solve: cannot allocate the checkpoint workspace");
+        ctx->ckpt_cap = ck_bytes;
+    }
+    A.ckpt = ctx->d_ckpt;
+    const size_t lds = static_cast<size_t>(A.rec_bytes) + sizeof(double2) * 6 * WAVE * waves;
+    if (lds > 160 * 1024) return fail(REXI_ENOTSUP, "rexi solve: LDS need exceeds 160 KB; lower waves");
+    if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&rexi_chain_kernel<T, S, SCHED, P>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(REXI_ENOTSUP, "rexi solve: LDS need exceeds the device limit; lower waves");
+        }
+    }
     const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * A.npb);
     const int slot = prof_begin(ctx, REXI_KERNEL_SOLVE, stream);
-    hipLaunchKernelGGL((rexi_chain_kernel<T, S>), dim3(blocks), dim3(WAVE), lds, stream, A);
+    hipLaunchKernelGGL((rexi_chain_kernel<T, S, SCHED, P>), dim3(blocks), dim3(WAVE * waves), lds, stream, A);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_SOLVE, slot, stream);
     return REXI_OK;
 }
 
+template <typename T, int S, int P>
+int launch_sched(swe_ctx* ctx, const SolveArgs& A, int waves, int sched, hipStream_t stream) {
+    switch (sched) {
+        case REXI_SOLVER_STREAM: return launch_typed<T, S, STREAM, P>(ctx, A, waves, stream);
+        case REXI_SOLVER_HYBRID: return launch_typed<T, S, HYBRID, P>(ctx, A, waves, stream);
+        default: return launch_typed<T, S, FUSED, P>(ctx, A, waves, stream);
+    }
+}
+
+// Supported shapes: one pole per lane with 16- or 32-row segments, two poles
+// per lane with 8- or 16-row segments (the segment registers of 32 rows for two
+// poles would not fit).
+template <typename T>
+int launch_shape(swe_ctx* ctx, const SolveArgs& A, const Tuning& t, hipStream_t stream) {
+    if (t.poles_per_lane == 2) {
+        if (t.seg_rows == 8) return launch_sched<T, 8, 2>(ctx, A, t.waves, t.solver, stream);
+        if (t.seg_rows == 16) return launch_sched<T, 16, 2>(ctx, A, t.waves, t.solver, stream);
+    } else {
+        if (t.seg_rows == 16) return launch_sched<T, 16, 1>(ctx, A, t.waves, t.solver, stream);
+        if (t.seg_rows == 32) return launch_sched<T, 32, 1>(ctx, A, t.waves, t.solver, stream);
+    }
+    return fail(REXI_ENOTSUP, "rexi solve: seg_rows must be 16 or 32 with one pole per lane, 8 or 16 with two");
+}
+
 }  // namespace
 
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx->d_rows) {
+        if (hipMalloc(&ctx->d_rows, sizeof(RowRec) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi solve: cannot allocate row records");
+    }
+    {
+        const int threads = 256;
+        const unsigned blocks = static_cast<unsigned>((ctx->modes + threads - 1) / threads);
+        hipLaunchKernelGGL(rexi_rows_kernel, dim3(blocks), dim3(threads), 0, stream,
+                           reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
+                           ctx->L, ctx->modes, dt, ctx->H);
+        REXI_HIP(hipGetLastError());
+    }
     SolveArgs A;
-    A.U0 = reinterpret_cast<const double2*>(U0);
+    A.rec = reinterpret_cast<const RowRec*>(ctx->d_rows);
     A.poles = ctx->d_poles;
-    A.coef = ctx->d_coef;
     A.L = ctx->L;
     A.modes = ctx->modes;
     A.N = N;
-    A.npb = (N + WAVE - 1) / WAVE;
-    A.dt = dt;
+    // the factorization layout pads the pole axis to whole pairs of waves for every launch shape
+    A.npad = (N + 2 * WAVE - 1) / (2 * WAVE) * (2 * WAVE);
+    const int P = ctx->tune.poles_per_lane;
+    const int nparts = (N + WAVE * P - 1) / (WAVE * P);       // pole waves that produce partial sums
     A.dtH = dt * ctx->H;
-    A.dt2H = dt * dt * ctx->H;
     const size_t count = static_cast<size_t>(3) * ctx->modes;
-    if (A.npb == 1) {
+    if (nparts == 1) {
         A.out = reinterpret_cast<double2*>(U1);
     } else {
-        const size_t need = 2 * count * A.npb;
+        const size_t need = 2 * count * nparts;
         if (need > ctx->partial_cap) {
             if (ctx->d_partial) REXI_HIP(hipFree(ctx->d_partial));
             ctx->d_partial = nullptr;
@@ -332,20 +666,17 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
         A.out = reinterpret_cast<double2*>(ctx->d_partial);
     }
     const bool fp32 = (ctx->prec & REXI_PREC_FP32_SOLVE) != 0;
-    int rc;
-    switch (ctx->tune.seg_rows) {
-        case 8: rc = fp32 ? launch_typed<float, 8>(ctx, A, stream) : launch_typed<double, 8>(ctx, A, stream); break;
-        case 32: rc = fp32 ? launch_typed<float, 32>(ctx, A, stream) : launch_typed<double, 32>(ctx, A, stream); break;
-        default: rc = fp32 ? launch_typed<float, 16>(ctx, A, stream) : launch_typed<double, 16>(ctx, A, stream); break;
-    }
+    A.fact = nullptr;
+    A.ckpt = nullptr;
+    const int rc = fp32 ? launch_shape<float>(ctx, A, ctx->tune, stream) : launch_shape<double>(ctx, A, ctx->tune, stream);
     if (rc != REXI_OK) return rc;
-    if (A.npb > 1) {
+    if (nparts > 1) {
         const int threads = 256;
         const unsigned blocks = static_cast<unsigned>((count + threads - 1) / threads);
         const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
         hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks), dim3(threads), 0, stream,
                            reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1),
-                           static_cast<int>(count), A.npb);
+                           static_cast<int>(count), nparts);
         REXI_HIP(hipGetLastError());
         prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
     }

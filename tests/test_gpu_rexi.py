@@ -32,11 +32,11 @@ def _kappa_max(alpha, beta, rho):
     return float(orexi.kappa(alpha, beta, 1j * w).max())
 
 
-def _run_gpu(L, alpha, beta, dt, U0, prec=0, seg_rows=0):
+def _run_gpu(L, alpha, beta, dt, U0, prec=0, seg_rows=0, solver=0, waves=0, poles_per_lane=0):
     api = _api()
     ctx = api.SWE(L, prec=prec)
-    if seg_rows:
-        ctx.set_tuning(seg_rows=seg_rows)
+    if seg_rows or solver or waves or poles_per_lane:
+        ctx.set_tuning(solver=solver, seg_rows=seg_rows, waves=waves, poles_per_lane=poles_per_lane)
     d0 = torch.from_numpy(U0).cuda()
     d1 = torch.empty_like(d0)
     ctx.rexi_linear_step(alpha, beta, dt, d0, d1)
@@ -60,8 +60,8 @@ CASES = [
     # name, L, N, dt, p0, y, seg_rows
     ("T31-paper-contour", 31, 128, 3600.0, 10.0, 30.0, 16),
     ("ragged-rows-and-poles", 20, 70, 3600.0, 8.0, 12.0, 16),
-    ("checkpointed-segments", 45, 96, 3600.0, 8.0, 16.0, 8),
-    ("smallest", 1, 4, 600.0, 1.0, 2.0, 8),
+    ("checkpointed-segments", 45, 96, 3600.0, 8.0, 16.0, 16),
+    ("smallest", 1, 4, 600.0, 1.0, 2.0, 16),
     ("single-pole-block-long-chain", 70, 64, 1800.0, 6.0, 9.0, 16),
 ]
 
@@ -90,33 +90,79 @@ def test_fp32_solve_parity_t31():
     _assert_close(got, ref, tol)
 
 
-def test_segment_length_does_not_change_bits():
-    """Re-sweeping a segment from its checkpoint repeats the same operations in
-    the same order, and the pole sum is grouped the same way, so every segment
-    length gives bit-identical results; repeated calls are bit-identical too."""
+@pytest.mark.parametrize("prec", [0, 1])
+def test_schedule_and_shape_do_not_change_bits(prec):
+    """Every schedule (pivots recomputed, streamed from the cached factorization,
+    or both), segment length and workgroup size performs the same operations in
+    the same order on each (pole, row), and the pole sum is grouped the same
+    way, so all give bit-identical results; repeated calls are bit-identical."""
+    api = _api()
     L, N, dt = 57, 200, 3600.0
     alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, N, 8.0, 16.0)
     U0 = random_state(L, 8)
-    outs = [_run_gpu(L, alpha, beta, dt, U0, seg_rows=S) for S in (8, 16, 32, 16)]
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+    refs = []
+    for P in (1, 2):
+        ref = _run_gpu(L, alpha, beta, dt, U0, prec=prec, solver=api.SOLVER_FUSED, seg_rows=16, waves=1,
+                       poles_per_lane=P)
+        for solver in (api.SOLVER_FUSED, api.SOLVER_STREAM, api.SOLVER_HYBRID):
+            for S in ((16, 32) if P == 1 else (8, 16)):
+                for W in (1, 2, 4):
+                    got = _run_gpu(L, alpha, beta, dt, U0, prec=prec, solver=solver, seg_rows=S, waves=W,
+                                   poles_per_lane=P)
+                    assert np.array_equal(got, ref), (P, solver, S, W)
+        refs.append(ref)
+    # interleaving two poles per lane only regroups the FP64 pole sum
+    scale = np.abs(refs[0]).max(axis=1, keepdims=True)
+    assert np.all(np.abs(refs[1] - refs[0]) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("solver", [2, 3])
+def test_factor_cache_follows_coefficients(solver):
+    """The cached factorization is reused while (alpha, beta, N, dt) stay the
+    same and rebuilt when any of them or the precision changes."""
+    api = _api()
+    L = 40
+    p = Params()
+    a1, b1, _, _ = orexi.coefficients(orexi.FN_EXP, 96, 8.0, 16.0)
+    a2, b2, _, _ = orexi.coefficients(orexi.FN_EXP, 128, 9.0, 20.0)
+    U0 = random_state(L, 11)
+    calls = [(a1, b1, 3600.0), (a1, b1, 3600.0), (a2, b2, 3600.0), (a2, b2, 1800.0), (a1, b1, 3600.0)]
+    ctx = api.SWE(L)
+    ctx.set_tuning(solver=solver)
+    d0 = torch.from_numpy(U0).cuda()
+    d1 = torch.empty_like(d0)
+    for a, b, dt in calls:
+        ctx.rexi_linear_step(a, b, dt, d0, d1)
+        got = d1.cpu().numpy()
+        fresh = _run_gpu(L, a, b, dt, U0, solver=api.SOLVER_FUSED)
+        assert np.array_equal(got, fresh)
+    ref = olinear.rexi_linear_step(U0, a1, b1, 3600.0, L, p)
+    tol = max(1e-12, 4 * U64 * _kappa_max(a1, b1, spectral_radius_bound(L, 3600.0, p)))
+    _assert_close(got, ref, tol)
+    ctx.close()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_t255_sampled_orders(prec):
-    """Full T255 / N = 800 in the launch shape the benchmark uses, checked on a
-    sample of zonal orders the oracle solves one by one."""
+    """Full T255 / N = 800 in the launch shape the benchmark uses (each
+    schedule), checked on a sample of zonal orders the oracle solves one by one."""
     from paper_1805_06557_amd import configs
+    api = _api()
     w = configs.T255_FP32 if prec else configs.T255_FP64
     p = Params()
     alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, w.N, w.p0, w.y)
     U0 = random_state(w.L, 2)
     orders = [0, 1, 2, 97, 200, 254, 255]
     ref = olinear.rexi_linear_step(U0, alpha, beta, w.dt, w.L, p, orders=orders)
-    got = _run_gpu(w.L, alpha, beta, w.dt, U0, prec=prec)
     kap = _kappa_max(alpha, beta, spectral_radius_bound(w.L, w.dt, p))
     tol = max(1e-12, 4 * U64 * kap) if prec == 0 else 16 * U32 * kap
-    _assert_close(got, ref, tol, orders=orders, L=w.L)
+    outs = []
+    for solver in (0, api.SOLVER_FUSED, api.SOLVER_STREAM, api.SOLVER_HYBRID):
+        got = _run_gpu(w.L, alpha, beta, w.dt, U0, prec=prec, solver=solver)
+        _assert_close(got, ref, tol, orders=orders, L=w.L)
+        outs.append(got)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
 
 
 def test_contour_not_enclosing_spectrum_is_rejected():
