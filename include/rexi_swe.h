@@ -123,6 +123,34 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta,
                      hipStream_t stream);
 
 /*
+ * rexi_linear_step_batched -- the REXI linear stage (Section 4.2, Eq. rexi)
+ * of an ensemble of independent problems, each with its own context (own
+ * truncation), coefficients, pole count and dt, in one row-record launch, one
+ * fused chain-solve launch over the work items of every member (longest
+ * chains first) and one pole-sum launch.  Per member the result is bit for
+ * bit that of rexi_linear_step with the launch shape of members[0].ctx (which
+ * is the shape used for all).  All members need distinct contexts on one
+ * device with the same solve precision.  The argument and work-item tables
+ * are cached in members[0].ctx and re-uploaded only when a member's pointers,
+ * N, dt, coefficients or the launch shape change; with nothing changed the
+ * call only enqueues kernels, so it can be captured into a HIP graph after
+ * one eager call.
+ * Errors: REXI_EINVAL (count outside [1, 4096], NULL pointers, a context used
+ * twice, mixed device or precision, bad N or dt, overlapping U0/U1),
+ * REXI_ENUMERIC, REXI_ENOMEM, REXI_ENOTSUP, REXI_EDEVICE.
+ */
+typedef struct {
+    swe_ctx* ctx;
+    const double* alpha;   /* host, 2N doubles */
+    const double* beta;    /* host, 2N doubles */
+    int N;
+    double dt;
+    const double* U0;      /* device [3][modes(ctx)] complex128 */
+    double* U1;            /* device [3][modes(ctx)] complex128 */
+} rexi_member;
+int rexi_linear_step_batched(const rexi_member* members, int count, hipStream_t stream);
+
+/*
  * sh_synthesis -- spectral to grid for nf scalar fields (Section 3.2):
  *   f(lambda_k, mu_j) = sum_l Pbar_l0 Re f_l0 + 2 Re sum_{m>=1} sum_l f_lm Pbar_lm(mu_j) e^{i m lambda_k}.
  * spec: device complex128 [nf][modes]; grid: device float64 [nf][nlat][nlon].
@@ -218,6 +246,23 @@ enum { REXI_SOLVER_FUSED = 1, REXI_SOLVER_STREAM = 2, REXI_SOLVER_HYBRID = 3 };
  * Errors: REXI_EINVAL for an unsupported value.
  */
 int swe_set_tuning(swe_ctx* ctx, int solver, int seg_rows, int waves, int poles_per_lane);
+
+/* swe_get_tuning -- the current schedule and launch shape (see swe_set_tuning).
+ * Errors: REXI_EINVAL for NULL arguments. */
+int swe_get_tuning(swe_ctx* ctx, int* solver, int* seg_rows, int* waves, int* poles_per_lane);
+
+/*
+ * swe_autotune -- times every supported schedule and launch shape of the REXI
+ * stage on this problem (reps timed calls each, after one untimed call that
+ * also builds a factorization where the schedule needs one) with HIP events
+ * on `stream`, and keeps the fastest in the context.  U1 is overwritten with
+ * the REXI stage of U0.  *best_ms (may be NULL) receives the mean time of one
+ * stage with the chosen shape.  If the fused schedule wins, the cached
+ * factorization is released.  Synchronizes the stream.
+ * Errors: as rexi_linear_step, REXI_EINVAL for reps outside [1, 1000].
+ */
+int swe_autotune(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                 const double* U0, double* U1, int reps, hipStream_t stream, double* best_ms);
 
 #ifdef __cplusplus
 }

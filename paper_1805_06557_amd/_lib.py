@@ -10,6 +10,14 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librexi_swe
 
 _c_int, _c_double, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class RexiMember(ctypes.Structure):
+    """rexi_member of include/rexi_swe.h."""
+    _fields_ = [("ctx", _vp), ("alpha", _dp), ("beta", _dp), ("N", _c_int), ("dt", _c_double),
+                ("U0", _vp), ("U1", _vp)]
+
 
 # name -> (restype, argtypes); the stream argument is a hipStream_t (void*).
 SIGNATURES = {
@@ -25,6 +33,9 @@ SIGNATURES = {
     "swe_sync": (_c_int, [_vp]),
     "rexi_last_error": (ctypes.c_char_p, []),
     "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
+    "swe_get_tuning": (_c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "swe_autotune": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _c_int, _vp, _dp]),
+    "rexi_linear_step_batched": (_c_int, [ctypes.POINTER(RexiMember), _c_int, _vp]),
     "swe_profile": (_c_int, [_vp, _c_int]),
     "swe_profile_read": (_c_int, [_vp, _c_int, _dp, ctypes.POINTER(_c_int)]),
 }

@@ -112,6 +112,22 @@ class SWE:
         """Schedule (SOLVER_*) and launch shape of the REXI solve; 0 keeps a value."""
         _check(self._lib.swe_set_tuning(self._h, solver, seg_rows, waves, poles_per_lane), "swe_set_tuning")
 
+    def get_tuning(self) -> dict:
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(self._lib.swe_get_tuning(self._h, *[ctypes.byref(x) for x in v]), "swe_get_tuning")
+        return dict(zip(("solver", "seg_rows", "waves", "poles_per_lane"), (x.value for x in v)))
+
+    def autotune(self, alpha, beta, dt: float, U0, U1, reps: int = 3, stream=None) -> float:
+        """Times every schedule and launch shape on this problem, keeps the fastest;
+        returns the mean milliseconds of one REXI stage with it."""
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        ms = ctypes.c_double()
+        _check(self._lib.swe_autotune(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt),
+                                      _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"), int(reps),
+                                      _stream_handle(stream), ctypes.byref(ms)), "swe_autotune")
+        return ms.value
+
     def rexi_linear_step(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
         a = _host_coeffs(alpha)
         b = _host_coeffs(beta)
@@ -157,3 +173,19 @@ class SWE:
 
     def sync(self) -> None:
         _check(self._lib.swe_sync(self._h), "swe_sync")
+
+
+def rexi_linear_step_batched(members, stream=None) -> None:
+    """members: sequence of (SWE, alpha, beta, dt, U0, U1); one ensemble REXI stage."""
+    lib = _lib.load()
+    arr = (_lib.RexiMember * len(members))()
+    keep = []
+    for i, (ctx, alpha, beta, dt, U0, U1) in enumerate(members):
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        if b.size != a.size:
+            raise ValueError("alpha and beta differ in length")
+        keep += [a, b]
+        arr[i] = _lib.RexiMember(ctx.handle, _dptr(a), _dptr(b), a.size // 2, float(dt),
+                                 _state_ptr(U0, ctx.L, 3, "U0"), _state_ptr(U1, ctx.L, 3, "U1"))
+    _check(lib.rexi_linear_step_batched(arr, len(members), _stream_handle(stream)), "rexi_linear_step_batched")

@@ -55,3 +55,43 @@ T511_FP64 = Workload(
     desc="linear+nonlinear SWE, T511 on 1536x768, dt = 7200 s, N = 2000, FP64")
 
 ALL = {w.name: w for w in [T31_LINEAR, T127_NONLINEAR, T255_FP64, T255_FP32, T511_FP64]}
+
+
+# FP32 against FP64 solves at one fixed accuracy: the T255 REXI stage
+# (dt = 3600 s) at a target scalar error E = 1e-4 on |w| <= rho.  Each
+# precision gets its own contour, the fewest poles whose predicted error
+# (approximation error + unit roundoff x kappa) meets E over the p0 grid of
+# contour.choose: FP32 needs a small shift (its rounding floor u_32 kappa grows
+# like e^{p0}) and therefore many poles, FP64 reaches E with a large shift and
+# few poles.
+EQUAL_ERROR_E = 1e-4
+T255_FP32_AT_E = Workload(
+    "T255-fp32-at-E", L=255, nlat=0, nlon=0, dt=3600.0, N=776, p0=8.0, y=67.91071976436587, prec=1, seed=2,
+    desc="REXI stage T255, dt = 3600 s, FP32 solves, contour chosen for E = 1e-4")
+T255_FP64_AT_E = Workload(
+    "T255-fp64-at-E", L=255, nlat=0, nlon=0, dt=3600.0, N=190, p0=28.0, y=67.91071976436587, prec=0, seed=2,
+    desc="REXI stage T255, dt = 3600 s, FP64 solves, contour chosen for E = 1e-4")
+
+# Ensemble of linear-SWE instances of mixed truncation (T63/T127/T255), pole
+# counts N = 2 randint(100, 400], dt = 3600 s, FP32 solves with the FP64 pole
+# sum; each member's p0 minimises its predicted error at its N.
+ENSEMBLE = Workload(
+    "ensemble-64", L=255, nlat=0, nlon=0, dt=3600.0, N=0, p0=0.0, y=0.0, prec=1, seed=3,
+    desc="64 linear-SWE members, T63/T127/T255 mixed, N in [202, 800], one fused REXI launch",
+    extra={"count": 64})
+
+ALL.update({w.name: w for w in [T255_FP32_AT_E, T255_FP64_AT_E, ENSEMBLE]})
+
+
+def ensemble_plan(count: int = 64, seed: int = 3, prec: int = 1, dt: float = 3600.0):
+    """Members of the ensemble: list of dicts with L, N, p0, y, dt and the input seed."""
+    from . import contour
+    from .inputs import ensemble_members
+    cache = {}
+    out = []
+    for L, N, s in ensemble_members(count, seed):
+        if (L, N) not in cache:
+            cache[(L, N)] = contour.best_p0(L, dt, N, prec)
+        c = cache[(L, N)]
+        out.append(dict(L=L, N=N, p0=c.p0, y=c.y, dt=dt, seed=s))
+    return out

@@ -3,6 +3,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -298,6 +300,7 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_rows) (void)hipFree(ctx->d_rows);
     if (ctx->d_fact) (void)hipFree(ctx->d_fact);
     if (ctx->d_ckpt) (void)hipFree(ctx->d_ckpt);
+    free_batch_plan(ctx);
     void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
@@ -348,6 +351,109 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int 
     int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
     if (rc != REXI_OK) return rc;
     return launch_rexi_solve(ctx, N, dt, U0, U1, stream);
+}
+
+int rexi_linear_step_batched(const rexi_member* members, int count, hipStream_t stream) {
+    if (!members || count < 1 || count > 4096)
+        return fail(REXI_EINVAL, "rexi_linear_step_batched: need 1 to 4096 members");
+    std::set<const swe_ctx*> seen;
+    std::vector<BatchMember> mem(count);
+    for (int i = 0; i < count; ++i) {
+        const rexi_member& m = members[i];
+        if (!m.ctx || !m.alpha || !m.beta || !m.U0 || !m.U1)
+            return fail(REXI_EINVAL, "rexi_linear_step_batched: NULL context or pointer in a member");
+        if (!seen.insert(m.ctx).second)
+            return fail(REXI_EINVAL, "rexi_linear_step_batched: every member needs its own context");
+        if (m.ctx->device != members[0].ctx->device ||
+            ((m.ctx->prec ^ members[0].ctx->prec) & REXI_PREC_FP32_SOLVE))
+            return fail(REXI_EINVAL, "rexi_linear_step_batched: members differ in device or solve precision");
+        if (m.N < 2 || (m.N & 1) || m.N > (1 << 20))
+            return fail(REXI_EINVAL, "rexi_linear_step_batched: N must be even and in [2, 2^20]");
+        if (!(m.dt > 0) || !std::isfinite(m.dt)) return fail(REXI_EINVAL, "rexi_linear_step_batched: dt must be positive");
+        const size_t bytes = sizeof(double) * 6 * m.ctx->modes;
+        const char* a0 = reinterpret_cast<const char*>(m.U0);
+        const char* a1 = reinterpret_cast<const char*>(m.U1);
+        if (a0 < a1 + bytes && a1 < a0 + bytes) return fail(REXI_EINVAL, "rexi_linear_step_batched: U0 and U1 overlap");
+        mem[i] = BatchMember{m.ctx, m.N, m.dt, m.U0, m.U1};
+    }
+    DeviceGuard guard(members[0].ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "rexi_linear_step_batched: cannot select the device");
+    for (int i = 0; i < count; ++i) {
+        const int rc = prepare_poles(members[i].ctx, members[i].alpha, members[i].beta, members[i].N,
+                                     members[i].dt, stream);
+        if (rc != REXI_OK) return rc;
+    }
+    return launch_rexi_batched(mem.data(), count, stream);
+}
+
+int swe_get_tuning(swe_ctx* ctx, int* solver, int* seg_rows, int* waves, int* poles_per_lane) {
+    if (!ctx || !solver || !seg_rows || !waves || !poles_per_lane)
+        return fail(REXI_EINVAL, "swe_get_tuning: NULL argument");
+    *solver = ctx->tune.solver;
+    *seg_rows = ctx->tune.seg_rows;
+    *waves = ctx->tune.waves;
+    *poles_per_lane = ctx->tune.poles_per_lane;
+    return REXI_OK;
+}
+
+int swe_autotune(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt, const double* U0,
+                 double* U1, int reps, hipStream_t stream, double* best_ms) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_autotune: NULL context");
+    if (reps < 1 || reps > 1000) return fail(REXI_EINVAL, "swe_autotune: reps must be in [1, 1000]");
+    int rc = rexi_linear_step(ctx, alpha, beta, N, dt, U0, U1, stream);   // validates, prepares the poles
+    if (rc != REXI_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(REXI_EDEVICE, "swe_autotune: cannot create events");
+    }
+    const Tuning saved = ctx->tune;
+    Tuning best = saved;
+    double best_t = std::numeric_limits<double>::infinity();
+    const int shapes[4][2] = {{1, 16}, {1, 32}, {2, 8}, {2, 16}};   // (poles per lane, segment rows)
+    rc = REXI_OK;
+    for (int solver = REXI_SOLVER_FUSED; solver <= REXI_SOLVER_HYBRID && rc == REXI_OK; ++solver) {
+        for (const auto& sh : shapes) {
+            for (int waves : {1, 2, 4}) {
+                ctx->tune = Tuning{solver, sh[1], waves, sh[0]};
+                int r = launch_rexi_solve(ctx, N, dt, U0, U1, stream);    // warm: builds a factorization
+                if (r == REXI_ENOTSUP) continue;                          // shape does not fit this problem
+                if (r != REXI_OK) { rc = r; break; }
+                if (hipEventRecord(e0, stream) != hipSuccess) { rc = fail(REXI_EDEVICE, "swe_autotune: event"); break; }
+                for (int i = 0; i < reps && r == REXI_OK; ++i) r = launch_rexi_solve(ctx, N, dt, U0, U1, stream);
+                if (r != REXI_OK) { rc = r; break; }
+                float ms = 0.0f;
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = fail(REXI_EDEVICE, "swe_autotune: timing failed");
+                    break;
+                }
+                if (ms < best_t) {
+                    best_t = ms;
+                    best = ctx->tune;
+                }
+            }
+            if (rc != REXI_OK) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != REXI_OK) {
+        ctx->tune = saved;
+        return rc;
+    }
+    ctx->tune = best;
+    if (best.solver == REXI_SOLVER_FUSED && ctx->d_fact) {
+        // the winning schedule does not read the factorization: release it
+        REXI_HIP(hipStreamSynchronize(stream));
+        REXI_HIP(hipFree(ctx->d_fact));
+        ctx->d_fact = nullptr;
+        ctx->fact_cap = 0;
+        ctx->fact_valid = false;
+    }
+    if (best_ms) *best_ms = best_t / reps;
+    return REXI_OK;
 }
 
 int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStream_t stream) {

@@ -139,6 +139,8 @@ struct swe_ctx {
     size_t fact_cap = 0;
     bool fact_valid = false;
     int fact_prec = 0;          // 1: FP32 pivots, 2: FP64 pivots
+    // device copy of the last ensemble launched with this context first
+    void* batch = nullptr;
     // segment-start states of the chain sweeps (per launch)
     void* d_ckpt = nullptr;
     size_t ckpt_cap = 0;
@@ -182,6 +184,19 @@ namespace rexi {
 // Launches the chain solve + reduction for one REXI stage on `stream`.
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
                       hipStream_t stream);
+
+// One member of an ensemble REXI stage (poles already prepared in ctx).
+struct BatchMember {
+    swe_ctx* ctx;
+    int N;
+    double dt;
+    const double* U0;
+    double* U1;
+};
+// Launches the REXI stages of `count` members (same precision; launch shape of
+// the first member's context) as one rows, one solve and one sum launch.
+int launch_rexi_batched(const BatchMember* mem, int count, hipStream_t stream);
+void free_batch_plan(swe_ctx* ctx);
 
 // Spherical-harmonic transform stages (sht.hip).  kind 0: nf scalar fields;
 // kind 1: the non-linear set (synthesis: h, zeta, U, V from a state;

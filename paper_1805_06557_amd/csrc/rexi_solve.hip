@@ -28,8 +28,11 @@
 // kernel adds in pole-wave order, so results are bit-reproducible.  The file is
 // compiled without automatic FMA contraction and every fused multiply-add is
 // written out, so all inlined copies of a step perform the same rounding.
+#include <algorithm>
+#include <cstring>
 #include <type_traits>
 #include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -92,11 +95,9 @@ struct RowRec {
 };
 static_assert(sizeof(RowRec) == 96, "RowRec layout");
 
-__global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
-                                                        RowRec* __restrict__ rec, int L, int modes, double dt,
-                                                        double H) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= modes) return;
+__device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
+                                               RowRec* __restrict__ rec, int L, int modes, double dt, double H,
+                                               int idx) {
     // recover (m, k) from the m-major index
     int m = 0;
     while (m < L && (m + 1) * (2 * L + 3 - (m + 1)) / 2 <= idx) ++m;
@@ -136,6 +137,31 @@ __global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restric
     z.rfx = static_cast<float>(rz.x);
     z.rfy = static_cast<float>(rz.y);
     rec[2 * base + (1 - cd) * Lm + j] = z;
+}
+
+
+__global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
+                                                        RowRec* __restrict__ rec, int L, int modes, double dt,
+                                                        double H) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= modes) return;
+    build_row_pair(U0, coef, rec, L, modes, dt, H, idx);
+}
+
+// Ensemble form: member blockIdx.y.
+struct RowsArgs {
+    const double2* U0;
+    const ModeCoef* coef;
+    RowRec* rec;
+    int L, modes;
+    double dt, H;
+};
+
+__global__ __launch_bounds__(256) void rexi_rows_batched_kernel(const RowsArgs* __restrict__ args) {
+    const RowsArgs a = args[blockIdx.y];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.modes) return;
+    build_row_pair(a.U0, a.coef, a.rec, a.L, a.modes, a.dt, a.H, idx);
 }
 
 struct SolveArgs {
@@ -487,6 +513,22 @@ void rexi_chain_kernel(SolveArgs A) {
         solve_chain<T, S, 0, SCHED, P>(A, task, m, pb, smem);
 }
 
+// Ensemble form: one launch over the work items (member, task, pole block) of
+// several independent problems of the same precision and launch shape; the
+// host orders the items longest chain first.
+template <typename T, int S, int SCHED, int P>
+__global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(chain_occupancy<T, S, P>())))
+void rexi_chain_batched_kernel(const SolveArgs* __restrict__ args, const int4* __restrict__ items) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int4 it = items[blockIdx.x];
+    const SolveArgs A = args[it.x];
+    const int task = it.y, pb = it.z, m = task >> 1;
+    if (task & 1)
+        solve_chain<T, S, 1, SCHED, P>(A, task, m, pb, smem);
+    else
+        solve_chain<T, S, 0, SCHED, P>(A, task, m, pb, smem);
+}
+
 // Factorization: the pivots of every chain row for every pole (padding lanes up
 // to npad use pole 0), stored at fact[(chain row) npad + pole].  One thread per
 // pole, one workgroup per (task, block of poles); depends on z, dt and the
@@ -515,13 +557,10 @@ __global__ __launch_bounds__(256) void rexi_factor_kernel(const RowRec* __restri
     }
 }
 
-// U1[i] = sum over pole blocks of part[pb][i], in block order, compensated.
-__global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part,
-                                                           double2* __restrict__ U1, int count, int npb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+// sum over pole waves of part[pw][i], in pole-wave order, compensated.
+__device__ __forceinline__ double2 sum_parts(const double2* __restrict__ part, int count, int nparts, int i) {
     double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
-    for (int b = 0; b < npb; ++b) {
+    for (int b = 0; b < nparts; ++b) {
         const double2 v = part[static_cast<size_t>(b) * count + i];
         double t = sx + v.x;
         cx += (fabs(sx) >= fabs(v.x)) ? (sx - t) + v.x : (v.x - t) + sx;
@@ -530,22 +569,53 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __rest
         cy += (fabs(sy) >= fabs(v.y)) ? (sy - t) + v.y : (v.y - t) + sy;
         sy = t;
     }
-    U1[i] = make_double2(sx + cx, sy + cy);
+    return make_double2(sx + cx, sy + cy);
 }
 
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part,
+                                                           double2* __restrict__ U1, int count, int nparts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    U1[i] = sum_parts(part, count, nparts, i);
+}
+
+// Ensemble form: member blockIdx.y (count = 0: the member has one pole wave
+// and its solve wrote U1 directly).
+struct SumArgs {
+    const double2* part;
+    double2* U1;
+    int count, nparts;
+};
+
+__global__ __launch_bounds__(256) void sum_partials_batched_kernel(const SumArgs* __restrict__ args) {
+    const SumArgs a = args[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.count) return;
+    a.U1[i] = sum_parts(a.part, a.count, a.nparts, i);
+}
+
+// The factorization cache of a context: reserve_factors sizes it (dropping a
+// cache of another size), build_factors fills it from the row records of the
+// current call when it is not valid for the cached coefficient set, dt and T.
 template <typename T>
-int ensure_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
-    const int tprec = std::is_same<T, float>::value ? 1 : 2;
-    if (ctx->fact_valid && ctx->fact_prec == tprec) return REXI_OK;
+int reserve_factors(swe_ctx* ctx, const SolveArgs& A) {
     const size_t bytes = sizeof(Cx<T>) * 2 * static_cast<size_t>(A.modes) * A.npad;
     if (bytes > ctx->fact_cap) {
         if (ctx->d_fact) REXI_HIP(hipFree(ctx->d_fact));
         ctx->d_fact = nullptr;
         ctx->fact_cap = 0;
+        ctx->fact_valid = false;
         if (hipMalloc(&ctx->d_fact, bytes) != hipSuccess)
             return fail(REXI_ENOMEM, "rexi solve: cannot allocate the factorization cache");
         ctx->fact_cap = bytes;
     }
+    return REXI_OK;
+}
+
+template <typename T>
+int build_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
+    const int tprec = std::is_same<T, float>::value ? 1 : 2;
+    if (ctx->fact_valid && ctx->fact_prec == tprec) return REXI_OK;
     const int threads = 256;
     const int fpb = (A.npad + threads - 1) / threads;
     const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * fpb);
@@ -559,15 +629,18 @@ int ensure_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
     return REXI_OK;
 }
 
+// Fills the shape-dependent fields of A and makes sure the context's
+// factorization cache (STREAM, HYBRID; filled later by build_factors, once the
+// row records of the call exist) and checkpoint workspace are allocated.
 template <typename T, int S, int SCHED, int P>
-int launch_typed(swe_ctx* ctx, SolveArgs A, int waves, hipStream_t stream) {
+int configure(swe_ctx* ctx, SolveArgs& A, int waves, hipStream_t stream) {
     const int nseg = (A.L + 1 + S - 1) / S;
     A.nck_max = nseg > 2 ? nseg - 2 : 0;
     A.rec_bytes = static_cast<int>(sizeof(RowRec)) * (A.L + 1);
     A.npb = (A.N + WAVE * P * waves - 1) / (WAVE * P * waves);
     constexpr int CKW = ckpt_words<SCHED>();
     if (SCHED != FUSED) {
-        const int rc = ensure_factors<T>(ctx, A, stream);
+        const int rc = reserve_factors<T>(ctx, A);
         if (rc != REXI_OK) return rc;
         A.fact = ctx->d_fact;
     }
@@ -583,21 +656,188 @@ int launch_typed(swe_ctx* ctx, SolveArgs A, int waves, hipStream_t stream) {
         ctx->ckpt_cap = ck_bytes;
     }
     A.ckpt = ctx->d_ckpt;
-    const size_t lds = static_cast<size_t>(A.rec_bytes) + sizeof(double2) * 6 * WAVE * waves;
+    return REXI_OK;
+}
+
+template <typename KernelFn>
+int prepare_lds(KernelFn* fn, size_t lds) {
     if (lds > 160 * 1024) return fail(REXI_ENOTSUP, "rexi solve: LDS need exceeds 160 KB; lower waves");
     if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&rexi_chain_kernel<T, S, SCHED, P>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(lds)) != hipSuccess) {
             (void)hipGetLastError();
             return fail(REXI_ENOTSUP, "rexi solve: LDS need exceeds the device limit; lower waves");
         }
     }
+    return REXI_OK;
+}
+
+template <typename T, int S, int SCHED, int P>
+int launch_typed(swe_ctx* ctx, SolveArgs A, int waves, hipStream_t stream) {
+    int rc = configure<T, S, SCHED, P>(ctx, A, waves, stream);
+    if (rc != REXI_OK) return rc;
+    if (SCHED != FUSED && (rc = build_factors<T>(ctx, A, stream)) != REXI_OK) return rc;
+    const size_t lds = static_cast<size_t>(A.rec_bytes) + sizeof(double2) * 6 * WAVE * waves;
+    if ((rc = prepare_lds(&rexi_chain_kernel<T, S, SCHED, P>, lds)) != REXI_OK) return rc;
     const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * A.npb);
     const int slot = prof_begin(ctx, REXI_KERNEL_SOLVE, stream);
     hipLaunchKernelGGL((rexi_chain_kernel<T, S, SCHED, P>), dim3(blocks), dim3(WAVE * waves), lds, stream, A);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_SOLVE, slot, stream);
     return REXI_OK;
+}
+
+// ---- ensemble launch ---------------------------------------------------------
+
+// Device copy of an ensemble's per-member arguments and work items, kept in the
+// first member's context and re-uploaded only when the key changes.
+struct BatchPlan {
+    uint64_t key = 0;
+    void* d_args = nullptr;     // SolveArgs[count]
+    void* d_rows = nullptr;     // RowsArgs[count]
+    void* d_sum = nullptr;      // SumArgs[count]
+    void* d_items = nullptr;    // int4[nitems]
+    size_t args_cap = 0, items_cap = 0;
+    int nitems = 0, max_count = 0, max_modes = 0;
+    size_t lds = 0;
+};
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+template <typename T, int S, int SCHED, int P>
+int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hipStream_t stream, SolveArgs* A,
+                         BatchPlan& plan) {
+    const int waves = t.waves;
+    int rc;
+    size_t rec_max = 0;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = configure<T, S, SCHED, P>(mem[i].ctx, A[i], waves, stream)) != REXI_OK) return rc;
+        rec_max = std::max(rec_max, static_cast<size_t>(A[i].rec_bytes));
+    }
+    for (int i = 0; i < count; ++i) A[i].rec_bytes = static_cast<int>(rec_max);
+    const size_t lds = rec_max + sizeof(double2) * 6 * WAVE * waves;
+    if ((rc = prepare_lds(&rexi_chain_batched_kernel<T, S, SCHED, P>, lds)) != REXI_OK) return rc;
+
+    uint64_t key = 1469598103934665603ULL;
+    key = mix(key, static_cast<uint64_t>(count));
+    key = mix(key, static_cast<uint64_t>(t.solver * 1000 + t.seg_rows * 10 + t.poles_per_lane) * 8 + waves);
+    for (int i = 0; i < count; ++i) {
+        const unsigned char* b = reinterpret_cast<const unsigned char*>(&A[i]);
+        for (size_t k = 0; k < sizeof(SolveArgs); k += 8) {
+            uint64_t v = 0;
+            std::memcpy(&v, b + k, std::min<size_t>(8, sizeof(SolveArgs) - k));
+            key = mix(key, v);
+        }
+        key = mix(key, reinterpret_cast<uintptr_t>(mem[i].U0));
+        key = mix(key, reinterpret_cast<uintptr_t>(mem[i].U1));
+        uint64_t dtb;
+        std::memcpy(&dtb, &mem[i].dt, 8);
+        key = mix(key, dtb);
+    }
+    if (key != plan.key || !plan.d_args) {
+        // work items, longest chains first (ties: member order, then task, then pole block)
+        std::vector<int4> items;
+        for (int i = 0; i < count; ++i)
+            for (int task = 0; task < 2 * (A[i].L + 1); ++task)
+                for (int pb = 0; pb < A[i].npb; ++pb) items.push_back(make_int4(i, task, pb, A[i].L - (task >> 1) + 1));
+        std::stable_sort(items.begin(), items.end(), [](const int4& a, const int4& b) { return a.w > b.w; });
+        std::vector<RowsArgs> rows(count);
+        std::vector<SumArgs> sums(count);
+        int max_modes = 0;
+        for (int i = 0; i < count; ++i) {
+            swe_ctx* c = mem[i].ctx;
+            rows[i] = RowsArgs{reinterpret_cast<const double2*>(mem[i].U0), c->d_coef,
+                               reinterpret_cast<RowRec*>(c->d_rows), c->L, c->modes, mem[i].dt, c->H};
+            const int nparts = (mem[i].N + WAVE * P - 1) / (WAVE * P);
+            sums[i] = SumArgs{reinterpret_cast<const double2*>(c->d_partial), reinterpret_cast<double2*>(mem[i].U1),
+                              nparts > 1 ? 3 * c->modes : 0, nparts};
+            max_modes = std::max(max_modes, c->modes);
+        }
+        const size_t abytes = (sizeof(SolveArgs) + sizeof(RowsArgs) + sizeof(SumArgs)) * count;
+        if (abytes > plan.args_cap) {
+            for (void** p : {&plan.d_args, &plan.d_rows, &plan.d_sum}) {
+                if (*p) REXI_HIP(hipFree(*p));
+                *p = nullptr;
+            }
+            plan.args_cap = 0;
+            if (hipMalloc(&plan.d_args, sizeof(SolveArgs) * count) != hipSuccess ||
+                hipMalloc(&plan.d_rows, sizeof(RowsArgs) * count) != hipSuccess ||
+                hipMalloc(&plan.d_sum, sizeof(SumArgs) * count) != hipSuccess)
+                return fail(REXI_ENOMEM, "rexi_linear_step_batched: cannot allocate the ensemble plan");
+            plan.args_cap = abytes;
+        }
+        if (sizeof(int4) * items.size() > plan.items_cap) {
+            if (plan.d_items) REXI_HIP(hipFree(plan.d_items));
+            plan.d_items = nullptr;
+            plan.items_cap = 0;
+            if (hipMalloc(&plan.d_items, sizeof(int4) * items.size()) != hipSuccess)
+                return fail(REXI_ENOMEM, "rexi_linear_step_batched: cannot allocate the work items");
+            plan.items_cap = sizeof(int4) * items.size();
+        }
+        // host arrays die at return: copy synchronously with respect to the host
+        REXI_HIP(hipMemcpyAsync(plan.d_args, A, sizeof(SolveArgs) * count, hipMemcpyHostToDevice, stream));
+        REXI_HIP(hipMemcpyAsync(plan.d_rows, rows.data(), sizeof(RowsArgs) * count, hipMemcpyHostToDevice, stream));
+        REXI_HIP(hipMemcpyAsync(plan.d_sum, sums.data(), sizeof(SumArgs) * count, hipMemcpyHostToDevice, stream));
+        REXI_HIP(hipMemcpyAsync(plan.d_items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, stream));
+        REXI_HIP(hipStreamSynchronize(stream));
+        plan.key = key;
+        plan.nitems = static_cast<int>(items.size());
+        plan.max_count = count;
+        plan.max_modes = max_modes;
+    }
+    swe_ctx* c0 = mem[0].ctx;
+    {
+        const int threads = 256;
+        hipLaunchKernelGGL(rexi_rows_batched_kernel, dim3((plan.max_modes + threads - 1) / threads, count),
+                           dim3(threads), 0, stream, reinterpret_cast<const RowsArgs*>(plan.d_rows));
+        REXI_HIP(hipGetLastError());
+    }
+    if (SCHED != FUSED) {
+        // factorizations that are missing are built now that the row records exist
+        for (int i = 0; i < count; ++i)
+            if ((rc = build_factors<T>(mem[i].ctx, A[i], stream)) != REXI_OK) return rc;
+    }
+    const int slot = prof_begin(c0, REXI_KERNEL_SOLVE, stream);
+    hipLaunchKernelGGL((rexi_chain_batched_kernel<T, S, SCHED, P>), dim3(plan.nitems), dim3(WAVE * waves), lds,
+                       stream, reinterpret_cast<const SolveArgs*>(plan.d_args),
+                       reinterpret_cast<const int4*>(plan.d_items));
+    REXI_HIP(hipGetLastError());
+    prof_end(c0, REXI_KERNEL_SOLVE, slot, stream);
+    {
+        const int threads = 256;
+        const int slot2 = prof_begin(c0, REXI_KERNEL_REDUCE, stream);
+        hipLaunchKernelGGL(sum_partials_batched_kernel, dim3((3 * plan.max_modes + threads - 1) / threads, count),
+                           dim3(threads), 0, stream, reinterpret_cast<const SumArgs*>(plan.d_sum));
+        REXI_HIP(hipGetLastError());
+        prof_end(c0, REXI_KERNEL_REDUCE, slot2, stream);
+    }
+    return REXI_OK;
+}
+
+template <typename T, int S, int P>
+int batched_sched(const BatchMember* mem, int count, const Tuning& t, hipStream_t stream, SolveArgs* A,
+                  BatchPlan& plan) {
+    switch (t.solver) {
+        case REXI_SOLVER_STREAM: return launch_batched_typed<T, S, STREAM, P>(mem, count, t, stream, A, plan);
+        case REXI_SOLVER_HYBRID: return launch_batched_typed<T, S, HYBRID, P>(mem, count, t, stream, A, plan);
+        default: return launch_batched_typed<T, S, FUSED, P>(mem, count, t, stream, A, plan);
+    }
+}
+
+template <typename T>
+int batched_shape(const BatchMember* mem, int count, const Tuning& t, hipStream_t stream, SolveArgs* A,
+                  BatchPlan& plan) {
+    if (t.poles_per_lane == 2) {
+        if (t.seg_rows == 8) return batched_sched<T, 8, 2>(mem, count, t, stream, A, plan);
+        if (t.seg_rows == 16) return batched_sched<T, 16, 2>(mem, count, t, stream, A, plan);
+    } else {
+        if (t.seg_rows == 16) return batched_sched<T, 16, 1>(mem, count, t, stream, A, plan);
+        if (t.seg_rows == 32) return batched_sched<T, 32, 1>(mem, count, t, stream, A, plan);
+    }
+    return fail(REXI_ENOTSUP, "rexi solve: seg_rows must be 16 or 32 with one pole per lane, 8 or 16 with two");
 }
 
 template <typename T, int S, int P>
@@ -624,22 +864,13 @@ int launch_shape(swe_ctx* ctx, const SolveArgs& A, const Tuning& t, hipStream_t 
     return fail(REXI_ENOTSUP, "rexi solve: seg_rows must be 16 or 32 with one pole per lane, 8 or 16 with two");
 }
 
-}  // namespace
-
-int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+// Shape-independent arguments of one member's solve; allocates the row records
+// and (for more than one pole wave) the partial sums.
+int base_args(swe_ctx* ctx, int N, double dt, const double* U1, int P, SolveArgs& A, int& nparts) {
     if (!ctx->d_rows) {
         if (hipMalloc(&ctx->d_rows, sizeof(RowRec) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess)
             return fail(REXI_ENOMEM, "rexi solve: cannot allocate row records");
     }
-    {
-        const int threads = 256;
-        const unsigned blocks = static_cast<unsigned>((ctx->modes + threads - 1) / threads);
-        hipLaunchKernelGGL(rexi_rows_kernel, dim3(blocks), dim3(threads), 0, stream,
-                           reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
-                           ctx->L, ctx->modes, dt, ctx->H);
-        REXI_HIP(hipGetLastError());
-    }
-    SolveArgs A;
     A.rec = reinterpret_cast<const RowRec*>(ctx->d_rows);
     A.poles = ctx->d_poles;
     A.L = ctx->L;
@@ -647,12 +878,14 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
     A.N = N;
     // the factorization layout pads the pole axis to whole pairs of waves for every launch shape
     A.npad = (N + 2 * WAVE - 1) / (2 * WAVE) * (2 * WAVE);
-    const int P = ctx->tune.poles_per_lane;
-    const int nparts = (N + WAVE * P - 1) / (WAVE * P);       // pole waves that produce partial sums
+    nparts = (N + WAVE * P - 1) / (WAVE * P);          // pole waves that produce partial sums
     A.dtH = dt * ctx->H;
+    A.fact = nullptr;
+    A.ckpt = nullptr;
+    A.npb = A.nck_max = A.rec_bytes = 0;
     const size_t count = static_cast<size_t>(3) * ctx->modes;
     if (nparts == 1) {
-        A.out = reinterpret_cast<double2*>(U1);
+        A.out = reinterpret_cast<double2*>(const_cast<double*>(U1));
     } else {
         const size_t need = 2 * count * nparts;
         if (need > ctx->partial_cap) {
@@ -665,22 +898,64 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
         }
         A.out = reinterpret_cast<double2*>(ctx->d_partial);
     }
+    return REXI_OK;
+}
+
+}  // namespace
+
+int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    SolveArgs A;
+    int nparts = 0;
+    int rc = base_args(ctx, N, dt, U1, ctx->tune.poles_per_lane, A, nparts);
+    if (rc != REXI_OK) return rc;
+    {
+        const int threads = 256;
+        const unsigned blocks = static_cast<unsigned>((ctx->modes + threads - 1) / threads);
+        hipLaunchKernelGGL(rexi_rows_kernel, dim3(blocks), dim3(threads), 0, stream,
+                           reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
+                           ctx->L, ctx->modes, dt, ctx->H);
+        REXI_HIP(hipGetLastError());
+    }
     const bool fp32 = (ctx->prec & REXI_PREC_FP32_SOLVE) != 0;
-    A.fact = nullptr;
-    A.ckpt = nullptr;
-    const int rc = fp32 ? launch_shape<float>(ctx, A, ctx->tune, stream) : launch_shape<double>(ctx, A, ctx->tune, stream);
+    rc = fp32 ? launch_shape<float>(ctx, A, ctx->tune, stream) : launch_shape<double>(ctx, A, ctx->tune, stream);
     if (rc != REXI_OK) return rc;
     if (nparts > 1) {
         const int threads = 256;
+        const int count = 3 * ctx->modes;
         const unsigned blocks = static_cast<unsigned>((count + threads - 1) / threads);
         const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
         hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks), dim3(threads), 0, stream,
-                           reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1),
-                           static_cast<int>(count), nparts);
+                           reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1), count,
+                           nparts);
         REXI_HIP(hipGetLastError());
         prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
     }
     return REXI_OK;
+}
+
+int launch_rexi_batched(const BatchMember* mem, int count, hipStream_t stream) {
+    swe_ctx* c0 = mem[0].ctx;
+    const Tuning t = c0->tune;
+    std::vector<SolveArgs> A(count);
+    for (int i = 0; i < count; ++i) {
+        int nparts = 0;
+        const int rc = base_args(mem[i].ctx, mem[i].N, mem[i].dt, mem[i].U1, t.poles_per_lane, A[i], nparts);
+        if (rc != REXI_OK) return rc;
+    }
+    if (!c0->batch) c0->batch = new BatchPlan();
+    BatchPlan& plan = *static_cast<BatchPlan*>(c0->batch);
+    const bool fp32 = (c0->prec & REXI_PREC_FP32_SOLVE) != 0;
+    return fp32 ? batched_shape<float>(mem, count, t, stream, A.data(), plan)
+                : batched_shape<double>(mem, count, t, stream, A.data(), plan);
+}
+
+void free_batch_plan(swe_ctx* ctx) {
+    if (!ctx->batch) return;
+    BatchPlan* p = static_cast<BatchPlan*>(ctx->batch);
+    for (void* q : {p->d_args, p->d_rows, p->d_sum, p->d_items})
+        if (q) (void)hipFree(q);
+    delete p;
+    ctx->batch = nullptr;
 }
 
 }  // namespace rexi
