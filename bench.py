@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-PEAK_FP32_VALU = 157.3     # TFLOP/s: the same with packed FP32 (2 per lane)
+PEAK_FP32_VALU = 78.6      # TFLOP/s: the same for unpacked FP32, the form this library is built for
+PEAK_FP32_PACKED = 157.3   # TFLOP/s: published FP32 vector peak (packed FP32, 2 per lane), reported alongside
 PEAK_HBM = 8000.0          # GB/s
 
 # Algorithmic flops of the fused chain solve per (pole, chain row), counting a
@@ -121,6 +122,108 @@ def _oracle_chunk(args):
     return len(orders)
 
 
+def _timed(fn, reps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def _field_errors(got, ref):
+    import numpy as np
+    linf = [float(np.abs(got[f] - ref[f]).max() / np.abs(ref[f]).max()) for f in range(3)]
+    l2 = [float(np.linalg.norm(got[f] - ref[f]) / np.linalg.norm(ref[f])) for f in range(3)]
+    return {"linf_rel": dict(zip(("h", "zeta", "delta"), linf)), "l2_rel": dict(zip(("h", "zeta", "delta"), l2))}
+
+
+def equal_error_arm(reps):
+    """FP32 against FP64 REXI stages at T255 (dt = 3600 s), each with the contour
+    that meets the same target scalar error E with the fewest poles, timed on the
+    same jet state; the error of each is measured per field against the FP64
+    stage with a much tighter contour (N = 800, p0 = 12, predicted error 1.3e-11)."""
+    import torch
+
+    from paper_1805_06557_amd import api, configs
+    from paper_1805_06557_amd.inputs import jet_state
+
+    stream = torch.cuda.current_stream()
+    ref_w = configs.T255_FP64
+    U0 = torch.from_numpy(jet_state(255, ref_w.seed)).cuda()
+    cref = api.SWE(255, prec=0)
+    a, b, _, _ = api.rexi_coefficients(api.FN_EXP, ref_w.N, ref_w.p0, ref_w.y)
+    Uref = torch.empty_like(U0)
+    cref.rexi_linear_step(a, b, ref_w.dt, U0, Uref, stream)
+    ref = Uref.cpu().numpy()
+    cref.close()
+    out = {"E": configs.EQUAL_ERROR_E, "reference": "FP64 stage, N=800, p0=12"}
+    for key, w in (("fp32", configs.T255_FP32_AT_E), ("fp64", configs.T255_FP64_AT_E)):
+        ctx = api.SWE(w.L, prec=w.prec)
+        a, b, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
+        U1 = torch.empty_like(U0)
+        ctx.autotune(a, b, w.dt, U0, U1, reps=3, stream=stream)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                ctx.rexi_linear_step(a, b, w.dt, U0, U1, side)
+            side.synchronize()
+            # a graph of `reps` stages, so host launch gaps do not count
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(reps):
+                    ctx.rexi_linear_step(a, b, w.dt, U0, U1, side)
+            ms = _timed(g.replay, 3, side) / reps
+        out[key] = {"N": w.N, "p0": w.p0, "tuning": ctx.get_tuning(), "ms_per_stage": ms,
+                    "term_solves_per_s": w.N / (ms * 1e-3),
+                    "sim_time_per_wall_rexi_stage": w.dt / (ms * 1e-3), **_field_errors(U1.cpu().numpy(), ref)}
+        ctx.close()
+    out["fp64_speedup_at_equal_error"] = out["fp32"]["ms_per_stage"] / out["fp64"]["ms_per_stage"]
+    return out
+
+
+def ensemble_arm(reps):
+    """64 linear-SWE members of mixed truncation and pole count (FP32 solves):
+    one fused ensemble launch (eager and replayed from a captured graph) against
+    one rexi_linear_step per member."""
+    import torch
+
+    from paper_1805_06557_amd import api, configs
+    from paper_1805_06557_amd.inputs import random_state
+
+    plan = configs.ensemble_plan()
+    members = []
+    for m in plan:
+        ctx = api.SWE(m["L"], prec=1)
+        a, b, _, _ = api.rexi_coefficients(api.FN_EXP, m["N"], m["p0"], m["y"])
+        U0 = torch.from_numpy(random_state(m["L"], m["seed"])).cuda()
+        members.append((ctx, a, b, m["dt"], U0, torch.empty_like(U0)))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        api.rexi_linear_step_batched(members, stream=stream)
+        eager = _timed(lambda: api.rexi_linear_step_batched(members, stream=stream), reps, stream)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            api.rexi_linear_step_batched(members, stream=stream)
+        graph = _timed(g.replay, reps, stream)
+
+        def separate():
+            for ctx, a, b, dt, U0, U1 in members:
+                ctx.rexi_linear_step(a, b, dt, U0, U1, stream)
+        separate()
+        sep = _timed(separate, reps, stream)
+    total_n = sum(m["N"] for m in plan)
+    for m in members:
+        m[0].close()
+    return {"members": len(plan), "truncations": sorted({m["L"] for m in plan}), "total_poles": total_n,
+            "ms_fused_eager": eager, "ms_fused_graph": graph, "ms_one_launch_per_member": sep,
+            "term_solves_per_s_graph": total_n / (graph * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,9 +235,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver", choices=["default", "fused", "stream", "hybrid"], default="default",
                     help="REXI chain-solve schedule")
-    ap.add_argument("--seg-rows", type=int, default=0, help="REXI solve segment length (16, 32; 0 = default)")
+    ap.add_argument("--seg-rows", type=int, default=0, help="REXI solve segment length (8, 16, 32; 0 = default)")
     ap.add_argument("--waves", type=int, default=0, help="REXI solve waves per workgroup (1, 2, 4; 0 = default)")
     ap.add_argument("--ppl", type=int, default=0, help="REXI solve poles per lane (1, 2; 0 = default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (reference kernel for HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default launch shape")
+    ap.add_argument("--no-arms", action="store_true",
+                    help="skip the FP32-vs-FP64 equal-error arm and the ensemble arm")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed but not built "
@@ -143,6 +251,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "copies": 5}))
+        return
 
     from paper_1805_06557_amd import api, configs
     from paper_1805_06557_amd.inputs import jet_state
@@ -158,6 +275,9 @@ def main():
     U = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
     V = torch.empty_like(U)
     stream = torch.cuda.current_stream()
+    if not (solver or args.seg_rows or args.waves or args.ppl or args.no_autotune):
+        # pick the REXI solve's schedule and launch shape on this problem (outside the timed region)
+        ctx.autotune(alpha, beta, w.dt, U, V, reps=3, stream=stream)
 
     def step(src, dst):
         if full:
@@ -203,6 +323,7 @@ def main():
     ms_per_step = ms_total / args.steps
     fp32 = bool(w.prec & api.PREC_FP32_SOLVE)
     peak = PEAK_FP32_VALU if fp32 else PEAK_FP64_VALU
+    tuning = ctx.get_tuning()
     avg_solve_ms = solve_ms / max(solve_n, 1)
     achieved = solve_flops(w.L, w.N) / (avg_solve_ms * 1e-3) / 1e12
     stage = "l_rexi_n_erk_ver1 step" if full else "REXI linear stage"
@@ -240,10 +361,17 @@ def main():
             "avg_kernel_ms": avg_solve_ms,
             "launches": solve_n,
             "algorithmic_flops_per_launch": solve_flops(w.L, w.N),
+            "peak_note": "unpacked vector ALU peak (the published 157.3 TFLOP/s FP32 figure needs packed FP32)",
+            "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED if fp32 else None,
+            "tuning": tuning,
         },
         "kernels": stage_ms,
         "setup": {"rexi_factor_kernel_ms": fact_ms / max(fact_n, 1), "launches": fact_n},
     }
+    ctx.close()
+    if not args.no_arms:
+        out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2))
+        out["ensemble"] = ensemble_arm(max(3, args.steps // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, full)
     print(json.dumps(out))

@@ -95,14 +95,12 @@ struct RowRec {
 };
 static_assert(sizeof(RowRec) == 96, "RowRec layout");
 
+// The delta and zeta records of degree k = m + j (one per chain).
 __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
                                                RowRec* __restrict__ rec, int L, int modes, double dt, double H,
-                                               int idx) {
-    // recover (m, k) from the m-major index
-    int m = 0;
-    while (m < L && (m + 1) * (2 * L + 3 - (m + 1)) / 2 <= idx) ++m;
+                                               int m, int j) {
     const int base = m * (2 * L + 3 - m) / 2;
-    const int j = idx - base;
+    const int idx = base + j;
     const int Lm = L - m + 1;
     const ModeCoef cf = coef[idx];
     const double2 rh = U0[idx], rz = U0[modes + idx], rd = U0[2 * modes + idx];
@@ -140,12 +138,12 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
 }
 
 
+// One workgroup per order m (blockIdx.x), threads over the degrees.
 __global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
                                                         RowRec* __restrict__ rec, int L, int modes, double dt,
                                                         double H) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= modes) return;
-    build_row_pair(U0, coef, rec, L, modes, dt, H, idx);
+    const int m = blockIdx.x;
+    for (int j = threadIdx.x; j < L - m + 1; j += blockDim.x) build_row_pair(U0, coef, rec, L, modes, dt, H, m, j);
 }
 
 // Ensemble form: member blockIdx.y.
@@ -159,9 +157,10 @@ struct RowsArgs {
 
 __global__ __launch_bounds__(256) void rexi_rows_batched_kernel(const RowsArgs* __restrict__ args) {
     const RowsArgs a = args[blockIdx.y];
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.modes) return;
-    build_row_pair(a.U0, a.coef, a.rec, a.L, a.modes, a.dt, a.H, idx);
+    const int m = blockIdx.x;
+    if (m > a.L) return;
+    for (int j = threadIdx.x; j < a.L - m + 1; j += blockDim.x)
+        build_row_pair(a.U0, a.coef, a.rec, a.L, a.modes, a.dt, a.H, m, j);
 }
 
 struct SolveArgs {
@@ -698,7 +697,7 @@ struct BatchPlan {
     void* d_sum = nullptr;      // SumArgs[count]
     void* d_items = nullptr;    // int4[nitems]
     size_t args_cap = 0, items_cap = 0;
-    int nitems = 0, max_count = 0, max_modes = 0;
+    int nitems = 0, max_count = 0, max_modes = 0, max_L = 0;
     size_t lds = 0;
 };
 
@@ -746,7 +745,7 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
         std::stable_sort(items.begin(), items.end(), [](const int4& a, const int4& b) { return a.w > b.w; });
         std::vector<RowsArgs> rows(count);
         std::vector<SumArgs> sums(count);
-        int max_modes = 0;
+        int max_modes = 0, max_L = 0;
         for (int i = 0; i < count; ++i) {
             swe_ctx* c = mem[i].ctx;
             rows[i] = RowsArgs{reinterpret_cast<const double2*>(mem[i].U0), c->d_coef,
@@ -755,6 +754,7 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
             sums[i] = SumArgs{reinterpret_cast<const double2*>(c->d_partial), reinterpret_cast<double2*>(mem[i].U1),
                               nparts > 1 ? 3 * c->modes : 0, nparts};
             max_modes = std::max(max_modes, c->modes);
+            max_L = std::max(max_L, c->L);
         }
         const size_t abytes = (sizeof(SolveArgs) + sizeof(RowsArgs) + sizeof(SumArgs)) * count;
         if (abytes > plan.args_cap) {
@@ -787,12 +787,12 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
         plan.nitems = static_cast<int>(items.size());
         plan.max_count = count;
         plan.max_modes = max_modes;
+        plan.max_L = max_L;
     }
     swe_ctx* c0 = mem[0].ctx;
     {
-        const int threads = 256;
-        hipLaunchKernelGGL(rexi_rows_batched_kernel, dim3((plan.max_modes + threads - 1) / threads, count),
-                           dim3(threads), 0, stream, reinterpret_cast<const RowsArgs*>(plan.d_rows));
+        hipLaunchKernelGGL(rexi_rows_batched_kernel, dim3(plan.max_L + 1, count), dim3(256), 0, stream,
+                           reinterpret_cast<const RowsArgs*>(plan.d_rows));
         REXI_HIP(hipGetLastError());
     }
     if (SCHED != FUSED) {
@@ -909,9 +909,7 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
     int rc = base_args(ctx, N, dt, U1, ctx->tune.poles_per_lane, A, nparts);
     if (rc != REXI_OK) return rc;
     {
-        const int threads = 256;
-        const unsigned blocks = static_cast<unsigned>((ctx->modes + threads - 1) / threads);
-        hipLaunchKernelGGL(rexi_rows_kernel, dim3(blocks), dim3(threads), 0, stream,
+        hipLaunchKernelGGL(rexi_rows_kernel, dim3(ctx->L + 1), dim3(256), 0, stream,
                            reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
                            ctx->L, ctx->modes, dt, ctx->H);
         REXI_HIP(hipGetLastError());
