@@ -879,7 +879,8 @@ int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* pa
     S.g = leg_args(ctx);
     S.spec = reinterpret_cast<const double2*>(spec);
     S.part = reinterpret_cast<double2*>(part);
-    const int NJ = lat_per_lane(ctx);
+    // one latitude per lane: more waves in flight (measured faster than 2 or 3 at T255)
+    const int NJ = 1;
     const int tiles = (ctx->nlat / 2 + NJ * WAVE - 1) / (NJ * WAVE);
     const dim3 grid(ctx->nseg, kind == 0 ? nf : 1, tiles);
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_SYNTH, stream);
