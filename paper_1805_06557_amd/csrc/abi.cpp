@@ -1,5 +1,6 @@
 // The C-ABI entry points: argument checks, context set-up, coefficient
 // caching and the contour check, then the kernel launches.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -134,6 +135,30 @@ int setup_sht(swe_ctx* ctx) {
     if ((rc = upload(&ctx->d_seed_pm, sg.seed_pm.data(), sg.seed_pm.size())) != REXI_OK) return rc;
     if ((rc = upload(&ctx->d_seed_p, sg.seed_p.data(), sg.seed_p.size())) != REXI_OK) return rc;
     if ((rc = upload(&ctx->d_seed_e, sg.seed_e.data(), sg.seed_e.size())) != REXI_OK) return rc;
+    if (ctx->prec & REXI_PREC_BF16_SPLIT) {
+        // row blocks per (m, parity of l - m) padded to 16, latitudes padded to 16
+        const int half = ctx->nlat / 2;
+        ctx->tab_hpad = (half + 15) / 16 * 16;
+        std::vector<int> kp(2 * (ctx->L + 1));
+        std::vector<long long> off(ctx->L + 2, 0);
+        int kmax = 16;
+        for (int m = 0; m <= ctx->L; ++m) {
+            const int Lm = ctx->L - m + 1;
+            kp[2 * m] = ((Lm + 1) / 2 + 15) / 16 * 16;
+            kp[2 * m + 1] = (Lm / 2 + 15) / 16 * 16;
+            kmax = std::max(kmax, std::max(kp[2 * m], kp[2 * m + 1]));
+            off[m + 1] = off[m] + static_cast<long long>(kp[2 * m] + kp[2 * m + 1]) * ctx->tab_hpad * 2;
+        }
+        ctx->tab_kmax = kmax;
+        ctx->tab_len = static_cast<size_t>(off[ctx->L + 1]);
+        if ((rc = upload(&ctx->d_tab_kp, kp.data(), kp.size())) != REXI_OK) return rc;
+        if ((rc = upload(&ctx->d_tab_off, off.data(), off.size())) != REXI_OK) return rc;
+        for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_hsyn, &ctx->d_tab_pana, &ctx->d_tab_hana})
+            if (hipMalloc(reinterpret_cast<void**>(t), sizeof(unsigned short) * ctx->tab_len) != hipSuccess)
+                return fail(REXI_ENOMEM, "swe_create: cannot allocate the split-precision Legendre tables");
+        if ((rc = build_split_tables(ctx, nullptr)) != REXI_OK) return rc;
+        REXI_HIP(hipStreamSynchronize(nullptr));
+    }
     // FFT of nlon reals = complex FFT of M = nlon/2 points, M = 2^a 3^b
     const int M = ctx->nlon / 2;
     std::vector<int> radix;
@@ -177,22 +202,37 @@ int reserve_fourier(swe_ctx* ctx, int nf) {
 }
 
 // One Heun step dU/dt = N(U) over tau on `stream`.
+bool split_legendre(const swe_ctx* ctx) { return (ctx->prec & REXI_PREC_BF16_SPLIT) != 0; }
+
+// Spectral fields -> Fourier coefficients [nf][nlat][L+1] in ctx->d_fin.
+int to_fourier(swe_ctx* ctx, int kind, const double* spec, int nf, hipStream_t stream) {
+    const int nfo = kind == 0 ? nf : 4;
+    if (split_legendre(ctx)) return launch_legendre_synth_split(ctx, kind, spec, ctx->d_fin, nf, stream);
+    int rc = launch_legendre_synth(ctx, kind, spec, ctx->d_part, nf, stream);
+    if (rc != REXI_OK) return rc;
+    return launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, nfo, stream);
+}
+
+// Fourier coefficients (ctx->d_fout) -> spectral fields or the Runge-Kutta update.
+int from_fourier(swe_ctx* ctx, int kind, double* spec, int nf, const double* U0, const double* Nprev, double* Nsave,
+                 double* out, double c0, double c1, hipStream_t stream) {
+    if (split_legendre(ctx))
+        return launch_legendre_anal_split(ctx, kind, ctx->d_fout, spec, nf, U0, Nprev, Nsave, out, c0, c1, stream);
+    return launch_legendre_anal(ctx, kind, ctx->d_fout, spec, nf, U0, Nprev, Nsave, out, c0, c1, stream);
+}
+
 int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
-    if ((rc = launch_legendre_synth(ctx, 1, U0, ctx->d_part, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, 4, stream)) != REXI_OK) return rc;
+    if ((rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
     if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
-    if ((rc = launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0,
-                                   stream)) != REXI_OK)
+    if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) != REXI_OK)
         return rc;
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
-    if ((rc = launch_legendre_synth(ctx, 1, ctx->d_ustar, ctx->d_part, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, 4, stream)) != REXI_OK) return rc;
+    if ((rc = to_fourier(ctx, 1, ctx->d_ustar, 3, stream)) != REXI_OK) return rc;
     if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
-    return launch_legendre_anal(ctx, 1, ctx->d_fout, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau,
-                                stream);
+    return from_fourier(ctx, 1, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau, stream);
 }
 
 }  // namespace
@@ -245,6 +285,8 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     }
     if (prec & ~(REXI_PREC_FP32_SOLVE | REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT))
         return fail(REXI_EINVAL, "swe_create: unknown precision flags");
+    if (prec & REXI_PREC_FP16_SPLIT)
+        return fail(REXI_ENOTSUP, "swe_create: the FP16 split Legendre stage is not built (BF16 split is)");
     if ((prec & REXI_PREC_BF16_SPLIT) && (prec & REXI_PREC_FP16_SPLIT))
         return fail(REXI_EINVAL, "swe_create: BF16 and FP16 Legendre modes are exclusive");
 
@@ -304,7 +346,8 @@ int swe_destroy(swe_ctx* ctx) {
     void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
-                        ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB};
+                        ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
+                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {
@@ -463,8 +506,7 @@ int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStre
     DeviceGuard guard(ctx->device);
     int rc;
     if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
-    if ((rc = launch_legendre_synth(ctx, 0, spec, ctx->d_part, nf, stream)) != REXI_OK) return rc;
-    if ((rc = launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, nf, stream)) != REXI_OK) return rc;
+    if ((rc = to_fourier(ctx, 0, spec, nf, stream)) != REXI_OK) return rc;
     return launch_ring(ctx, 0, ctx->d_fin, nullptr, nullptr, grid, nf, stream);
 }
 
@@ -476,7 +518,7 @@ int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStrea
     int rc;
     if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
     if ((rc = launch_ring(ctx, 1, nullptr, ctx->d_fout, grid, nullptr, nf, stream)) != REXI_OK) return rc;
-    return launch_legendre_anal(ctx, 0, ctx->d_fout, spec, nf, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, stream);
+    return from_fourier(ctx, 0, spec, nf, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, stream);
 }
 
 int swe_nonlinear_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {

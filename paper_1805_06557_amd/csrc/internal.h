@@ -175,6 +175,18 @@ struct swe_ctx {
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
+    // split-precision Legendre tables (REXI_PREC_BF16_SPLIT): Pbar and H as bf16
+    // (hi, lo) pairs in a latitude-major (synthesis) and a degree-major
+    // (analysis) layout; order m starts at tab_off[m], each (m, parity) block
+    // has tab_kp[2m + parity] rows (padded to 16) by tab_hpad latitudes
+    unsigned short* d_tab_psyn = nullptr;
+    unsigned short* d_tab_hsyn = nullptr;
+    unsigned short* d_tab_pana = nullptr;
+    unsigned short* d_tab_hana = nullptr;
+    long long* d_tab_off = nullptr;   // [L+2]
+    int* d_tab_kp = nullptr;          // [2 (L+1)]
+    int tab_hpad = 0, tab_kmax = 0;
+    size_t tab_len = 0;               // shorts per table
     double* d_tmpA = nullptr;         // Strang intermediates [3][modes]
     double* d_tmpB = nullptr;
 };
@@ -207,6 +219,15 @@ int launch_legendre_synth(swe_ctx* ctx, int kind, const double* spec, double* pa
 int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                          const double* Nprev, double* Nsave, double* out, double c0, double c1,
                          hipStream_t stream);
+// Split-precision (bf16 hi/lo, matrix-core) Legendre stage: tables and the two
+// directions.  The synthesis writes the Fourier coefficients [nf][nlat][L+1]
+// directly (no segment partials).
+int build_split_tables(swe_ctx* ctx, hipStream_t stream);
+int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, double* four, int nf,
+                                hipStream_t stream);
+int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
+                               const double* Nprev, double* Nsave, double* out, double c0, double c1,
+                               hipStream_t stream);
 // Sums segment partials and transposes them to [nf][nlat][L+1].
 int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
