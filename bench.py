@@ -140,6 +140,53 @@ def _oracle_chunk(args):
     return len(orders)
 
 
+PEAK_BF16_MFMA = 2500.0    # TFLOP/s, dense bf16 matrix cores
+
+
+def _split_blocks(L, nlat):
+    hpad = (nlat // 2 + 15) // 16 * 16
+    rows = 0
+    for m in range(L + 1):
+        Lm = L - m + 1
+        rows += ((Lm + 1) // 2 + 15) // 16 * 16 + (Lm // 2 + 15) // 16 * 16
+    return hpad, rows
+
+
+def split_mfma_flops(L, nlat):
+    """Matrix-core flops of one split-precision Legendre launch of the non-linear
+    set (Pbar and H products, three bf16 products each, 16x16x16 tiles incl. padding)."""
+    hpad, rows = _split_blocks(L, nlat)
+    return 2 * 3 * (hpad // 16) * (rows // 16) * 2 * 16 * 16 * 16
+
+
+def split_table_bytes(L, nlat):
+    """Bytes of the two tables (Pbar, H; hi and lo) one such launch streams."""
+    hpad, rows = _split_blocks(L, nlat)
+    return 2 * rows * hpad * 2 * 2
+
+
+def step_error_vs_fp64(ctx, w, alpha, beta):
+    """Per-field error of one step of this workload against the same step in FP64
+    (FP64 solves and transforms; that path matches the FP64 oracle to 1e-12)."""
+    import torch
+
+    from paper_1805_06557_amd import api
+    from paper_1805_06557_amd.inputs import jet_state
+
+    U0 = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
+    got = torch.empty_like(U0)
+    ctx.strang_step(alpha, beta, w.dt, U0, got)
+    ref_ctx = api.SWE(w.L, w.nlat, w.nlon, prec=0)
+    ref = torch.empty_like(U0)
+    ref_ctx.strang_step(alpha, beta, w.dt, U0, ref)
+    g, r = got.cpu().numpy(), ref.cpu().numpy()
+    ref_ctx.close()
+    out = {"state": _field_errors(g, r)}
+    u0 = U0.cpu().numpy()
+    out["increment"] = _field_errors(g - u0, r - u0)
+    return out
+
+
 def _timed(fn, reps, stream):
     import torch
     start = torch.cuda.Event(enable_timing=True)
@@ -247,7 +294,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="T255-fp32")
+    ap.add_argument("--workload", default="T255-fp32-bf16")
     ap.add_argument("--stage", choices=["auto", "rexi"], default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -387,6 +434,23 @@ def main():
         "kernels": stage_ms,
         "setup": {"rexi_factor_kernel_ms": fact_ms / max(fact_n, 1), "launches": fact_n},
     }
+    if full and w.prec:
+        out["step_error_vs_fp64_path"] = step_error_vs_fp64(ctx, w, alpha, beta)
+    if full and (w.prec & api.PREC_BF16_SPLIT):
+        syn = stage_ms["legendre_synth_kernel"]["ms_per_launch"]
+        ana = stage_ms["legendre_anal_kernel"]["ms_per_launch"]
+        fl = split_mfma_flops(w.L, w.nlat)
+        out["legendre_mfma"] = {
+            "precision": "bf16 hi/lo split, 3 products, FP32 accumulation",
+            "mfma_flops_per_launch": fl,
+            "synth_TFLOP_s": fl / (syn * 1e-3) / 1e12, "anal_TFLOP_s": fl / (ana * 1e-3) / 1e12,
+            "peak_TFLOP_s": PEAK_BF16_MFMA,
+            "synth_frac": fl / (syn * 1e-3) / 1e12 / PEAK_BF16_MFMA,
+            "anal_frac": fl / (ana * 1e-3) / 1e12 / PEAK_BF16_MFMA,
+            "table_bytes_per_launch": split_table_bytes(w.L, w.nlat),
+            "synth_GB_s": split_table_bytes(w.L, w.nlat) / (syn * 1e-3) / 1e9,
+            "anal_GB_s": split_table_bytes(w.L, w.nlat) / (ana * 1e-3) / 1e9,
+        }
     ctx.close()
     if not args.no_arms:
         out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2))

@@ -153,6 +153,9 @@ int setup_sht(swe_ctx* ctx) {
         ctx->tab_len = static_cast<size_t>(off[ctx->L + 1]);
         if ((rc = upload(&ctx->d_tab_kp, kp.data(), kp.size())) != REXI_OK) return rc;
         if ((rc = upload(&ctx->d_tab_off, off.data(), off.size())) != REXI_OK) return rc;
+        std::vector<int> segid(ctx->L + 2);
+        for (int m = 0; m <= ctx->L + 1; ++m) segid[m] = m;
+        if ((rc = upload(&ctx->d_tab_segid, segid.data(), segid.size())) != REXI_OK) return rc;
         for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_hsyn, &ctx->d_tab_pana, &ctx->d_tab_hana})
             if (hipMalloc(reinterpret_cast<void**>(t), sizeof(unsigned short) * ctx->tab_len) != hipSuccess)
                 return fail(REXI_ENOMEM, "swe_create: cannot allocate the split-precision Legendre tables");
@@ -207,8 +210,12 @@ bool split_legendre(const swe_ctx* ctx) { return (ctx->prec & REXI_PREC_BF16_SPL
 // Spectral fields -> Fourier coefficients [nf][nlat][L+1] in ctx->d_fin.
 int to_fourier(swe_ctx* ctx, int kind, const double* spec, int nf, hipStream_t stream) {
     const int nfo = kind == 0 ? nf : 4;
-    if (split_legendre(ctx)) return launch_legendre_synth_split(ctx, kind, spec, ctx->d_fin, nf, stream);
-    int rc = launch_legendre_synth(ctx, kind, spec, ctx->d_part, nf, stream);
+    int rc;
+    if (split_legendre(ctx)) {
+        if ((rc = launch_legendre_synth_split(ctx, kind, spec, ctx->d_part, nf, stream)) != REXI_OK) return rc;
+        return launch_gather_fourier_with(ctx, ctx->d_part, ctx->d_fin, nfo, ctx->d_tab_segid, ctx->L + 1, stream);
+    }
+    rc = launch_legendre_synth(ctx, kind, spec, ctx->d_part, nf, stream);
     if (rc != REXI_OK) return rc;
     return launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, nfo, stream);
 }
@@ -285,10 +292,10 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     }
     if (prec & ~(REXI_PREC_FP32_SOLVE | REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT))
         return fail(REXI_EINVAL, "swe_create: unknown precision flags");
-    if (prec & REXI_PREC_FP16_SPLIT)
-        return fail(REXI_ENOTSUP, "swe_create: the FP16 split Legendre stage is not built (BF16 split is)");
     if ((prec & REXI_PREC_BF16_SPLIT) && (prec & REXI_PREC_FP16_SPLIT))
         return fail(REXI_EINVAL, "swe_create: BF16 and FP16 Legendre modes are exclusive");
+    if (prec & REXI_PREC_FP16_SPLIT)
+        return fail(REXI_ENOTSUP, "swe_create: the FP16 split Legendre stage is not built (BF16 split is)");
 
     swe_ctx* ctx = new (std::nothrow) swe_ctx;
     if (!ctx) return fail(REXI_ENOMEM, "swe_create: out of host memory");
@@ -347,7 +354,7 @@ int swe_destroy(swe_ctx* ctx) {
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
-                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp};
+                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {

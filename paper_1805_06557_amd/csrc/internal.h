@@ -184,6 +184,7 @@ struct swe_ctx {
     unsigned short* d_tab_pana = nullptr;
     unsigned short* d_tab_hana = nullptr;
     long long* d_tab_off = nullptr;   // [L+2]
+    int* d_tab_segid = nullptr;       // [L+2] m: one Fourier row per order
     int* d_tab_kp = nullptr;          // [2 (L+1)]
     int tab_hpad = 0, tab_kmax = 0;
     size_t tab_len = 0;               // shorts per table
@@ -221,7 +222,7 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
                          hipStream_t stream);
 // Split-precision (bf16 hi/lo, matrix-core) Legendre stage: tables and the two
 // directions.  The synthesis writes the Fourier coefficients [nf][nlat][L+1]
-// directly (no segment partials).
+// [nf][L+1][nlat] (one row per order, gathered like segment partials).
 int build_split_tables(swe_ctx* ctx, hipStream_t stream);
 int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, double* four, int nf,
                                 hipStream_t stream);
@@ -230,6 +231,9 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
                                hipStream_t stream);
 // Sums segment partials and transposes them to [nf][nlat][L+1].
 int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream);
+// The same with another segmentation (segbase[m] .. segbase[m+1] - 1 are the rows of order m).
+int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
+                               hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
                 hipStream_t stream);

@@ -785,10 +785,15 @@ __global__ __launch_bounds__(256) void gather_fourier_kernel(const double2* __re
 }  // namespace
 
 int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream) {
+    return launch_gather_fourier_with(ctx, part, four, nf, ctx->d_segbase, ctx->nseg, stream);
+}
+
+int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
+                               hipStream_t stream) {
     const dim3 grid((ctx->nlat + GJ - 1) / GJ, (ctx->L + 1 + GM - 1) / GM, nf);
     const int slot = prof_begin(ctx, REXI_KERNEL_GATHER, stream);
     hipLaunchKernelGGL(gather_fourier_kernel, grid, dim3(256), 0, stream, reinterpret_cast<const double2*>(part),
-                       reinterpret_cast<double2*>(four), ctx->d_segbase, ctx->L, ctx->nlat, ctx->nseg);
+                       reinterpret_cast<double2*>(four), segbase, ctx->L, ctx->nlat, nseg);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_GATHER, slot, stream);
     return REXI_OK;

@@ -8,9 +8,10 @@
 // The degrees of each parity of l - m form their own row block (the southern
 // hemisphere follows from Pbar(-mu) = (-1)^{l-m} Pbar(mu), H with the opposite
 // sign), so a 16-row tile is all even or all odd.  T is tabulated once per
-// context in two layouts (latitude-major for the synthesis, degree-major for
-// the analysis) so that each lane's four consecutive K values of an MFMA
-// operand are one 16-byte load.  Every value x is stored as x_hi = bf16(x),
+// context in two layouts, each in MFMA operand order (synthesis: M = latitude,
+// K = degree; analysis: M = degree, K = latitude): every (tile, K step) is a
+// contiguous block of 64 lanes x 16 bytes, so a wave reads one operand with one
+// coalesced 1 KB load.  Every value x is stored as x_hi = bf16(x),
 // x_lo = bf16(x - x_hi), interleaved in groups of four (hi[4], lo[4]); a
 // product is accumulated in FP32 as a_hi b_hi + a_hi b_lo + a_lo b_hi with
 // v_mfma_f32_16x16x16_bf16 (relative error about 2^-16 per product, plus FP32
@@ -87,20 +88,24 @@ __global__ __launch_bounds__(256) void leg_table_kernel(TabArgs A) {
         const int K = par ? ko : ke;
         const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
         unsigned short hi, lo;
-        // synthesis layout: row j (length 2 K), element r
-        const long long ps = blk + static_cast<long long>(j) * 2 * K;
+        // operand order: each (tile, K step) holds 64 lanes x (hi[4], lo[4]), so a
+        // wave's operand load is one contiguous 1 KB read
+        // synthesis (M = latitude j, K = row r): lane (j % 16) + 16 ((r % 16) / 4), element r % 4
+        const long long ps = blk + ((static_cast<long long>(j >> 4) * (K >> 4) + (r >> 4)) * 64 +
+                                    (j & 15) + 16 * ((r & 15) >> 2)) * 8 + (r & 3);
+        // analysis (M = row r, K = latitude j): lane (r % 16) + 16 ((j % 16) / 4), element j % 4
+        const long long pa = blk + ((static_cast<long long>(r >> 4) * (A.hpad >> 4) + (j >> 4)) * 64 +
+                                    (r & 15) + 16 * ((j & 15) >> 2)) * 8 + (j & 3);
         split_bf16(pv, hi, lo);
-        A.p_syn[ps + grp_hi(r)] = hi;
-        A.p_syn[ps + grp_lo(r)] = lo;
-        // analysis layout: row r (length 2 hpad), element j
-        const long long pa = blk + static_cast<long long>(r) * 2 * A.hpad;
-        A.p_ana[pa + grp_hi(j)] = hi;
-        A.p_ana[pa + grp_lo(j)] = lo;
+        A.p_syn[ps] = hi;
+        A.p_syn[ps + 4] = lo;
+        A.p_ana[pa] = hi;
+        A.p_ana[pa + 4] = lo;
         split_bf16(hv, hi, lo);
-        A.h_syn[ps + grp_hi(r)] = hi;
-        A.h_syn[ps + grp_lo(r)] = lo;
-        A.h_ana[pa + grp_hi(j)] = hi;
-        A.h_ana[pa + grp_lo(j)] = lo;
+        A.h_syn[ps] = hi;
+        A.h_syn[ps + 4] = lo;
+        A.h_ana[pa] = hi;
+        A.h_ana[pa + 4] = lo;
         pm = p;
         p = pn;
     }
@@ -133,7 +138,7 @@ struct MfmaArgs {
     double a;
     // synthesis
     const double2* __restrict__ spec;   // KIND 0: [nf][modes]; KIND 1: state [3][modes]
-    double2* __restrict__ four_out;     // [nfo][nlat][L+1]
+    double2* __restrict__ four_out;     // [nfo][L+1][nlat]
     // analysis
     const double2* __restrict__ four_in;  // [nfi][nlat][L+1]
     double2* __restrict__ spec_out;       // KIND 0: [nf][modes]
@@ -161,20 +166,24 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     unsigned short* xh = xs + 2 * 16 * rowlen;      // KIND 1 only
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
-    // stage: every (parity, row, column) entry, zero where no degree or column
-    const int nent = 2 * A.kmax * 16;
-    for (int t = threadIdx.x; t < nent; t += blockDim.x) {
-        const int c = t & 15, rp = t >> 4;
+    // stage: one thread per (parity, row) forms the row's 16 columns, zero where
+    // there is no degree or column
+    for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
         const int par = rp / A.kmax, r = rp - par * A.kmax;
         const int i = 2 * r + par;                  // l - m
-        double vp = 0.0, vh = 0.0;
+        double vp[16], vh[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) vp[c] = vh[c] = 0.0;
         if (i < Lm) {
             const int l = m + i;
             if constexpr (KIND == 0) {
-                const int f = f0 + (c >> 1);
-                if (f < A.nf) {
-                    const double2 s = A.spec[static_cast<size_t>(f) * A.modes + base + i];
-                    vp = (c & 1) ? s.y : s.x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (f0 + q < A.nf) {
+                        const double2 v = A.spec[static_cast<size_t>(f0 + q) * A.modes + base + i];
+                        vp[2 * q] = v.x;
+                        vp[2 * q + 1] = v.y;
+                    }
                 }
             } else {
                 const double2 ch = A.spec[base + i];
@@ -183,35 +192,38 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                 const double aon = A.aon[l], maon = dm * aon;
                 // Pbar columns: h, zeta, U_P = -i delta m a/N, V_P = -i zeta m a/N
                 // H columns (at the U, V positions): U_H = zeta a/N, V_H = -delta a/N
-                switch (c) {
-                    case 0: vp = ch.x; break;
-                    case 1: vp = ch.y; break;
-                    case 2: vp = cz.x; break;
-                    case 3: vp = cz.y; break;
-                    case 4: vp = cd.y * maon; vh = cz.x * aon; break;
-                    case 5: vp = -cd.x * maon; vh = cz.y * aon; break;
-                    case 6: vp = cz.y * maon; vh = -cd.x * aon; break;
-                    case 7: vp = -cz.x * maon; vh = -cd.y * aon; break;
-                    default: break;
-                }
+                vp[0] = ch.x;
+                vp[1] = ch.y;
+                vp[2] = cz.x;
+                vp[3] = cz.y;
+                vp[4] = cd.y * maon;
+                vp[5] = -cd.x * maon;
+                vp[6] = cz.y * maon;
+                vp[7] = -cz.x * maon;
+                vh[4] = cz.x * aon;
+                vh[5] = cz.y * aon;
+                vh[6] = -cd.x * aon;
+                vh[7] = -cd.y * aon;
             }
         }
-        unsigned short hi, lo;
-        const int o = (par * 16 + c) * rowlen;
-        split_bf16(vp, hi, lo);
-        xp[o + grp_hi(r)] = hi;
-        xp[o + grp_lo(r)] = lo;
-        if constexpr (KIND == 1) {
-            split_bf16(vh, hi, lo);
-            xh[o + grp_hi(r)] = hi;
-            xh[o + grp_lo(r)] = lo;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            unsigned short hi, lo;
+            const int o = (par * 16 + c) * rowlen;
+            split_bf16(vp[c], hi, lo);
+            xp[o + grp_hi(r)] = hi;
+            xp[o + grp_lo(r)] = lo;
+            if constexpr (KIND == 1) {
+                split_bf16(vh[c], hi, lo);
+                xh[o + grp_hi(r)] = hi;
+                xh[o + grp_lo(r)] = lo;
+            }
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int tile = blockIdx.y * 4 + threadIdx.x / WAVE;
     if (tile * 16 >= A.hpad) return;
-    const int jrow = tile * 16 + (lane & 15);       // A-operand latitude of this lane
     const int kq = lane >> 4;                       // K quarter of this lane
     f32x4 accP[2], accH[2];
     for (int par = 0; par < 2; ++par) {
@@ -219,38 +231,41 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
         accH[par] = f32x4{0.f, 0.f, 0.f, 0.f};
         const int K = par ? ko : ke;
         const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-        const unsigned short* ap = A.p_syn + blk + static_cast<long long>(jrow) * 2 * K;
-        const unsigned short* ah = A.h_syn + blk + static_cast<long long>(jrow) * 2 * K;
+        // operand blocks of this latitude tile: 64 lanes x 8 shorts per K step
+        const unsigned short* ap = A.p_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
+        const unsigned short* ah = A.h_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
         const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
         const unsigned short* bh = xh + (par * 16 + (lane & 15)) * rowlen;
-        for (int r0 = 0; r0 < K; r0 += 16) {
-            const int g = (r0 >> 2) + kq;           // group of four rows for this lane
-            const uint4 a = *reinterpret_cast<const uint4*>(ap + 8 * g);
+        for (int ks = 0; ks < (K >> 4); ++ks) {
+            const int g = 4 * ks + kq;              // group of four rows for this lane
+            const uint4 a = *reinterpret_cast<const uint4*>(ap + ks * 512);
             const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
             mfma3(accP[par], a, b);
             if constexpr (KIND == 1) {
-                const uint4 a2 = *reinterpret_cast<const uint4*>(ah + 8 * g);
+                const uint4 a2 = *reinterpret_cast<const uint4*>(ah + ks * 512);
                 const uint4 b2 = *reinterpret_cast<const uint4*>(bh + 8 * g);
                 mfma3(accH[par], a2, b2);
             }
         }
     }
-    // lane holds column c = lane % 16 of rows (latitudes) 4 (lane / 16) + t
+    // lane holds column c = lane % 16 of rows (latitudes) 4 (lane / 16) + t; the
+    // imaginary part (odd column) moves to the real part's lane, which writes the
+    // complex value into row (field, m) of the Fourier buffer [nfo][L+1][nlat]
     const int c = lane & 15;
-    const int fl = c >> 1, part = c & 1;
-    const int f = KIND == 0 ? f0 + fl : fl;
-    const bool col_ok = KIND == 0 ? (f < A.nf) : (c < 8);
-    if (!col_ok) return;
-    double* fo = reinterpret_cast<double*>(A.four_out);
+    const int f = KIND == 0 ? f0 + (c >> 1) : (c >> 1);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int j = tile * 16 + 4 * kq + t;
-        if (j >= A.half) continue;
         const float e = accP[0][t] + accH[1][t], o = accP[1][t] + accH[0][t];   // even, odd in mu
-        const size_t rn = (static_cast<size_t>(f) * A.nlat + j) * (A.L + 1) + m;
-        const size_t rs = (static_cast<size_t>(f) * A.nlat + (A.nlat - 1 - j)) * (A.L + 1) + m;
-        fo[2 * rn + part] = static_cast<double>(e) + static_cast<double>(o);
-        fo[2 * rs + part] = static_cast<double>(e) - static_cast<double>(o);
+        const double vn = static_cast<double>(e) + static_cast<double>(o);
+        const double vs = static_cast<double>(e) - static_cast<double>(o);
+        const double vn_im = __shfl(vn, lane + 1 < WAVE ? lane + 1 : lane);
+        const double vs_im = __shfl(vs, lane + 1 < WAVE ? lane + 1 : lane);
+        const int j = tile * 16 + 4 * kq + t;
+        const bool col_ok = (c & 1) == 0 && (KIND == 0 ? (f < A.nf) : (c < 8));
+        if (!col_ok || j >= A.half) continue;
+        double2* row = A.four_out + (static_cast<size_t>(f) * (A.L + 1) + m) * A.nlat;
+        row[j] = make_double2(vn, vn_im);
+        row[A.nlat - 1 - j] = make_double2(vs, vs_im);
     }
 }
 
@@ -277,10 +292,11 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
     unsigned short* yh = ys + 2 * 16 * rowlen;      // KIND 1 only
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
-    const int nent = A.hpad * 16;
-    for (int t = threadIdx.x; t < nent; t += blockDim.x) {
-        const int c = t & 15, j = t >> 4;
-        double sp = 0.0, dp = 0.0, sh = 0.0, dh = 0.0;   // P columns (fold S, D), H columns (fold S, D)
+    // stage: one thread per northern latitude forms its 16 columns for both folds
+    for (int j = threadIdx.x; j < A.hpad; j += blockDim.x) {
+        double sp[16], dp[16], sh[16], dh[16];   // Pbar columns (fold S, D), H columns (fold S, D)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sp[c] = dp[c] = sh[c] = dh[c] = 0.0;
         if (j < A.half) {
             const double wj = A.w[j];
             auto fold = [&](int f, double wt, double2& S, double2& D) {
@@ -291,99 +307,110 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
                 D = make_double2((nn.x - ss.x) * wt, (nn.y - ss.y) * wt);
             };
             if constexpr (KIND == 0) {
-                const int f = f0 + (c >> 1);
-                if (f < A.nf) {
-                    double2 S, D;
-                    fold(f, wj, S, D);
-                    sp = (c & 1) ? S.y : S.x;
-                    dp = (c & 1) ? D.y : D.x;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (f0 + q < A.nf) {
+                        double2 S, D;
+                        fold(f0 + q, wj, S, D);
+                        sp[2 * q] = S.x;
+                        sp[2 * q + 1] = S.y;
+                        dp[2 * q] = D.x;
+                        dp[2 * q + 1] = D.y;
+                    }
                 }
-            } else if (c < 8) {
+            } else {
                 const double wdiv = wj / (A.a * A.sint[j] * A.sint[j]);
-                double2 S, D;
-                switch (c) {
-                    case 0: fold(0, wdiv, S, D); sp = dm * S.y; dp = dm * D.y; fold(1, wdiv, S, D); sh = S.x; dh = D.x; break;
-                    case 1: fold(0, wdiv, S, D); sp = -dm * S.x; dp = -dm * D.x; fold(1, wdiv, S, D); sh = S.y; dh = D.y; break;
-                    case 2: fold(2, wdiv, S, D); sp = dm * S.y; dp = dm * D.y; fold(3, wdiv, S, D); sh = S.x; dh = D.x; break;
-                    case 3: fold(2, wdiv, S, D); sp = -dm * S.x; dp = -dm * D.x; fold(3, wdiv, S, D); sh = S.y; dh = D.y; break;
-                    case 4: fold(3, wdiv, S, D); sp = -dm * S.y; dp = -dm * D.y; fold(2, wdiv, S, D); sh = S.x; dh = D.x; break;
-                    case 5: fold(3, wdiv, S, D); sp = dm * S.x; dp = dm * D.x; fold(2, wdiv, S, D); sh = S.y; dh = D.y; break;
-                    case 6: fold(4, wj, S, D); sp = S.x; dp = D.x; break;
-                    default: fold(4, wj, S, D); sp = S.y; dp = D.y; break;
-                }
+                double2 hUs, hUd, hVs, hVd, zUs, zUd, zVs, zVd, kes, ked;
+                fold(0, wdiv, hUs, hUd);
+                fold(1, wdiv, hVs, hVd);
+                fold(2, wdiv, zUs, zUd);
+                fold(3, wdiv, zVs, zVd);
+                fold(4, wj, kes, ked);
+                sp[0] = dm * hUs.y;  dp[0] = dm * hUd.y;  sh[0] = hVs.x; dh[0] = hVd.x;
+                sp[1] = -dm * hUs.x; dp[1] = -dm * hUd.x; sh[1] = hVs.y; dh[1] = hVd.y;
+                sp[2] = dm * zUs.y;  dp[2] = dm * zUd.y;  sh[2] = zVs.x; dh[2] = zVd.x;
+                sp[3] = -dm * zUs.x; dp[3] = -dm * zUd.x; sh[3] = zVs.y; dh[3] = zVd.y;
+                sp[4] = -dm * zVs.y; dp[4] = -dm * zVd.y; sh[4] = zUs.x; dh[4] = zUd.x;
+                sp[5] = dm * zVs.x;  dp[5] = dm * zVd.x;  sh[5] = zUs.y; dh[5] = zUd.y;
+                sp[6] = kes.x;       dp[6] = ked.x;
+                sp[7] = kes.y;       dp[7] = ked.y;
             }
         }
-        unsigned short hi, lo;
-        const int o0 = c * rowlen, o1 = (16 + c) * rowlen;
-        split_bf16(sp, hi, lo);
-        yp[o0 + grp_hi(j)] = hi;
-        yp[o0 + grp_lo(j)] = lo;
-        split_bf16(dp, hi, lo);
-        yp[o1 + grp_hi(j)] = hi;
-        yp[o1 + grp_lo(j)] = lo;
-        if constexpr (KIND == 1) {
-            split_bf16(sh, hi, lo);
-            yh[o0 + grp_hi(j)] = hi;
-            yh[o0 + grp_lo(j)] = lo;
-            split_bf16(dh, hi, lo);
-            yh[o1 + grp_hi(j)] = hi;
-            yh[o1 + grp_lo(j)] = lo;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            unsigned short hi, lo;
+            const int o0 = c * rowlen, o1 = (16 + c) * rowlen;
+            split_bf16(sp[c], hi, lo);
+            yp[o0 + grp_hi(j)] = hi;
+            yp[o0 + grp_lo(j)] = lo;
+            split_bf16(dp[c], hi, lo);
+            yp[o1 + grp_hi(j)] = hi;
+            yp[o1 + grp_lo(j)] = lo;
+            if constexpr (KIND == 1) {
+                split_bf16(sh[c], hi, lo);
+                yh[o0 + grp_hi(j)] = hi;
+                yh[o0 + grp_lo(j)] = lo;
+                split_bf16(dh[c], hi, lo);
+                yh[o1 + grp_hi(j)] = hi;
+                yh[o1 + grp_lo(j)] = lo;
+            }
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
-    const int tile = blockIdx.y * 4 + threadIdx.x / WAVE;
     const int te = ke / 16, to = ko / 16;
-    if (tile >= te + to) return;
-    const int par = tile < te ? 0 : 1;
-    const int r0 = (par ? tile - te : tile) * 16;
-    const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-    const int kq = lane >> 4;
-    const unsigned short* ap = A.p_ana + blk + static_cast<long long>(r0 + (lane & 15)) * 2 * A.hpad;
-    const unsigned short* ah = A.h_ana + blk + static_cast<long long>(r0 + (lane & 15)) * 2 * A.hpad;
-    // Pbar of parity par pairs with fold par; H (opposite parity) with fold 1 - par
-    const unsigned short* bp = yp + (par * 16 + (lane & 15)) * rowlen;
-    const unsigned short* bh = yh + ((1 - par) * 16 + (lane & 15)) * rowlen;
-    f32x4 accP = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
-    for (int j0 = 0; j0 < A.hpad; j0 += 16) {
-        const int g = (j0 >> 2) + kq;
-        const uint4 a = *reinterpret_cast<const uint4*>(ap + 8 * g);
-        const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
-        mfma3(accP, a, b);
-        if constexpr (KIND == 1) {
-            const uint4 a2 = *reinterpret_cast<const uint4*>(ah + 8 * g);
-            const uint4 b2 = *reinterpret_cast<const uint4*>(bh + 8 * g);
-            mfma3(accH, a2, b2);
+    for (int tile = threadIdx.x / WAVE; tile < te + to; tile += 4) {
+        const int par = tile < te ? 0 : 1;
+        const int r0 = (par ? tile - te : tile) * 16;
+        const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
+        const int kq = lane >> 4;
+        // operand blocks of this row tile: 64 lanes x 8 shorts per K step
+        const unsigned short* ap = A.p_ana + blk + (static_cast<long long>(r0 >> 4) * (A.hpad >> 4) * 64 + lane) * 8;
+        const unsigned short* ah = A.h_ana + blk + (static_cast<long long>(r0 >> 4) * (A.hpad >> 4) * 64 + lane) * 8;
+        // Pbar of parity par pairs with fold par; H (opposite parity) with fold 1 - par
+        const unsigned short* bp = yp + (par * 16 + (lane & 15)) * rowlen;
+        const unsigned short* bh = yh + ((1 - par) * 16 + (lane & 15)) * rowlen;
+        f32x4 accP = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
+        for (int js = 0; js < (A.hpad >> 4); ++js) {
+            const int g = 4 * js + kq;
+            const uint4 a = *reinterpret_cast<const uint4*>(ap + js * 512);
+            const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
+            mfma3(accP, a, b);
+            if constexpr (KIND == 1) {
+                const uint4 a2 = *reinterpret_cast<const uint4*>(ah + js * 512);
+                const uint4 b2 = *reinterpret_cast<const uint4*>(bh + 8 * g);
+                mfma3(accH, a2, b2);
+            }
         }
-    }
-    const int c = lane & 15;
-    float ke_t[4];
-    if constexpr (KIND == 1) {
-        // the KE columns 6, 7 are added to columns 4, 5 (same rows, two lanes up)
+        const int c = lane & 15;
+        float ke_t[4];
+        if constexpr (KIND == 1) {
+            // the KE columns 6, 7 are added to columns 4, 5 (same rows, two lanes up)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) ke_t[t] = __shfl(accP[t], lane + 2 < WAVE ? lane + 2 : lane);
-    }
+            for (int t = 0; t < 4; ++t) ke_t[t] = __shfl(accP[t], lane + 2 < WAVE ? lane + 2 : lane);
+        }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int r = r0 + 4 * kq + t;
-        const int i = 2 * r + par;                  // l - m
-        if (i >= Lm) continue;
-        const size_t idx = static_cast<size_t>(base) + i;
-        if constexpr (KIND == 0) {
-            const int f = f0 + (c >> 1);
-            if (f >= A.nf) continue;
-            reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + idx)[c & 1] =
-                static_cast<double>(accP[t]);
-        } else {
-            if (c >= 6) continue;
-            double v = static_cast<double>(accP[t]) + static_cast<double>(accH[t]);
-            if (c >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(ke_t[t]), v);
-            const int f = c >> 1, part = c & 1;
-            const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-            double o = __builtin_fma(A.c0, v, reinterpret_cast<const double*>(A.U0)[e2]);
-            if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
-            if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
-            reinterpret_cast<double*>(A.out)[e2] = o;
+        for (int t = 0; t < 4; ++t) {
+            const int r = r0 + 4 * kq + t;
+            const int i = 2 * r + par;                  // l - m
+            if (i >= Lm) continue;
+            const size_t idx = static_cast<size_t>(base) + i;
+            if constexpr (KIND == 0) {
+                const int f = f0 + (c >> 1);
+                if (f >= A.nf) continue;
+                reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + idx)[c & 1] =
+                    static_cast<double>(accP[t]);
+            } else {
+                if (c >= 6) continue;
+                double v = static_cast<double>(accP[t]) + static_cast<double>(accH[t]);
+                if (c >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(ke_t[t]), v);
+                const int f = c >> 1, part = c & 1;
+                const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
+                double o = __builtin_fma(A.c0, v, reinterpret_cast<const double*>(A.U0)[e2]);
+                if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
+                if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
+                reinterpret_cast<double*>(A.out)[e2] = o;
+            }
         }
     }
 }
@@ -487,8 +514,7 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     A.c1 = c1;
     A.nf = nf;
     const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.hpad) * (kind == 0 ? 1 : 2);
-    const int maxtiles = 2 * (A.kmax / 16);
-    const dim3 grid(ctx->L + 1, (maxtiles + 3) / 4, kind == 0 ? (nf + 7) / 8 : 1);
+    const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
     const void* fn = kind == 0 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0>)
                                : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1>);
