@@ -198,6 +198,25 @@ int swe_sync(swe_ctx* ctx);
 const char* rexi_last_error(void);
 
 /*
+ * swe_etdrk2_step -- one step of l_rexi_n_etdrk, the second-order exponential
+ * time differencing Runge-Kutta scheme (Section 4.3, Eq. etdrk) with
+ * L = L_g + L_c applied through REXI and N explicit:
+ *   A  = psi_0(dt L) U0 + dt psi_1(dt L) N(U0)
+ *   U1 = A + dt psi_2(dt L) (N(A) - N(U0)),
+ * psi_0 = exp, psi_1(K) = K^-1 (exp(K) - I), psi_2(K) = K^-2 (exp(K) - I - K).
+ * alpha: the poles of one contour; beta0, beta1, beta2: the weights of psi_0,
+ * psi_1, psi_2 on it (rexi_coefficients with REXI_FN_EXP, REXI_FN_PSI1,
+ * REXI_FN_PSI2 and the same N, p0, y); host arrays of 2N doubles.  U0, U1:
+ * device states [3][modes]; U1 may equal U0.  Two non-linear evaluations and
+ * three REXI stages; the three coefficient sets stay cached in the context.
+ * Errors: REXI_ENOTSUP for a linear-only context, REXI_EINVAL, REXI_ENUMERIC,
+ * REXI_ENOMEM, REXI_EDEVICE.
+ */
+int swe_etdrk2_step(swe_ctx* ctx, const double* alpha, const double* beta0, const double* beta1,
+                    const double* beta2, int N, double dt, const double* U0, double* U1,
+                    hipStream_t stream);
+
+/*
  * Per-kernel timing (tracing).  swe_profile(ctx, 1) starts recording a HIP
  * event pair on the launch stream around every launch of the given kernels
  * (up to 4096 launches per kernel between reads); swe_profile(ctx, 0) stops.

@@ -112,6 +112,25 @@ def expm_step(U0: np.ndarray, dt: float, L: int, p: Params = Params()) -> np.nda
     return U1
 
 
+def psi_step(U0: np.ndarray, dt: float, L: int, k: int, p: Params = Params()) -> np.ndarray:
+    """psi_k(dt L) U0 for k = 1, 2 (psi_1(K) = K^-1 (e^K - I), psi_2(K) = K^-2 (e^K - I - K),
+    Section 4.3) by one dense exponential per zonal order of the augmented matrix
+    [[dt A, b, 0], [0, 0, 1], [0, 0, 0]], whose exponential carries psi_1(dt A) b and
+    psi_2(dt A) b in its last two columns (energy-scaled unknowns as in expm_step)."""
+    U1 = np.zeros_like(U0, dtype=np.complex128)
+    for m in range(L + 1):
+        d = energy_scale(m, L, p)
+        B = d[:, None] * operator_matrix(m, L, p) / d[None, :]
+        n = B.shape[0]
+        M = np.zeros((n + 2, n + 2), dtype=np.complex128)
+        M[:n, :n] = dt * B
+        M[:n, n] = d * gather_m(U0, m, L)
+        M[n, n + 1] = 1.0
+        E = scipy.linalg.expm(M)
+        scatter_m(U1, E[:n, n + k - 1] / d, m, L)
+    return U1
+
+
 def cn_step(U0: np.ndarray, dt: float, L: int, p: Params = Params(), a: float = 0.5) -> np.ndarray:
     """Crank-Nicolson (Section 4.1): (I - a dt L)^{-1} (I + (1 - a) dt L) U0."""
     U1 = np.zeros_like(U0, dtype=np.complex128)

@@ -61,6 +61,18 @@ def strang_ver1(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta: n
     return heun(grid, U, 0.5 * dt)
 
 
+def etdrk2(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta0: np.ndarray, beta1: np.ndarray,
+           beta2: np.ndarray) -> np.ndarray:
+    """One step of l_rexi_n_etdrk (Section 4.3, Eq. etdrk), the matrix functions
+    psi_0, psi_1, psi_2 of dt L applied through their REXI sums on one contour:
+      A = psi_0(dt L) U + dt psi_1(dt L) N(U),  U1 = A + dt psi_2(dt L) (N(A) - N(U))."""
+    L, p = grid.L, grid.p
+    N0 = tendency(grid, U)
+    A = linear.rexi_linear_step(U, alpha, beta0, dt, L, p) + dt * linear.rexi_linear_step(N0, alpha, beta1, dt, L, p)
+    NA = tendency(grid, A)
+    return A + dt * linear.rexi_linear_step(NA - N0, alpha, beta2, dt, L, p)
+
+
 def full_tendency(grid: Grid, U: np.ndarray) -> np.ndarray:
     """(L + N)(U): the whole right-hand side of Eq. (sw_compact)."""
     from .operator import apply

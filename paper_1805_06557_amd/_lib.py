@@ -30,6 +30,7 @@ SIGNATURES = {
     "sh_analysis": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
     "swe_nonlinear_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),
     "swe_strang_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
+    "swe_etdrk2_step": (_c_int, [_vp, _dp, _dp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "swe_sync": (_c_int, [_vp]),
     "rexi_last_error": (ctypes.c_char_p, []),
     "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),

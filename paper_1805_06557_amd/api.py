@@ -160,6 +160,16 @@ class SWE:
                                          _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
                                          _stream_handle(stream)), "swe_strang_step")
 
+    def etdrk2_step(self, alpha, beta0, beta1, beta2, dt: float, U0, U1, stream=None) -> None:
+        """One l_rexi_n_etdrk step; beta0/1/2: the psi_0/1/2 weights on the contour alpha."""
+        a = _host_coeffs(alpha)
+        b = [_host_coeffs(x) for x in (beta0, beta1, beta2)]
+        if any(x.size != a.size for x in b):
+            raise ValueError("alpha and the beta sets differ in length")
+        _check(self._lib.swe_etdrk2_step(self._h, _dptr(a), _dptr(b[0]), _dptr(b[1]), _dptr(b[2]), a.size // 2,
+                                         float(dt), _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                         _stream_handle(stream)), "swe_etdrk2_step")
+
     def profile(self, enable: bool) -> None:
         _check(self._lib.swe_profile(self._h, 1 if enable else 0), "swe_profile")
 

@@ -62,10 +62,18 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     key = fnv1a(alpha, sizeof(double) * 2 * N, key);
     key = fnv1a(beta, sizeof(double) * 2 * N, key);
     key = fnv1a(&N, sizeof(N), key);
-    if (ctx->poles_valid && key == ctx->poles_key && N == ctx->poles_n && dt == ctx->poles_dt)
-        return REXI_OK;
-    ctx->poles_valid = false;
-    ctx->fact_valid = false;
+    key = fnv1a(&dt, sizeof(dt), key);
+    ++ctx->pole_clock;
+    PoleSet* slot = nullptr;
+    for (PoleSet& ps : ctx->pole_sets) {
+        if (ps.valid && ps.key == key && ps.n == N) {
+            ps.used = ctx->pole_clock;
+            ctx->d_poles = ps.d;
+            ctx->poles_key = key;
+            return REXI_OK;
+        }
+        if (!slot || !ps.valid || (slot->valid && ps.used < slot->used)) slot = &ps;
+    }
 
     std::vector<PoleData> pd(N);
     build_pole_data(alpha, beta, N, pd.data());
@@ -89,21 +97,26 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     if (!(min_distance_to_segment(pd.data(), N, rho) > 1e-6 * (1.0 + rho)))
         return fail(REXI_ENUMERIC, "rexi_linear_step: a pole lies on the spectrum of dt L");
 
-    if (N > ctx->poles_cap) {
-        if (ctx->d_poles) REXI_HIP(hipFree(ctx->d_poles));
-        ctx->d_poles = nullptr;
-        ctx->poles_cap = 0;
-        if (hipMalloc(&ctx->d_poles, sizeof(PoleData) * N) != hipSuccess)
+    // replace the least recently used set; the device may still read it, so wait
+    if (slot->valid) REXI_HIP(hipStreamSynchronize(stream));
+    slot->valid = false;
+    if (N > slot->cap) {
+        if (slot->d) REXI_HIP(hipFree(slot->d));
+        slot->d = nullptr;
+        slot->cap = 0;
+        if (hipMalloc(&slot->d, sizeof(PoleData) * N) != hipSuccess)
             return fail(REXI_ENOMEM, "rexi_linear_step: cannot allocate pole table");
-        ctx->poles_cap = N;
+        slot->cap = N;
     }
     // The host vector dies at return: copy synchronously with respect to the host.
-    REXI_HIP(hipMemcpyAsync(ctx->d_poles, pd.data(), sizeof(PoleData) * N, hipMemcpyHostToDevice, stream));
+    REXI_HIP(hipMemcpyAsync(slot->d, pd.data(), sizeof(PoleData) * N, hipMemcpyHostToDevice, stream));
     REXI_HIP(hipStreamSynchronize(stream));
+    slot->key = key;
+    slot->n = N;
+    slot->valid = true;
+    slot->used = ctx->pole_clock;
+    ctx->d_poles = slot->d;
     ctx->poles_key = key;
-    ctx->poles_n = N;
-    ctx->poles_dt = dt;
-    ctx->poles_valid = true;
     return REXI_OK;
 }
 
@@ -228,6 +241,15 @@ int from_fourier(swe_ctx* ctx, int kind, double* spec, int nf, const double* U0,
     return launch_legendre_anal(ctx, kind, ctx->d_fout, spec, nf, U0, Nprev, Nsave, out, c0, c1, stream);
 }
 
+// Nout = N(U): one evaluation of the non-linear tendency.
+int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t stream) {
+    int rc;
+    if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
+    if ((rc = to_fourier(ctx, 1, U, 3, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    return from_fourier(ctx, 1, nullptr, 0, nullptr, nullptr, nullptr, Nout, 1.0, 0.0, stream);
+}
+
 int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
@@ -344,7 +366,8 @@ int swe_destroy(swe_ctx* ctx) {
     DeviceGuard guard(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->d_coef) (void)hipFree(ctx->d_coef);
-    if (ctx->d_poles) (void)hipFree(ctx->d_poles);
+    for (PoleSet& ps : ctx->pole_sets)
+        if (ps.d) (void)hipFree(ps.d);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
     if (ctx->d_rows) (void)hipFree(ctx->d_rows);
     if (ctx->d_fact) (void)hipFree(ctx->d_fact);
@@ -550,6 +573,40 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N
     if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
     return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
+}
+
+int swe_etdrk2_step(swe_ctx* ctx, const double* alpha, const double* beta0, const double* beta1,
+                    const double* beta2, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_etdrk2_step: NULL context");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_etdrk2_step: linear-only context (no grid)");
+    if (!alpha || !beta0 || !beta1 || !beta2 || !U0 || !U1) return fail(REXI_EINVAL, "swe_etdrk2_step: NULL pointer");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "swe_etdrk2_step: N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_etdrk2_step: dt must be positive");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "swe_etdrk2_step: cannot select the context's device");
+    // dt psi_1 and dt psi_2 as sums with the weights scaled by dt
+    std::vector<double> b1(2 * static_cast<size_t>(N)), b2(2 * static_cast<size_t>(N));
+    for (int i = 0; i < 2 * N; ++i) {
+        b1[i] = dt * beta1[i];
+        b2[i] = dt * beta2[i];
+    }
+    const int n = 6 * ctx->modes;
+    int rc;
+    // N0 = N(U0)
+    if ((rc = tendency_eval(ctx, U0, ctx->d_n0, stream)) != REXI_OK) return rc;
+    // A = psi_0(dt L) U0 + dt psi_1(dt L) N0
+    if ((rc = prepare_poles(ctx, alpha, beta0, N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = launch_rexi_solve(ctx, N, dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
+    if ((rc = prepare_poles(ctx, alpha, b1.data(), N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_n0, ctx->d_tmpB, stream)) != REXI_OK) return rc;
+    if ((rc = launch_axpy(ctx->d_tmpA, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, stream)) != REXI_OK) return rc;
+    // D = N(A) - N0
+    if ((rc = tendency_eval(ctx, ctx->d_tmpA, ctx->d_ustar, stream)) != REXI_OK) return rc;
+    if ((rc = launch_axpy(ctx->d_ustar, ctx->d_ustar, -1.0, ctx->d_n0, n, stream)) != REXI_OK) return rc;
+    // U1 = A + dt psi_2(dt L) D
+    if ((rc = prepare_poles(ctx, alpha, b2.data(), N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_ustar, ctx->d_tmpB, stream)) != REXI_OK) return rc;
+    return launch_axpy(U1, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, stream);
 }
 
 int swe_profile(swe_ctx* ctx, int enable) {

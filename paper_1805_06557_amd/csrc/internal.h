@@ -104,6 +104,15 @@ struct Profiler {
 int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream);
 void prof_end(swe_ctx* ctx, int kernel, int slot, hipStream_t stream);
 
+// One cached coefficient set on the device.
+struct PoleSet {
+    PoleData* d = nullptr;
+    int cap = 0, n = 0;
+    uint64_t key = 0;              // hash of alpha, beta, N and dt
+    bool valid = false;
+    unsigned long long used = 0;   // last use, for replacement
+};
+
 struct Tuning {
     int solver = REXI_SOLVER_FUSED;   // sweep schedule (REXI_SOLVER_*)
     int seg_rows = 16;                // rows per register-resident segment (8, 16, 32)
@@ -122,13 +131,14 @@ struct swe_ctx {
     // REXI tables
     rexi::ModeCoef* d_coef = nullptr;  // [modes]
 
-    // cached coefficient set
+    // cached coefficient sets (a few, so that schemes alternating between
+    // several sums on one contour, such as ETD2RK's psi_0, psi_1, psi_2, do not
+    // re-upload); d_poles / poles_key name the active one
+    static constexpr int kPoleSets = 4;
+    rexi::PoleSet pole_sets[kPoleSets];
+    unsigned long long pole_clock = 0;
     rexi::PoleData* d_poles = nullptr;
-    int poles_cap = 0;
-    int poles_n = 0;
     uint64_t poles_key = 0;
-    double poles_dt = 0;
-    bool poles_valid = false;
 
     // chain-ordered row records of the REXI solve, rebuilt per call [2 modes]
     void* d_rows = nullptr;
@@ -138,6 +148,7 @@ struct swe_ctx {
     void* d_fact = nullptr;
     size_t fact_cap = 0;
     bool fact_valid = false;
+    uint64_t fact_key = 0;      // coefficient set (and dt) the pivots belong to
     int fact_prec = 0;          // 1: FP32 pivots, 2: FP64 pivots
     // device copy of the last ensemble launched with this context first
     void* batch = nullptr;
@@ -234,6 +245,8 @@ int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf
 // The same with another segmentation (segbase[m] .. segbase[m+1] - 1 are the rows of order m).
 int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
                                hipStream_t stream);
+// out = x + a y over n doubles (out may equal x or y).
+int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
                 hipStream_t stream);

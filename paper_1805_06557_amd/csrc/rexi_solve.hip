@@ -614,7 +614,7 @@ int reserve_factors(swe_ctx* ctx, const SolveArgs& A) {
 template <typename T>
 int build_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
     const int tprec = std::is_same<T, float>::value ? 1 : 2;
-    if (ctx->fact_valid && ctx->fact_prec == tprec) return REXI_OK;
+    if (ctx->fact_valid && ctx->fact_prec == tprec && ctx->fact_key == ctx->poles_key) return REXI_OK;
     const int threads = 256;
     const int fpb = (A.npad + threads - 1) / threads;
     const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * fpb);
@@ -624,6 +624,7 @@ int build_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_FACTOR, slot, stream);
     ctx->fact_valid = true;
+    ctx->fact_key = ctx->poles_key;
     ctx->fact_prec = tprec;
     return REXI_OK;
 }

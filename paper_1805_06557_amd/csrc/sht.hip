@@ -249,7 +249,7 @@ struct AnaArgs {
     const double2* __restrict__ four;   // [nf][nlat][L+1]
     double2* __restrict__ spec;         // KIND 0: [nf][modes]
     // KIND 1 epilogue
-    const double2* __restrict__ U0;     // [3][modes]
+    const double2* __restrict__ U0;     // [3][modes] or nullptr (zero)
     const double2* __restrict__ Nprev;  // [3][modes] or nullptr
     double2* __restrict__ Nsave;        // [3][modes] or nullptr
     double2* __restrict__ out;          // [3][modes]
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
                 } else {
                     const int f = k >> 1, part = k & 1;
                     const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-                    double v = __builtin_fma(P.c0, s, reinterpret_cast<const double*>(P.U0)[e2]);
+                    double v = __builtin_fma(P.c0, s, P.U0 ? reinterpret_cast<const double*>(P.U0)[e2] : 0.0);
                     if (P.Nprev) v = __builtin_fma(P.c1, reinterpret_cast<const double*>(P.Nprev)[e2], v);
                     if (P.Nsave) reinterpret_cast<double*>(P.Nsave)[e2] = s;
                     reinterpret_cast<double*>(P.out)[e2] = v;
@@ -796,6 +796,20 @@ int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, i
                        reinterpret_cast<double2*>(four), segbase, ctx->L, ctx->nlat, nseg);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_GATHER, slot, stream);
+    return REXI_OK;
+}
+
+namespace {
+// out = x + a y over n doubles (spectral-state combinations of the time steppers).
+__global__ __launch_bounds__(256) void axpy_kernel(double* out, const double* x, double a, const double* y, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = __builtin_fma(a, y[i], x[i]);
+}
+}  // namespace
+
+int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, out, x, a, y, n);
+    REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
 

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
                 if (c >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(ke_t[t]), v);
                 const int f = c >> 1, part = c & 1;
                 const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-                double o = __builtin_fma(A.c0, v, reinterpret_cast<const double*>(A.U0)[e2]);
+                double o = __builtin_fma(A.c0, v, A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0);
                 if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
                 if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
                 reinterpret_cast<double*>(A.out)[e2] = o;

@@ -10,6 +10,9 @@
 * m = 0 coefficients of a real field stay real; energy is conserved to the
   REXI error.
 """
+import cmath
+import math
+
 import numpy as np
 import pytest
 
@@ -132,3 +135,35 @@ def test_crank_nicolson_nonrotating_amplification():
     amp = (1 + 0.5j * w * dt) / (1 - 0.5j * w * dt)
     np.testing.assert_allclose(out[:, idx], amp * V[:, idx], rtol=1e-13)
     assert np.all(np.isfinite(got))
+
+
+def _psi(k, z):
+    """psi_1, psi_2 at a scalar (series near 0, where dt L has its zero eigenvalues)."""
+    if abs(z) < 1e-3:
+        return sum(z ** j / math.factorial(j + k) for j in range(8))
+    e = cmath.exp(z)
+    return (e - 1) / z if k == 1 else (e - 1 - z) / (z * z)
+
+
+@pytest.mark.parametrize("fn,k", [(rexi.FN_PSI1, 1), (rexi.FN_PSI2, 2)])
+def test_psi_sums_against_augmented_expm(fn, k):
+    """The REXI sums of psi_1, psi_2 applied through the banded solves reproduce
+    psi_k(dt L) U0 from the augmented-matrix exponential (an independent
+    definition), at T8, to the scalar error of the sum plus its rounding floor."""
+    L, dt, N, p0, y = 8, 3600.0, 128, 10.0, 30.0
+    p = Params()
+    alpha, beta, _, _ = rexi.coefficients(fn, N, p0, y)
+    U0 = random_state(L, 6)
+    got = linear.rexi_linear_step(U0, alpha, beta, dt, L, p)
+    ref = linear.psi_step(U0, dt, L, k, p)
+    # scalar error of the psi_k sum at the eigenvalues of dt L
+    worst = 0.0
+    for m in range(L + 1):
+        ev = np.linalg.eigvals(dt * op.operator_matrix(m, L, p))
+        f = np.array([_psi(k, complex(e)) for e in ev])
+        worst = max(worst, float(np.abs(rexi.rexi_sum(alpha, beta, ev) - f).max()))
+    err = np.sqrt(_energy(got - ref, L, p) / _energy(U0, L, p))
+    floor = 16 * np.finfo(float).eps * rexi.kappa(alpha, beta, 0.0)[0]
+    assert err <= 1.01 * worst + floor, (err, worst, floor)
+    # and psi_k is not exp: the two differ by O(1)
+    assert np.sqrt(_energy(got - linear.expm_step(U0, dt, L, p), L, p) / _energy(U0, L, p)) > 1e-2

@@ -118,3 +118,29 @@ def test_strang_ver1_second_order():
     e1 = np.abs(run(2)[0] - ref[0]).max()
     e2 = np.abs(run(4)[0] - ref[0]).max()
     assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+def test_etdrk2_second_order():
+    """l_rexi_n_etdrk (Section 4.3) converges at second order to an RK4 reference."""
+    L = 8
+    p = Params()
+    g = _grid(L)
+    U = random_state(L, 4, amps=(50.0, 2e-5, 2e-6))
+    T = 2 * 3600.0
+    ref = nonlinear.rk4(g, U, T / 160, 160)
+
+    def run(n):
+        dt = T / n
+        rho = spectral_radius_bound(L, dt, p)
+        y = 1.5 * rho + 2.0
+        a, b0, _, _ = rexi.coefficients(rexi.FN_EXP, 128, 8.0, y)
+        _, b1, _, _ = rexi.coefficients(rexi.FN_PSI1, 128, 8.0, y)
+        _, b2, _, _ = rexi.coefficients(rexi.FN_PSI2, 128, 8.0, y)
+        V = U.copy()
+        for _ in range(n):
+            V = nonlinear.etdrk2(g, V, dt, a, b0, b1, b2)
+        return V
+
+    e1 = np.abs(run(2)[0] - ref[0]).max()
+    e2 = np.abs(run(4)[0] - ref[0]).max()
+    assert 3.0 < e1 / e2 < 5.0, (e1, e2)
