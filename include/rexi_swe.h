@@ -198,6 +198,32 @@ int swe_sync(swe_ctx* ctx);
 const char* rexi_last_error(void);
 
 /*
+ * swe_cn_step -- the Crank-Nicolson step of the linear part (Section 4.1,
+ * the implicit baseline ``irk``): U1 = (I - dt/2 L)^-1 (I + dt/2 L) U0 with
+ * L = L_g + L_c, computed as -U0 + 4 (2 I - dt L)^-1 U0 by the same banded
+ * chain solve with one real shift.  U0, U1: device states [3][modes], must
+ * not overlap.  Errors: REXI_EINVAL, REXI_ENOMEM, REXI_EDEVICE.
+ */
+int swe_cn_step(swe_ctx* ctx, double dt, const double* U0, double* U1, hipStream_t stream);
+
+/*
+ * swe_split_step -- one Strang-split step of the full equations (Section 4.4)
+ * with the non-linear part by Heun (``erk``):
+ *   REXI_SPLIT_REXI_V1  l_rexi_n_erk_ver1: N^{dt/2} o REXI^{dt} o N^{dt/2}
+ *   REXI_SPLIT_REXI_V0  l_rexi_n_erk_ver0: REXI^{dt/2} o N^{dt} o REXI^{dt/2}
+ *   REXI_SPLIT_CN_V1    l_irk_n_erk_ver1:  N^{dt/2} o CN^{dt} o N^{dt/2}
+ *   REXI_SPLIT_CN_V0    l_irk_n_erk_ver0:  CN^{dt/2} o N^{dt} o CN^{dt/2}
+ * For the REXI schemes alpha, beta (host, 2N doubles) must approximate exp on
+ * the spectrum of the linear step's length (dt for version 1, dt/2 for
+ * version 0); the CN schemes ignore them (they may be NULL).  U1 may equal U0.
+ * Errors: REXI_ENOTSUP for a linear-only context, REXI_EINVAL, REXI_ENUMERIC,
+ * REXI_ENOMEM, REXI_EDEVICE.
+ */
+enum { REXI_SPLIT_REXI_V1 = 0, REXI_SPLIT_REXI_V0 = 1, REXI_SPLIT_CN_V1 = 2, REXI_SPLIT_CN_V0 = 3 };
+int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* beta, int N, double dt,
+                   const double* U0, double* U1, hipStream_t stream);
+
+/*
  * swe_etdrk2_step -- one step of l_rexi_n_etdrk, the second-order exponential
  * time differencing Runge-Kutta scheme (Section 4.3, Eq. etdrk) with
  * L = L_g + L_c applied through REXI and N explicit:

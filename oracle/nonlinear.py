@@ -61,6 +61,22 @@ def strang_ver1(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta: n
     return heun(grid, U, 0.5 * dt)
 
 
+def split_step(grid: Grid, U: np.ndarray, dt: float, version: int, alpha=None, beta=None) -> np.ndarray:
+    """One Strang-split step (Section 4.4) with Heun for N and, for the linear
+    part, the REXI sum (alpha, beta given) or Crank-Nicolson (alpha None):
+    version 1: N^{dt/2} o L^{dt} o N^{dt/2};  version 0: L^{dt/2} o N^{dt} o L^{dt/2}."""
+    L, p = grid.L, grid.p
+
+    def lin(V, h):
+        if alpha is None:
+            return linear.cn_step(V, h, L, p)
+        return linear.rexi_linear_step(V, alpha, beta, h, L, p)
+
+    if version == 1:
+        return heun(grid, lin(heun(grid, U, 0.5 * dt), dt), 0.5 * dt)
+    return lin(heun(grid, lin(U, 0.5 * dt), dt), 0.5 * dt)
+
+
 def etdrk2(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta0: np.ndarray, beta1: np.ndarray,
            beta2: np.ndarray) -> np.ndarray:
     """One step of l_rexi_n_etdrk (Section 4.3, Eq. etdrk), the matrix functions

@@ -31,6 +31,8 @@ SIGNATURES = {
     "swe_nonlinear_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),
     "swe_strang_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "swe_etdrk2_step": (_c_int, [_vp, _dp, _dp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
+    "swe_cn_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),
+    "swe_split_step": (_c_int, [_vp, _c_int, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "swe_sync": (_c_int, [_vp]),
     "rexi_last_error": (ctypes.c_char_p, []),
     "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),

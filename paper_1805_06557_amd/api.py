@@ -17,6 +17,7 @@ FN_EXP, FN_PSI1, FN_PSI2 = 0, 1, 2
 PREC_FP64, PREC_FP32_SOLVE, PREC_BF16_SPLIT, PREC_FP16_SPLIT = 0, 1, 2, 4
 KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_GATHER, KERNEL_FACTOR = range(7)
 SOLVER_FUSED, SOLVER_STREAM, SOLVER_HYBRID = 1, 2, 3
+SPLIT_REXI_V1, SPLIT_REXI_V0, SPLIT_CN_V1, SPLIT_CN_V0 = 0, 1, 2, 3
 EARTH = dict(a=6.37122e6, g=9.80616, H=1.0e4, Omega=7.292e-5)
 
 
@@ -159,6 +160,24 @@ class SWE:
         _check(self._lib.swe_strang_step(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt),
                                          _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
                                          _stream_handle(stream)), "swe_strang_step")
+
+    def cn_step(self, dt: float, U0, U1, stream=None) -> None:
+        """Crank-Nicolson step of the linear part (U0 and U1 must differ)."""
+        _check(self._lib.swe_cn_step(self._h, float(dt), _state_ptr(U0, self.L, 3, "U0"),
+                                     _state_ptr(U1, self.L, 3, "U1"), _stream_handle(stream)), "swe_cn_step")
+
+    def split_step(self, scheme: int, alpha, beta, dt: float, U0, U1, stream=None) -> None:
+        """One Strang-split step (SPLIT_*); alpha, beta may be None for the CN schemes."""
+        if alpha is None:
+            a = b = None
+            N = 0
+        else:
+            a, b = _host_coeffs(alpha), _host_coeffs(beta)
+            N = a.size // 2
+        _check(self._lib.swe_split_step(self._h, int(scheme), None if a is None else _dptr(a),
+                                        None if b is None else _dptr(b), N, float(dt),
+                                        _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                        _stream_handle(stream)), "swe_split_step")
 
     def etdrk2_step(self, alpha, beta0, beta1, beta2, dt: float, U0, U1, stream=None) -> None:
         """One l_rexi_n_etdrk step; beta0/1/2: the psi_0/1/2 weights on the contour alpha."""

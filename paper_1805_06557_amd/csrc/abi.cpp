@@ -54,6 +54,49 @@ struct DeviceGuard {
     }
 };
 
+// Uploads a coefficient set into the cache slot and makes it the active one.
+int activate_poles(swe_ctx* ctx, PoleSet* slot, const PoleData* pd, int N, uint64_t key, hipStream_t stream) {
+    // replace the least recently used set; the device may still read it, so wait
+    if (slot->valid) REXI_HIP(hipStreamSynchronize(stream));
+    slot->valid = false;
+    if (N > slot->cap) {
+        if (slot->d) REXI_HIP(hipFree(slot->d));
+        slot->d = nullptr;
+        slot->cap = 0;
+        if (hipMalloc(&slot->d, sizeof(PoleData) * N) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi_linear_step: cannot allocate pole table");
+        slot->cap = N;
+    }
+    // The host vector dies at return: copy synchronously with respect to the host.
+    REXI_HIP(hipMemcpyAsync(slot->d, pd, sizeof(PoleData) * N, hipMemcpyHostToDevice, stream));
+    REXI_HIP(hipStreamSynchronize(stream));
+    slot->key = key;
+    slot->n = N;
+    slot->valid = true;
+    slot->used = ctx->pole_clock;
+    ctx->d_poles = slot->d;
+    ctx->poles_key = key;
+    return REXI_OK;
+}
+
+// The cache slot for a new set: the least recently used one (or an empty one).
+PoleSet* pole_slot(swe_ctx* ctx, uint64_t key, int N, bool& hit) {
+    ++ctx->pole_clock;
+    PoleSet* slot = nullptr;
+    hit = false;
+    for (PoleSet& ps : ctx->pole_sets) {
+        if (ps.valid && ps.key == key && ps.n == N) {
+            ps.used = ctx->pole_clock;
+            ctx->d_poles = ps.d;
+            ctx->poles_key = key;
+            hit = true;
+            return &ps;
+        }
+        if (!slot || !ps.valid || (slot->valid && ps.used < slot->used)) slot = &ps;
+    }
+    return slot;
+}
+
 // Uploads (alpha, beta) if they differ from the cached set and checks that the
 // poles enclose the spectrum of dt L.
 int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
@@ -63,17 +106,9 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     key = fnv1a(beta, sizeof(double) * 2 * N, key);
     key = fnv1a(&N, sizeof(N), key);
     key = fnv1a(&dt, sizeof(dt), key);
-    ++ctx->pole_clock;
-    PoleSet* slot = nullptr;
-    for (PoleSet& ps : ctx->pole_sets) {
-        if (ps.valid && ps.key == key && ps.n == N) {
-            ps.used = ctx->pole_clock;
-            ctx->d_poles = ps.d;
-            ctx->poles_key = key;
-            return REXI_OK;
-        }
-        if (!slot || !ps.valid || (slot->valid && ps.used < slot->used)) slot = &ps;
-    }
+    bool hit = false;
+    PoleSet* slot = pole_slot(ctx, key, N, hit);
+    if (hit) return REXI_OK;
 
     std::vector<PoleData> pd(N);
     build_pole_data(alpha, beta, N, pd.data());
@@ -97,27 +132,7 @@ int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, 
     if (!(min_distance_to_segment(pd.data(), N, rho) > 1e-6 * (1.0 + rho)))
         return fail(REXI_ENUMERIC, "rexi_linear_step: a pole lies on the spectrum of dt L");
 
-    // replace the least recently used set; the device may still read it, so wait
-    if (slot->valid) REXI_HIP(hipStreamSynchronize(stream));
-    slot->valid = false;
-    if (N > slot->cap) {
-        if (slot->d) REXI_HIP(hipFree(slot->d));
-        slot->d = nullptr;
-        slot->cap = 0;
-        if (hipMalloc(&slot->d, sizeof(PoleData) * N) != hipSuccess)
-            return fail(REXI_ENOMEM, "rexi_linear_step: cannot allocate pole table");
-        slot->cap = N;
-    }
-    // The host vector dies at return: copy synchronously with respect to the host.
-    REXI_HIP(hipMemcpyAsync(slot->d, pd.data(), sizeof(PoleData) * N, hipMemcpyHostToDevice, stream));
-    REXI_HIP(hipStreamSynchronize(stream));
-    slot->key = key;
-    slot->n = N;
-    slot->valid = true;
-    slot->used = ctx->pole_clock;
-    ctx->d_poles = slot->d;
-    ctx->poles_key = key;
-    return REXI_OK;
+    return activate_poles(ctx, slot, pd.data(), N, key, stream);
 }
 
 template <typename T>
@@ -248,6 +263,28 @@ int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t strea
     if ((rc = to_fourier(ctx, 1, U, 3, stream)) != REXI_OK) return rc;
     if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
     return from_fourier(ctx, 1, nullptr, 0, nullptr, nullptr, nullptr, Nout, 1.0, 0.0, stream);
+}
+
+// Crank-Nicolson over tau: (I - tau/2 L)^-1 (I + tau/2 L) U0 = -U0 + 4 (2 - tau L)^-1 U0,
+// one real shift z = 2 with weight 4 on the chain solve.  U0 and U1 must differ.
+int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
+    uint64_t key = 0x43726e6b4e69636fULL;            // a tag no coefficient hash is expected to hit
+    key = fnv1a(&tau, sizeof(tau), key);
+    bool hit = false;
+    PoleSet* slot = pole_slot(ctx, key, 1, hit);
+    int rc;
+    if (!hit) {
+        PoleData pd{};
+        pd.zr = 2.0;
+        pd.zi = 0.0;
+        pd.zir = 0.5;
+        pd.zii = 0.0;
+        pd.wr = 4.0;
+        pd.wi = 0.0;
+        if ((rc = activate_poles(ctx, slot, &pd, 1, key, stream)) != REXI_OK) return rc;
+    }
+    if ((rc = launch_rexi_solve(ctx, 1, tau, U0, U1, stream)) != REXI_OK) return rc;
+    return launch_axpy(U1, U1, -1.0, U0, 6 * ctx->modes, stream);
 }
 
 int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
@@ -573,6 +610,51 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N
     if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
     return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
+}
+
+int swe_cn_step(swe_ctx* ctx, double dt, const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_cn_step: NULL context");
+    if (!U0 || !U1) return fail(REXI_EINVAL, "swe_cn_step: NULL pointer");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_cn_step: dt must be positive");
+    const size_t bytes = sizeof(double) * 6 * ctx->modes;
+    const char* a0 = reinterpret_cast<const char*>(U0);
+    const char* a1 = reinterpret_cast<const char*>(U1);
+    if (a0 < a1 + bytes && a1 < a0 + bytes) return fail(REXI_EINVAL, "swe_cn_step: U0 and U1 overlap");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "swe_cn_step: cannot select the context's device");
+    return cn_linear(ctx, dt, U0, U1, stream);
+}
+
+int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* beta, int N, double dt,
+                   const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_split_step: NULL context");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_split_step: linear-only context (no grid)");
+    if (scheme < REXI_SPLIT_REXI_V1 || scheme > REXI_SPLIT_CN_V0)
+        return fail(REXI_EINVAL, "swe_split_step: unknown scheme");
+    const bool rexi = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_REXI_V0;
+    const bool v1 = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_CN_V1;
+    if (!U0 || !U1 || (rexi && (!alpha || !beta))) return fail(REXI_EINVAL, "swe_split_step: NULL pointer");
+    if (rexi && (N < 2 || (N & 1) || N > (1 << 20)))
+        return fail(REXI_EINVAL, "swe_split_step: N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_split_step: dt must be positive");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "swe_split_step: cannot select the context's device");
+    const double tl = v1 ? dt : 0.5 * dt;   // step of the linear part
+    int rc;
+    auto linear = [&](const double* in, double* out) -> int {
+        if (!rexi) return cn_linear(ctx, tl, in, out, stream);
+        int r = prepare_poles(ctx, alpha, beta, N, tl, stream);
+        if (r != REXI_OK) return r;
+        return launch_rexi_solve(ctx, N, tl, in, out, stream);
+    };
+    if (v1) {
+        if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
+        if ((rc = linear(ctx->d_tmpA, ctx->d_tmpB)) != REXI_OK) return rc;
+        return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
+    }
+    if ((rc = linear(U0, ctx->d_tmpA)) != REXI_OK) return rc;
+    if ((rc = heun_step(ctx, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
+    return linear(ctx->d_tmpB, U1);
 }
 
 int swe_etdrk2_step(swe_ctx* ctx, const double* alpha, const double* beta0, const double* beta1,

@@ -144,3 +144,42 @@ def test_etdrk2_second_order():
     e1 = np.abs(run(2)[0] - ref[0]).max()
     e2 = np.abs(run(4)[0] - ref[0]).max()
     assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+@pytest.mark.parametrize("version,use_rexi", [(0, True), (1, False), (0, False)],
+                         ids=["rexi-ver0", "cn-ver1", "cn-ver0"])
+def test_split_schemes_second_order(version, use_rexi):
+    """l_rexi_n_erk_ver0 and the Crank-Nicolson splittings l_irk_n_erk_ver0/1
+    (Section 4.4) converge at second order to an RK4 reference."""
+    L = 8
+    p = Params()
+    g = _grid(L)
+    U = random_state(L, 4, amps=(50.0, 2e-5, 2e-6))
+    T = 2 * 3600.0
+    ref = nonlinear.rk4(g, U, T / 160, 160)
+
+    def run(n):
+        dt = T / n
+        tl = dt if version == 1 else 0.5 * dt
+        a = b = None
+        if use_rexi:
+            rho = spectral_radius_bound(L, tl, p)
+            a, b, _, _ = rexi.coefficients(rexi.FN_EXP, 128, 8.0, 1.5 * rho + 2.0)
+        V = U.copy()
+        for _ in range(n):
+            V = nonlinear.split_step(g, V, dt, version, a, b)
+        return V
+
+    e1 = np.abs(run(2)[0] - ref[0]).max()
+    e2 = np.abs(run(4)[0] - ref[0]).max()
+    assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+def test_split_ver1_with_rexi_is_strang_ver1():
+    L = 8
+    p = Params()
+    g = _grid(L)
+    U = random_state(L, 5, amps=(50.0, 2e-5, 2e-6))
+    rho = spectral_radius_bound(L, 1800.0, p)
+    a, b, _, _ = rexi.coefficients(rexi.FN_EXP, 64, 6.0, 1.5 * rho + 2.0)
+    assert np.array_equal(nonlinear.split_step(g, U, 1800.0, 1, a, b), nonlinear.strang_ver1(g, U, 1800.0, a, b))
