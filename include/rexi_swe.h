@@ -123,6 +123,17 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta,
                      hipStream_t stream);
 
 /*
+ * rexi_lg_step -- the REXI stage of the gravity-wave part L_g alone (Section 3:
+ * L_g couples h and delta of one degree, zeta is left alone):
+ *   U1 = sum_n beta_n (dt L_g + alpha_n)^-1 U0,
+ * computed per degree from two sums over the poles and applied per mode
+ * (no banded solve).  U1 may equal U0.  Same contour check and errors as
+ * rexi_linear_step.
+ */
+int rexi_lg_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                 const double* U0, double* U1, hipStream_t stream);
+
+/*
  * rexi_linear_step_batched -- the REXI linear stage (Section 4.2, Eq. rexi)
  * of an ensemble of independent problems, each with its own context (own
  * truncation), coefficients, pole count and dt, in one row-record launch, one
@@ -213,13 +224,18 @@ int swe_cn_step(swe_ctx* ctx, double dt, const double* U0, double* U1, hipStream
  *   REXI_SPLIT_REXI_V0  l_rexi_n_erk_ver0: REXI^{dt/2} o N^{dt} o REXI^{dt/2}
  *   REXI_SPLIT_CN_V1    l_irk_n_erk_ver1:  N^{dt/2} o CN^{dt} o N^{dt/2}
  *   REXI_SPLIT_CN_V0    l_irk_n_erk_ver0:  CN^{dt/2} o N^{dt} o CN^{dt/2}
+ *   REXI_SPLIT_LG_REXI_V1  lg_rexi_lc_n_erk_ver1: REXI on the gravity-wave part
+ *                       L_g alone (rexi_lg_step), the Coriolis part L_c joined to
+ *                       N and formed on the grid through the absolute vorticity
+ *                       (Section 3 splitting, Section 5.3 fastest REXI variant)
  * For the REXI schemes alpha, beta (host, 2N doubles) must approximate exp on
  * the spectrum of the linear step's length (dt for version 1, dt/2 for
  * version 0); the CN schemes ignore them (they may be NULL).  U1 may equal U0.
  * Errors: REXI_ENOTSUP for a linear-only context, REXI_EINVAL, REXI_ENUMERIC,
  * REXI_ENOMEM, REXI_EDEVICE.
  */
-enum { REXI_SPLIT_REXI_V1 = 0, REXI_SPLIT_REXI_V0 = 1, REXI_SPLIT_CN_V1 = 2, REXI_SPLIT_CN_V0 = 3 };
+enum { REXI_SPLIT_REXI_V1 = 0, REXI_SPLIT_REXI_V0 = 1, REXI_SPLIT_CN_V1 = 2, REXI_SPLIT_CN_V0 = 3,
+       REXI_SPLIT_LG_REXI_V1 = 4 };
 int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* beta, int N, double dt,
                    const double* U0, double* U1, hipStream_t stream);
 

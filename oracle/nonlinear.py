@@ -47,11 +47,21 @@ def tendency(grid: Grid, U: np.ndarray) -> np.ndarray:
     return out
 
 
-def heun(grid: Grid, U: np.ndarray, tau: float) -> np.ndarray:
-    """U + tau/2 (N(U) + N(U + tau N(U)))."""
-    N0 = tendency(grid, U)
-    N1 = tendency(grid, U + tau * N0)
+def heun(grid: Grid, U: np.ndarray, tau: float, tend=None) -> np.ndarray:
+    """U + tau/2 (N(U) + N(U + tau N(U))) (tend: another explicit right-hand side)."""
+    f = tendency if tend is None else tend
+    N0 = f(grid, U)
+    N1 = f(grid, U + tau * N0)
     return U + 0.5 * tau * (N0 + N1)
+
+
+def tendency_lc(grid: Grid, U: np.ndarray) -> np.ndarray:
+    """N(U) + L_c U: the explicit part when only L_g is treated by REXI (Section 3
+    splitting L = L_g + L_c); L_c is the Coriolis part of the spectral operator."""
+    from dataclasses import replace
+
+    from .operator import apply
+    return tendency(grid, U) + apply(U, grid.L, grid.p) - apply(U, grid.L, replace(grid.p, Omega=0.0))
 
 
 def strang_ver1(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta: np.ndarray) -> np.ndarray:
@@ -61,11 +71,16 @@ def strang_ver1(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta: n
     return heun(grid, U, 0.5 * dt)
 
 
-def split_step(grid: Grid, U: np.ndarray, dt: float, version: int, alpha=None, beta=None) -> np.ndarray:
+def split_step(grid: Grid, U: np.ndarray, dt: float, version: int, alpha=None, beta=None,
+               lg: bool = False) -> np.ndarray:
     """One Strang-split step (Section 4.4) with Heun for N and, for the linear
     part, the REXI sum (alpha, beta given) or Crank-Nicolson (alpha None):
-    version 1: N^{dt/2} o L^{dt} o N^{dt/2};  version 0: L^{dt/2} o N^{dt} o L^{dt/2}."""
-    L, p = grid.L, grid.p
+    version 1: N^{dt/2} o L^{dt} o N^{dt/2};  version 0: L^{dt/2} o N^{dt} o L^{dt/2}.
+    lg: the linear part is L_g alone and L_c joins N (lg_rexi_lc_n_erk_ver1)."""
+    from dataclasses import replace
+    L = grid.L
+    p = replace(grid.p, Omega=0.0) if lg else grid.p
+    tend = tendency_lc if lg else None
 
     def lin(V, h):
         if alpha is None:
@@ -73,8 +88,8 @@ def split_step(grid: Grid, U: np.ndarray, dt: float, version: int, alpha=None, b
         return linear.rexi_linear_step(V, alpha, beta, h, L, p)
 
     if version == 1:
-        return heun(grid, lin(heun(grid, U, 0.5 * dt), dt), 0.5 * dt)
-    return lin(heun(grid, lin(U, 0.5 * dt), dt), 0.5 * dt)
+        return heun(grid, lin(heun(grid, U, 0.5 * dt, tend), dt), 0.5 * dt, tend)
+    return lin(heun(grid, lin(U, 0.5 * dt), dt, tend), 0.5 * dt)
 
 
 def etdrk2(grid: Grid, U: np.ndarray, dt: float, alpha: np.ndarray, beta0: np.ndarray, beta1: np.ndarray,

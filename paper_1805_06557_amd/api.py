@@ -17,7 +17,7 @@ FN_EXP, FN_PSI1, FN_PSI2 = 0, 1, 2
 PREC_FP64, PREC_FP32_SOLVE, PREC_BF16_SPLIT, PREC_FP16_SPLIT = 0, 1, 2, 4
 KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_GATHER, KERNEL_FACTOR = range(7)
 SOLVER_FUSED, SOLVER_STREAM, SOLVER_HYBRID = 1, 2, 3
-SPLIT_REXI_V1, SPLIT_REXI_V0, SPLIT_CN_V1, SPLIT_CN_V0 = 0, 1, 2, 3
+SPLIT_REXI_V1, SPLIT_REXI_V0, SPLIT_CN_V1, SPLIT_CN_V0, SPLIT_LG_REXI_V1 = 0, 1, 2, 3, 4
 EARTH = dict(a=6.37122e6, g=9.80616, H=1.0e4, Omega=7.292e-5)
 
 
@@ -138,6 +138,14 @@ class SWE:
         _check(self._lib.rexi_linear_step(self._h, _dptr(a), _dptr(b), N, float(dt),
                                           _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
                                           _stream_handle(stream)), "rexi_linear_step")
+
+    def rexi_lg_step(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
+        """REXI stage of the gravity-wave part L_g alone (U1 may equal U0)."""
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        _check(self._lib.rexi_lg_step(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt),
+                                      _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                      _stream_handle(stream)), "rexi_lg_step")
 
     def sh_synthesis(self, spec, grid, nf: int, stream=None) -> None:
         _check(self._lib.sh_synthesis(self._h, _state_ptr(spec, self.L, nf, "spec"),

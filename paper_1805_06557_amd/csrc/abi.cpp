@@ -256,12 +256,14 @@ int from_fourier(swe_ctx* ctx, int kind, double* spec, int nf, const double* U0,
     return launch_legendre_anal(ctx, kind, ctx->d_fout, spec, nf, U0, Nprev, Nsave, out, c0, c1, stream);
 }
 
-// Nout = N(U): one evaluation of the non-linear tendency.
-int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t stream) {
+// Nout = N(U): one evaluation of the non-linear tendency (with two_omega = 2 Omega:
+// N + L_c, the Coriolis term formed on the grid through the absolute vorticity).
+int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t stream, double two_omega = 0.0) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     if ((rc = to_fourier(ctx, 1, U, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
+        return rc;
     return from_fourier(ctx, 1, nullptr, 0, nullptr, nullptr, nullptr, Nout, 1.0, 0.0, stream);
 }
 
@@ -287,17 +289,19 @@ int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     return launch_axpy(U1, U1, -1.0, U0, 6 * ctx->modes, stream);
 }
 
-int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
+int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream, double two_omega = 0.0) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
     if ((rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
+        return rc;
     if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) != REXI_OK)
         return rc;
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
     if ((rc = to_fourier(ctx, 1, ctx->d_ustar, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
+        return rc;
     return from_fourier(ctx, 1, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau, stream);
 }
 
@@ -409,6 +413,7 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_rows) (void)hipFree(ctx->d_rows);
     if (ctx->d_fact) (void)hipFree(ctx->d_fact);
     if (ctx->d_ckpt) (void)hipFree(ctx->d_ckpt);
+    if (ctx->d_lgsum) (void)hipFree(ctx->d_lgsum);
     free_batch_plan(ctx);
     void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
@@ -461,6 +466,19 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int 
     int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
     if (rc != REXI_OK) return rc;
     return launch_rexi_solve(ctx, N, dt, U0, U1, stream);
+}
+
+int rexi_lg_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt, const double* U0,
+                 double* U1, hipStream_t stream) {
+    if (!ctx) return fail(REXI_EINVAL, "rexi_lg_step: NULL context");
+    if (!alpha || !beta || !U0 || !U1) return fail(REXI_EINVAL, "rexi_lg_step: NULL pointer");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "rexi_lg_step: N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "rexi_lg_step: dt must be positive");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(REXI_EDEVICE, "rexi_lg_step: cannot select the context's device");
+    int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
+    if (rc != REXI_OK) return rc;
+    return launch_rexi_lg(ctx, N, dt, U0, U1, stream);
 }
 
 int rexi_linear_step_batched(const rexi_member* members, int count, hipStream_t stream) {
@@ -629,10 +647,12 @@ int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* 
                    const double* U0, double* U1, hipStream_t stream) {
     if (!ctx) return fail(REXI_EINVAL, "swe_split_step: NULL context");
     if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_split_step: linear-only context (no grid)");
-    if (scheme < REXI_SPLIT_REXI_V1 || scheme > REXI_SPLIT_CN_V0)
+    if (scheme < REXI_SPLIT_REXI_V1 || scheme > REXI_SPLIT_LG_REXI_V1)
         return fail(REXI_EINVAL, "swe_split_step: unknown scheme");
-    const bool rexi = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_REXI_V0;
-    const bool v1 = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_CN_V1;
+    const bool lg = scheme == REXI_SPLIT_LG_REXI_V1;
+    const bool rexi = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_REXI_V0 || lg;
+    const bool v1 = scheme == REXI_SPLIT_REXI_V1 || scheme == REXI_SPLIT_CN_V1 || lg;
+    const double two_omega = lg ? 2.0 * ctx->Omega : 0.0;   // L_c joins the explicit part
     if (!U0 || !U1 || (rexi && (!alpha || !beta))) return fail(REXI_EINVAL, "swe_split_step: NULL pointer");
     if (rexi && (N < 2 || (N & 1) || N > (1 << 20)))
         return fail(REXI_EINVAL, "swe_split_step: N must be even and in [2, 2^20]");
@@ -645,12 +665,12 @@ int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* 
         if (!rexi) return cn_linear(ctx, tl, in, out, stream);
         int r = prepare_poles(ctx, alpha, beta, N, tl, stream);
         if (r != REXI_OK) return r;
-        return launch_rexi_solve(ctx, N, tl, in, out, stream);
+        return lg ? launch_rexi_lg(ctx, N, tl, in, out, stream) : launch_rexi_solve(ctx, N, tl, in, out, stream);
     };
     if (v1) {
-        if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
+        if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream, two_omega)) != REXI_OK) return rc;
         if ((rc = linear(ctx->d_tmpA, ctx->d_tmpB)) != REXI_OK) return rc;
-        return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
+        return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream, two_omega);
     }
     if ((rc = linear(U0, ctx->d_tmpA)) != REXI_OK) return rc;
     if ((rc = heun_step(ctx, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;

@@ -150,6 +150,8 @@ struct swe_ctx {
     bool fact_valid = false;
     uint64_t fact_key = 0;      // coefficient set (and dt) the pivots belong to
     int fact_prec = 0;          // 1: FP32 pivots, 2: FP64 pivots
+    // per-degree sums of the gravity-wave REXI stage [L+2][2] complex
+    void* d_lgsum = nullptr;
     // device copy of the last ensemble launched with this context first
     void* batch = nullptr;
     // segment-start states of the chain sweeps (per launch)
@@ -245,10 +247,14 @@ int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf
 // The same with another segmentation (segbase[m] .. segbase[m+1] - 1 are the rows of order m).
 int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
                                hipStream_t stream);
+// The REXI stage of the gravity-wave part L_g alone (Coriolis-free): per degree
+// l a 2x2 system in (h, delta), zeta multiplied by S(0); the sums over poles are
+// formed once per degree.
+int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream);
 // out = x + a y over n doubles (out may equal x or y).
 int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
-                hipStream_t stream);
+                hipStream_t stream, double two_omega = 0.0);
 
 }  // namespace rexi

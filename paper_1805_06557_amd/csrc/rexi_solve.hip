@@ -932,6 +932,102 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
     return REXI_OK;
 }
 
+namespace {
+
+// REXI sums of the gravity-wave part alone.  L_g leaves zeta alone and couples
+// (h_l, delta_l) of one degree: (z - dt L_g) = [[z, dt H], [-dt gN_l, z]], gN_l =
+// g l(l+1)/a^2, so sum_n w_n (z_n - dt L_g)^-1 = [[A_l, -dt H B_l], [dt gN_l B_l, A_l]]
+// with A_l = sum w z / (z^2 + c_l), B_l = sum w / (z^2 + c_l), c_l = dt^2 H gN_l.
+// One workgroup per degree l (l = L + 1 gives S(0) = sum w / z for zeta);
+// each thread sums a strided share of the poles with compensation, then the
+// workgroup adds the 256 shares in a fixed tree.
+__global__ __launch_bounds__(256) void lg_sums_kernel(const PoleData* __restrict__ poles, int N, int L, double c1,
+                                                      double2* __restrict__ AB) {
+    __shared__ double red[4][256];
+    const int l = blockIdx.x;
+    const double c = l <= L ? c1 * l * (l + 1.0) : 0.0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0}, e[4] = {0.0, 0.0, 0.0, 0.0};
+    auto add = [&](int k, double v) {
+        const double t = s[k] + v;
+        e[k] += (fabs(s[k]) >= fabs(v)) ? (s[k] - t) + v : (v - t) + s[k];
+        s[k] = t;
+    };
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const PoleData q = poles[n];
+        // d = z^2 + c, then w / d and w z / d
+        const double dr = __builtin_fma(q.zr, q.zr, __builtin_fma(-q.zi, q.zi, c));
+        const double di = 2.0 * q.zr * q.zi;
+        const double den = __builtin_fma(dr, dr, di * di);
+        const double ir = dr / den, ii = -di / den;                 // 1 / d
+        const double br = __builtin_fma(q.wr, ir, -(q.wi * ii));    // w / d
+        const double bi = __builtin_fma(q.wr, ii, q.wi * ir);
+        const double ar = __builtin_fma(br, q.zr, -(bi * q.zi));    // w z / d
+        const double ai = __builtin_fma(br, q.zi, bi * q.zr);
+        add(0, ar);
+        add(1, ai);
+        add(2, br);
+        add(3, bi);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = s[k] + e[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        AB[2 * l] = make_double2(red[0][0], red[1][0]);
+        AB[2 * l + 1] = make_double2(red[2][0], red[3][0]);
+    }
+}
+
+// U1 = (sum over poles) U0 per mode; one workgroup per order m.  U1 may equal U0.
+__global__ __launch_bounds__(256) void lg_apply_kernel(const double2* U0, double2* U1, const double2* __restrict__ AB,
+                                                       int L, int modes, double dtH, double dtg_a2) {
+    const int m = blockIdx.x;
+    const int base = m * (2 * L + 3 - m) / 2;
+    const double2 S0 = AB[2 * (L + 1)];
+    for (int j = threadIdx.x; j < L - m + 1; j += blockDim.x) {
+        const int l = m + j, idx = base + j;
+        const double2 A = AB[2 * l], B = AB[2 * l + 1];
+        const double2 h = U0[idx], z = U0[modes + idx], d = U0[2 * modes + idx];
+        const double gn = dtg_a2 * l * (l + 1.0);                    // dt g l(l+1)/a^2
+        const double2 hb = make_double2(-dtH * B.x, -dtH * B.y);     // -dt H B
+        const double2 db = make_double2(gn * B.x, gn * B.y);         // dt gN B
+        const double2 h1 = make_double2(__builtin_fma(A.x, h.x, -(A.y * h.y)) + __builtin_fma(hb.x, d.x, -(hb.y * d.y)),
+                                        __builtin_fma(A.x, h.y, A.y * h.x) + __builtin_fma(hb.x, d.y, hb.y * d.x));
+        const double2 d1 = make_double2(__builtin_fma(db.x, h.x, -(db.y * h.y)) + __builtin_fma(A.x, d.x, -(A.y * d.y)),
+                                        __builtin_fma(db.x, h.y, db.y * h.x) + __builtin_fma(A.x, d.y, A.y * d.x));
+        const double2 z1 = make_double2(__builtin_fma(S0.x, z.x, -(S0.y * z.y)), __builtin_fma(S0.x, z.y, S0.y * z.x));
+        U1[idx] = h1;
+        U1[modes + idx] = z1;
+        U1[2 * modes + idx] = d1;
+    }
+}
+
+}  // namespace
+
+int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx->d_lgsum) {
+        if (hipMalloc(&ctx->d_lgsum, sizeof(double2) * 2 * static_cast<size_t>(ctx->L + 2)) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi_lg_step: cannot allocate the per-degree sums");
+    }
+    const double c1 = dt * dt * ctx->H * ctx->g / (ctx->a * ctx->a);
+    const int slot = prof_begin(ctx, REXI_KERNEL_SOLVE, stream);
+    hipLaunchKernelGGL(lg_sums_kernel, dim3(ctx->L + 2), dim3(256), 0, stream, ctx->d_poles, N, ctx->L, c1,
+                       reinterpret_cast<double2*>(ctx->d_lgsum));
+    REXI_HIP(hipGetLastError());
+    hipLaunchKernelGGL(lg_apply_kernel, dim3(ctx->L + 1), dim3(256), 0, stream, reinterpret_cast<const double2*>(U0),
+                       reinterpret_cast<double2*>(U1), reinterpret_cast<const double2*>(ctx->d_lgsum), ctx->L,
+                       ctx->modes, dt * ctx->H, dt * ctx->g / (ctx->a * ctx->a));
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_SOLVE, slot, stream);
+    return REXI_OK;
+}
+
 int launch_rexi_batched(const BatchMember* mem, int count, hipStream_t stream) {
     swe_ctx* c0 = mem[0].ctx;
     const Tuning t = c0->tune;

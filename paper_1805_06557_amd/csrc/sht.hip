@@ -427,6 +427,7 @@ struct RingArgs {
     const double* __restrict__ tw;     // [M] complex e^{-2 pi i k / M}
     const double* __restrict__ twr;    // [M] complex e^{-2 pi i k / nlon}
     const double* __restrict__ sint;   // [half]
+    const double* __restrict__ mu;     // [half] sin(latitude), northern
     const int* __restrict__ radix;     // [npass]
     int npass, L, nlat, nlon, half;
     const double2* __restrict__ fin;   // Fourier coefficients [nf_in][nlat][L+1]
@@ -434,6 +435,7 @@ struct RingArgs {
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
     int nf;
+    double two_omega;                  // mode 2: 2 Omega adds f = 2 Omega mu to zeta (absolute vorticity)
 };
 
 // One Stockham pass of radix R over M complex points, for narr arrays at once
@@ -712,6 +714,7 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
         const int jn = j < A.half ? j : A.nlat - 1 - j;
         const double sn = A.sint[jn];
         const double kefac = 0.5 / (sn * sn);
+        const double fcor = A.two_omega * (j < A.half ? A.mu[jn] : -A.mu[jn]);   // 0 unless L_c joins N
         double* h = reinterpret_cast<double*>(res[0]);
         double* z = reinterpret_cast<double*>(res[1]);
         const double* U = reinterpret_cast<const double*>(res[2]);
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
         double* ke = reinterpret_cast<double*>(freea[0]);
         double* hv = reinterpret_cast<double*>(freea[1]);
         for (int k = threadIdx.x; k < A.nlon; k += blockDim.x) {
-            const double u = U[k], v = V[k], hh = h[k], zz = z[k];
+            const double u = U[k], v = V[k], hh = h[k], zz = z[k] + fcor;
             ke[k] = __builtin_fma(u, u, v * v) * kefac;
             hv[k] = hh * v;
             V[k] = zz * v;          // zeta V
@@ -842,6 +845,7 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     r.tw = ctx->d_tw;
     r.twr = ctx->d_twr;
     r.sint = ctx->d_sint;
+    r.mu = ctx->d_mu;
     r.radix = ctx->d_radix;
     r.npass = ctx->npass;
     r.L = ctx->L;
@@ -955,8 +959,9 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
 }
 
 int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
-                hipStream_t stream) {
+                hipStream_t stream, double two_omega) {
     RingArgs R = ring_args(ctx);
+    R.two_omega = two_omega;
     R.fin = reinterpret_cast<const double2*>(fin);
     R.fout = reinterpret_cast<double2*>(fout);
     R.gin = gin;

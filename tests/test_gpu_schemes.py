@@ -73,3 +73,48 @@ def test_split_step(scheme):
         ctx.strang_step(a, b, dt, d0, d2)
         assert np.array_equal(d2.cpu().numpy(), got)
     ctx.close()
+
+
+@pytest.mark.parametrize("L,dt,N,p0", [(31, 3600.0, 128, 10.0), (255, 3600.0, 800, 12.0)], ids=["T31", "T255"])
+def test_rexi_lg_stage(L, dt, N, p0):
+    """The gravity-wave REXI stage (per-degree sums, no banded solve) against the
+    oracle's banded REXI solve with Omega = 0."""
+    from dataclasses import replace
+    api = _api()
+    p = Params()
+    rho = spectral_radius_bound(L, dt, p)
+    y = 30.0 if L == 31 else np.sqrt(2) * 1.05 * rho
+    a, b, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, y)
+    U0 = random_state(L, 31)
+    orders = None if L == 31 else [0, 1, 128, 255]
+    ref = olinear.rexi_linear_step(U0, a, b, dt, L, replace(p, Omega=0.0), orders=orders)
+    ctx = api.SWE(L)
+    d0 = torch.from_numpy(U0).cuda()
+    d1 = torch.empty_like(d0)
+    ctx.rexi_lg_step(a, b, dt, d0, d1)
+    got = d1.cpu().numpy()
+    kap = float(orexi.kappa(a, b, 1j * np.linspace(-rho, rho, 401)).max())
+    if orders is not None:
+        from oracle.operator import mode_index
+        idx = np.concatenate([np.arange(mode_index(L, m, m), mode_index(L, m, m) + L - m + 1) for m in orders])
+        got, ref = got[:, idx], ref[:, idx]
+    _close(got, ref, max(1e-12, 4 * U64 * kap))
+    ctx.close()
+
+
+def test_lg_split_step():
+    api = _api()
+    L, nlat, nlon, dt = 31, 48, 96, 3600.0
+    p = Params()
+    g = Grid(L, nlat, nlon, p)
+    U0 = jet_state(L, 7)
+    rho = spectral_radius_bound(L, dt, p)
+    a, b, _, _ = orexi.coefficients(orexi.FN_EXP, 128, 8.0, np.sqrt(2) * 1.05 * rho)
+    kap = float(orexi.kappa(a, b, 1j * np.linspace(-rho, rho, 401)).max())
+    ref = onl.split_step(g, U0, dt, 1, a, b, lg=True)
+    ctx = api.SWE(L, nlat, nlon)
+    d0 = torch.from_numpy(U0).cuda()
+    d1 = torch.empty_like(d0)
+    ctx.split_step(api.SPLIT_LG_REXI_V1, a, b, dt, d0, d1)
+    _close(d1.cpu().numpy(), ref, max(1e-12, 4 * U64 * kap))
+    ctx.close()

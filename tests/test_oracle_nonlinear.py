@@ -183,3 +183,50 @@ def test_split_ver1_with_rexi_is_strang_ver1():
     rho = spectral_radius_bound(L, 1800.0, p)
     a, b, _, _ = rexi.coefficients(rexi.FN_EXP, 64, 6.0, 1.5 * rho + 2.0)
     assert np.array_equal(nonlinear.split_step(g, U, 1800.0, 1, a, b), nonlinear.strang_ver1(g, U, 1800.0, a, b))
+
+
+def test_lg_split_second_order():
+    """lg_rexi_lc_n_erk_ver1 (REXI on L_g, L_c with N) converges at second order
+    to the RK4 reference of the full equations: a wrong sign or factor in the
+    Coriolis part moved to the explicit side would break it."""
+    L = 8
+    p = Params()
+    g = _grid(L)
+    U = random_state(L, 4, amps=(50.0, 2e-5, 2e-6))
+    T = 2 * 3600.0
+    ref = nonlinear.rk4(g, U, T / 160, 160)
+
+    def run(n):
+        dt = T / n
+        rho = spectral_radius_bound(L, dt, p)
+        a, b, _, _ = rexi.coefficients(rexi.FN_EXP, 128, 8.0, 1.5 * rho + 2.0)
+        V = U.copy()
+        for _ in range(n):
+            V = nonlinear.split_step(g, V, dt, 1, a, b, lg=True)
+        return V
+
+    e1 = np.abs(run(2)[0] - ref[0]).max()
+    e2 = np.abs(run(4)[0] - ref[0]).max()
+    assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+def test_grid_coriolis_matches_spectral_operator():
+    """The Coriolis part L_c U equals what the spectral operator's Omega terms
+    give (the difference of apply with and without Omega), checked against a
+    grid-space evaluation of -div(f V) and curl(f V) + nothing for h, f = 2 Omega mu."""
+    from dataclasses import replace
+
+    from oracle.operator import apply
+    from oracle.sht import inv_laplacian
+    L = 13
+    p = Params()
+    g = Grid(L, 2 * (L + 1), 4 * (L + 1), p)
+    U = random_state(L, 12)
+    lc = apply(U, L, p) - apply(U, L, replace(p, Omega=0.0))
+    Ug, Vg = g.uv_from_psichi(inv_laplacian(U[1], L, p.a), inv_laplacian(U[2], L, p.a))
+    f = 2.0 * p.Omega * g.mu[:, None]
+    div_f, curl_f = g.div_curl(f * Ug, f * Vg)
+    scale = np.abs(lc[1:]).max()
+    assert np.abs(lc[0]).max() == 0.0
+    assert np.abs(lc[1] - (-div_f)).max() <= 1e-12 * scale
+    assert np.abs(lc[2] - curl_f).max() <= 1e-12 * scale
