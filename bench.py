@@ -45,7 +45,11 @@ FLOPS_ZETA_ROW = 39
 # scaled by the same counter on a copy of known size (profiles/rexi_chain_kernel_T255_N800.md).
 # Valid only for the kernel source (sha256) and launch shape they were taken with.
 MEASURED_TRAFFIC = {
+    # the FP32 solve at T255, N = 800 (the same launch in both workloads: only the
+    # Legendre stage around it differs)
     ("T255-fp32", "01136df7fea7a723e94d772371b16096c868d86a40fd576712a466e6baeea340",
+     (1, 16, 4, 1)): 66.3e6 + 86.0e6,
+    ("T255-fp32-bf16", "01136df7fea7a723e94d772371b16096c868d86a40fd576712a466e6baeea340",
      (1, 16, 4, 1)): 66.3e6 + 86.0e6,
 }
 
@@ -251,6 +255,39 @@ def equal_error_arm(reps):
     return out
 
 
+def schemes_arm(reps):
+    """Time per step of the time-stepping schemes built on the same kernels, T255
+    on 768 x 384, dt = 3600 s, N = 800 (FP64 solves and transforms): the
+    Strang-split REXI step (L = L_g + L_c), the fast variant with REXI on L_g
+    only, Crank-Nicolson in place of REXI, and ETD2RK."""
+    import torch
+
+    from paper_1805_06557_amd import api, configs
+    from paper_1805_06557_amd.inputs import jet_state
+
+    w = configs.T255_FP64
+    a, b0, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
+    _, b1, _, _ = api.rexi_coefficients(api.FN_PSI1, w.N, w.p0, w.y)
+    _, b2, _, _ = api.rexi_coefficients(api.FN_PSI2, w.N, w.p0, w.y)
+    ctx = api.SWE(w.L, w.nlat, w.nlon, prec=0)
+    U = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
+    V = torch.empty_like(U)
+    stream = torch.cuda.current_stream()
+    runs = {
+        "l_rexi_n_erk_ver1": lambda: ctx.split_step(api.SPLIT_REXI_V1, a, b0, w.dt, U, V, stream),
+        "lg_rexi_lc_n_erk_ver1": lambda: ctx.split_step(api.SPLIT_LG_REXI_V1, a, b0, w.dt, U, V, stream),
+        "l_irk_n_erk_ver1 (Crank-Nicolson)": lambda: ctx.split_step(api.SPLIT_CN_V1, None, None, w.dt, U, V, stream),
+        "l_rexi_n_etdrk": lambda: ctx.etdrk2_step(a, b0, b1, b2, w.dt, U, V, stream),
+    }
+    out = {"workload": "T255 on 768x384, dt=3600 s, N=800 (p0=12), FP64"}
+    for name, fn in runs.items():
+        fn()
+        ms = _timed(fn, reps, stream)
+        out[name] = {"ms_per_step": ms, "sim_time_per_wall": w.dt / (ms * 1e-3)}
+    ctx.close()
+    return out
+
+
 def ensemble_arm(reps):
     """64 linear-SWE members of mixed truncation and pole count (FP32 solves):
     one fused ensemble launch (eager and replayed from a captured graph) against
@@ -360,6 +397,8 @@ def main():
     fact_ms, fact_n = ctx.profile_read(api.KERNEL_FACTOR)
     for kid in range(api.KERNEL_FACTOR):
         ctx.profile_read(kid)
+    # timed region: HIP events around the dominant kernel's launches only
+    ctx.profile_kernels([api.KERNEL_SOLVE])
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -372,6 +411,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(stop)
+    solve_ms_timed, solve_n_timed = ctx.profile_read(api.KERNEL_SOLVE)
+    # a second pass of the same steps with HIP events around every kernel launch
+    # for the per-stage breakdown (their gaps would add to a timed step)
+    ctx.profile(True)
+    for i in range(args.steps):
+        step(U, V)
+        U, V = V, U
+    torch.cuda.synchronize()
     stage_ms = {}
     for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, "sum_partials_kernel"),
                       (api.KERNEL_LEG_SYNTH, "legendre_synth_kernel"), (api.KERNEL_RING, "ring_kernel"),
@@ -379,8 +426,7 @@ def main():
         ms, n = ctx.profile_read(kid)
         stage_ms[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                           "ms_per_launch": ms / max(n, 1)}
-    solve_ms = stage_ms["rexi_chain_kernel"]["ms_per_step"] * args.steps
-    solve_n = int(round(stage_ms["rexi_chain_kernel"]["launches_per_step"] * args.steps))
+    solve_ms, solve_n = solve_ms_timed, solve_n_timed
     ctx.profile(False)
     if not torch.isfinite(torch.view_as_real(U)).all():
         print("bench.py: non-finite state after the timed steps", file=sys.stderr)
@@ -455,6 +501,7 @@ def main():
     if not args.no_arms:
         out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2))
         out["ensemble"] = ensemble_arm(max(3, args.steps // 2))
+        out["schemes"] = schemes_arm(max(3, args.steps // 4))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, full)
     print(json.dumps(out))

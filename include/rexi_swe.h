@@ -278,6 +278,9 @@ enum {
     REXI_KERNEL_COUNT = 7
 };
 int swe_profile(swe_ctx* ctx, int enable);
+/* The same for a subset: bit k of mask records kernel k (0 stops recording).
+ * Errors: REXI_EINVAL for a NULL context. */
+int swe_profile_kernels(swe_ctx* ctx, unsigned mask);
 int swe_profile_read(swe_ctx* ctx, int kernel, double* total_ms, int* launches);
 
 /*

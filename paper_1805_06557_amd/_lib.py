@@ -41,6 +41,7 @@ SIGNATURES = {
     "swe_autotune": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _c_int, _vp, _dp]),
     "rexi_linear_step_batched": (_c_int, [ctypes.POINTER(RexiMember), _c_int, _vp]),
     "swe_profile": (_c_int, [_vp, _c_int]),
+    "swe_profile_kernels": (_c_int, [_vp, ctypes.c_uint]),
     "swe_profile_read": (_c_int, [_vp, _c_int, _dp, ctypes.POINTER(_c_int)]),
 }
 

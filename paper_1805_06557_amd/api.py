@@ -200,6 +200,13 @@ class SWE:
     def profile(self, enable: bool) -> None:
         _check(self._lib.swe_profile(self._h, 1 if enable else 0), "swe_profile")
 
+    def profile_kernels(self, kernels) -> None:
+        """Record HIP events around the launches of the given kernel ids only."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << int(k)
+        _check(self._lib.swe_profile_kernels(self._h, mask), "swe_profile_kernels")
+
     def profile_read(self, kernel: int):
         """(total_ms, launches) recorded for one kernel since the last read."""
         ms = ctypes.c_double()

@@ -309,7 +309,7 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
 
 int prof_begin(swe_ctx* ctx, int kernel, hipStream_t stream) {
     Profiler& p = ctx->prof;
-    if (!p.enabled || p.count[kernel] >= Profiler::kCap) return -1;
+    if (!(p.mask & (1u << kernel)) || p.count[kernel] >= Profiler::kCap) return -1;
     const int slot = p.count[kernel];
     if (!p.start[kernel]) {
         p.start[kernel] = new (std::nothrow) hipEvent_t[Profiler::kCap]();
@@ -713,7 +713,13 @@ int swe_etdrk2_step(swe_ctx* ctx, const double* alpha, const double* beta0, cons
 
 int swe_profile(swe_ctx* ctx, int enable) {
     if (!ctx) return fail(REXI_EINVAL, "swe_profile: NULL context");
-    ctx->prof.enabled = enable != 0;
+    ctx->prof.mask = enable ? ~0u : 0u;
+    return REXI_OK;
+}
+
+int swe_profile_kernels(swe_ctx* ctx, unsigned mask) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_profile_kernels: NULL context");
+    ctx->prof.mask = mask;
     return REXI_OK;
 }
 

@@ -94,7 +94,7 @@ void build_twiddles(int M, std::vector<double>& tw);
 // ------------------------------------------------------------- context --
 struct Profiler {
     static constexpr int kCap = 4096;
-    bool enabled = false;
+    unsigned mask = 0;     // bit k: record kernel k
     hipEvent_t* start[REXI_KERNEL_COUNT] = {};
     hipEvent_t* stop[REXI_KERNEL_COUNT] = {};
     int count[REXI_KERNEL_COUNT] = {};
