@@ -411,6 +411,7 @@ int swe_destroy(swe_ctx* ctx) {
         if (ps.d) (void)hipFree(ps.d);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
     if (ctx->d_rows) (void)hipFree(ctx->d_rows);
+    if (ctx->d_rows32) (void)hipFree(ctx->d_rows32);
     if (ctx->d_fact) (void)hipFree(ctx->d_fact);
     if (ctx->d_ckpt) (void)hipFree(ctx->d_ckpt);
     if (ctx->d_lgsum) (void)hipFree(ctx->d_lgsum);

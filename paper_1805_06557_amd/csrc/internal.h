@@ -141,7 +141,9 @@ struct swe_ctx {
     uint64_t poles_key = 0;
 
     // chain-ordered row records of the REXI solve, rebuilt per call [2 modes]
+    // (FP64 and FP32 forms)
     void* d_rows = nullptr;
+    void* d_rows32 = nullptr;
     // cached factorization: pivots of every chain row for every pole,
     // [2 modes][N rounded to 64] complex (FP32 or FP64), valid for the cached
     // coefficient set and dt

@@ -95,10 +95,37 @@ struct RowRec {
 };
 static_assert(sizeof(RowRec) == 96, "RowRec layout");
 
+// The FP32 solve's record: the same quantities rounded once to FP32 (48 B, so a
+// chain's records take half the LDS and half the broadcast reads).
+struct RowRec32 {
+    float a, c, dts, g2, tx, ty, rx, ry, hx, hy;
+    float pad[2];
+};
+static_assert(sizeof(RowRec32) == 48, "RowRec32 layout");
+
+template <typename T>
+using RecT = typename std::conditional<std::is_same<T, float>::value, RowRec32, RowRec>::type;
+
 // The delta and zeta records of degree k = m + j (one per chain).
+__device__ __forceinline__ RowRec32 round_rec(const RowRec& r) {
+    RowRec32 q;
+    q.a = static_cast<float>(r.a);
+    q.c = static_cast<float>(r.c);
+    q.dts = static_cast<float>(r.dts);
+    q.g2 = static_cast<float>(r.g2);
+    q.tx = static_cast<float>(r.tx);
+    q.ty = static_cast<float>(r.ty);
+    q.rx = static_cast<float>(r.rx);
+    q.ry = static_cast<float>(r.ry);
+    q.hx = static_cast<float>(r.hx);
+    q.hy = static_cast<float>(r.hy);
+    q.pad[0] = q.pad[1] = 0.0f;
+    return q;
+}
+
 __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
-                                               RowRec* __restrict__ rec, int L, int modes, double dt, double H,
-                                               int m, int j) {
+                                               RowRec* __restrict__ rec, RowRec32* __restrict__ rec32, int L,
+                                               int modes, double dt, double H, int m, int j) {
     const int base = m * (2 * L + 3 - m) / 2;
     const int idx = base + j;
     const int Lm = L - m + 1;
@@ -121,6 +148,7 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
     d.rfx = static_cast<float>(rd.x);
     d.rfy = static_cast<float>(rd.y);
     rec[2 * base + cd * Lm + j] = d;
+    rec32[2 * base + cd * Lm + j] = round_rec(d);
     RowRec z;
     z.a = dt * cf.cm;
     z.c = dt * cf.cp;
@@ -135,15 +163,17 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
     z.rfx = static_cast<float>(rz.x);
     z.rfy = static_cast<float>(rz.y);
     rec[2 * base + (1 - cd) * Lm + j] = z;
+    rec32[2 * base + (1 - cd) * Lm + j] = round_rec(z);
 }
 
 
 // One workgroup per order m (blockIdx.x), threads over the degrees.
 __global__ __launch_bounds__(256) void rexi_rows_kernel(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
-                                                        RowRec* __restrict__ rec, int L, int modes, double dt,
-                                                        double H) {
+                                                        RowRec* __restrict__ rec, RowRec32* __restrict__ rec32, int L,
+                                                        int modes, double dt, double H) {
     const int m = blockIdx.x;
-    for (int j = threadIdx.x; j < L - m + 1; j += blockDim.x) build_row_pair(U0, coef, rec, L, modes, dt, H, m, j);
+    for (int j = threadIdx.x; j < L - m + 1; j += blockDim.x)
+        build_row_pair(U0, coef, rec, rec32, L, modes, dt, H, m, j);
 }
 
 // Ensemble form: member blockIdx.y.
@@ -151,6 +181,7 @@ struct RowsArgs {
     const double2* U0;
     const ModeCoef* coef;
     RowRec* rec;
+    RowRec32* rec32;
     int L, modes;
     double dt, H;
 };
@@ -160,11 +191,12 @@ __global__ __launch_bounds__(256) void rexi_rows_batched_kernel(const RowsArgs* 
     const int m = blockIdx.x;
     if (m > a.L) return;
     for (int j = threadIdx.x; j < a.L - m + 1; j += blockDim.x)
-        build_row_pair(a.U0, a.coef, a.rec, a.L, a.modes, a.dt, a.H, m, j);
+        build_row_pair(a.U0, a.coef, a.rec, a.rec32, a.L, a.modes, a.dt, a.H, m, j);
 }
 
 struct SolveArgs {
     const RowRec* __restrict__ rec;     // [2 modes] chain-ordered row records
+    const RowRec32* __restrict__ rec32; // the same rounded to FP32
     double2* __restrict__ out;          // [pole waves][3][modes] partial sums (one per wave of 64 poles)
     const PoleData* __restrict__ poles; // [N]
     const void* __restrict__ fact;      // cached pivots [2 modes][npad] complex T (STREAM, HYBRID)
@@ -178,50 +210,69 @@ struct Lane {
     PoleData p;
     double wzr, wzi;   // w / z
     float zrf, zif;    // z in FP32
+    float zirf, ziif;  // 1/z in FP32
 };
 
-// Right-hand side d = r + t/z of a row, formed in FP64 and rounded once to T
-// (zeta rows have t = 0 and use the record's own rounding of r).
+template <typename T>
+__host__ __device__ __forceinline__ const RecT<T>* chain_records(const SolveArgs& A, int row0) {
+    if constexpr (std::is_same<T, float>::value) return A.rec32 + row0; else return A.rec + row0;
+}
+
+// Right-hand side d = r + t/z of a row (zeta rows have t = 0).  FP64 solve: in
+// FP64.  FP32 solve: in FP32 from the rounded record (a rounding of the
+// right-hand side by u_32 relative to its terms, which the FP32 solve's own
+// backward error already contains).
 template <typename T, bool DELTA>
-__device__ __forceinline__ void row_rhs(const RowRec& R, const Lane& ln, T& dR, T& dI) {
-    if constexpr (DELTA) {
-        dR = static_cast<T>(__builtin_fma(ln.p.zir, R.tx, __builtin_fma(-ln.p.zii, R.ty, R.rx)));
-        dI = static_cast<T>(__builtin_fma(ln.p.zir, R.ty, __builtin_fma(ln.p.zii, R.tx, R.ry)));
-    } else if constexpr (std::is_same<T, float>::value) {
-        dR = R.rfx;
-        dI = R.rfy;
+__device__ __forceinline__ void row_rhs(const RecT<T>& R, const Lane& ln, T& dR, T& dI) {
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (DELTA) {
+            dR = __builtin_fmaf(ln.zirf, R.tx, __builtin_fmaf(-ln.ziif, R.ty, R.rx));
+            dI = __builtin_fmaf(ln.zirf, R.ty, __builtin_fmaf(ln.ziif, R.tx, R.ry));
+        } else {
+            dR = R.rx;
+            dI = R.ry;
+        }
     } else {
-        dR = R.rx;
-        dI = R.ry;
+        if constexpr (DELTA) {
+            dR = __builtin_fma(ln.p.zir, R.tx, __builtin_fma(-ln.p.zii, R.ty, R.rx));
+            dI = __builtin_fma(ln.p.zir, R.ty, __builtin_fma(ln.p.zii, R.tx, R.ry));
+        } else {
+            dR = R.rx;
+            dI = R.ry;
+        }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ T coupling_a(const RowRec& R) {
-    if constexpr (std::is_same<T, float>::value) return R.af; else return R.a;
-}
+__device__ __forceinline__ T coupling_a(const RecT<T>& R) { return R.a; }
 template <typename T>
-__device__ __forceinline__ T coupling_c(const RowRec& R) {
-    if constexpr (std::is_same<T, float>::value) return R.cf; else return R.c;
-}
+__device__ __forceinline__ T coupling_c(const RecT<T>& R) { return R.c; }
 
-// Pivot of a row: p = 1/(b - a c'_prev), then c' = c p.  The diagonal
-// b = z + g2/z - i dts is formed in FP64 for delta rows (where it can be much
-// smaller than its terms) and rounded once to T; for zeta rows |b| ~ |z| and it
-// is formed in T.  Used by the factorization and by both sweeps of the fused
-// schedule, so cached and recomputed pivots agree bit for bit.
+// Pivot of a row: p = 1/(b - a c'_prev), then c' = c p, with the diagonal
+// b = z + g2/z - i dts (g2 = 0 for zeta rows) formed in T; an FP32 diagonal is off
+// by u_32 relative to |z| + g2/|z|, a backward error of the size the FP32 sweep
+// makes anyway (the shifted systems are well conditioned: the poles stay at a
+// distance y - rho from the spectrum).  Used by the factorization and by both
+// sweeps of the fused schedule, so cached and recomputed pivots agree bit for bit.
 template <typename T, bool DELTA>
-__device__ __forceinline__ Cx<T> pivot_row(const RowRec& R, const Lane& ln, Cx<T>& cp) {
+__device__ __forceinline__ Cx<T> pivot_row(const RecT<T>& R, const Lane& ln, Cx<T>& cp) {
     T bR, bI;
-    if constexpr (DELTA) {
-        bR = static_cast<T>(__builtin_fma(R.g2, ln.p.zir, ln.p.zr));
-        bI = static_cast<T>(__builtin_fma(R.g2, ln.p.zii, ln.p.zi) - R.dts);
-    } else if constexpr (std::is_same<T, float>::value) {
-        bR = ln.zrf;
-        bI = ln.zif - static_cast<float>(R.dts);
+    if constexpr (std::is_same<T, float>::value) {
+        if constexpr (DELTA) {
+            bR = __builtin_fmaf(R.g2, ln.zirf, ln.zrf);
+            bI = __builtin_fmaf(R.g2, ln.ziif, ln.zif) - R.dts;
+        } else {
+            bR = ln.zrf;
+            bI = ln.zif - R.dts;
+        }
     } else {
-        bR = ln.p.zr;
-        bI = ln.p.zi - R.dts;
+        if constexpr (DELTA) {
+            bR = __builtin_fma(R.g2, ln.p.zir, ln.p.zr);
+            bI = __builtin_fma(R.g2, ln.p.zii, ln.p.zi) - R.dts;
+        } else {
+            bR = ln.p.zr;
+            bI = ln.p.zi - R.dts;
+        }
     }
     const T ta = coupling_a<T>(R), tc = coupling_c<T>(R);
     const T wr = fmaT(-ta, cp.x, bR);
@@ -235,7 +286,7 @@ __device__ __forceinline__ Cx<T> pivot_row(const RowRec& R, const Lane& ln, Cx<T
 
 // The right-hand-side part of a forward step with pivot p: d' = (d - a d'_prev) p.
 template <typename T, bool DELTA>
-__device__ __forceinline__ void forward_rhs(const RowRec& R, const Lane& ln, Cx<T> p, Cx<T>& dp) {
+__device__ __forceinline__ void forward_rhs(const RecT<T>& R, const Lane& ln, Cx<T> p, Cx<T>& dp) {
     T dR, dI;
     row_rhs<T, DELTA>(R, ln, dR, dI);
     const T ta = coupling_a<T>(R);
@@ -286,7 +337,7 @@ __device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, i
 // registers: x_j = d'_j - c_j p_j x_{j+1}; the weighted outputs of the lane's
 // P poles are added in pole order, then summed over the wave.
 template <typename T, int S, int C, int P>
-__device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln, const RowRec* rc, int j0, int Lm,
+__device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln, const RecT<T>* rc, int j0, int Lm,
                                              int base, int pw, int lane, const Cx<T> (*ps)[S],
                                              const Cx<T> (*ds)[S], Cx<T>* vnext, double2* red) {
     static_for<0, S / 4>([&](auto G) {
@@ -315,8 +366,8 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
                 sy = k ? sy + oy : oy;
                 if constexpr (DELTA) {
                     if (live) {
-                        const double tx = __builtin_fma(-A.dtH, vx, rc[j].hx);
-                        const double ty = __builtin_fma(-A.dtH, vy, rc[j].hy);
+                        const double tx = __builtin_fma(-A.dtH, vx, static_cast<double>(rc[j].hx));
+                        const double ty = __builtin_fma(-A.dtH, vy, static_cast<double>(rc[j].hy));
                         const double gx = __builtin_fma(ln[k].wzr, tx, -(ln[k].wzi * ty));
                         const double gy = __builtin_fma(ln[k].wzr, ty, ln[k].wzi * tx);
                         hx = k ? hx + gx : gx;
@@ -355,11 +406,12 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     constexpr int CKW = ckpt_words<SCHED>();
 
     // the chain's row records, shared by all waves of the block
-    RowRec* rc = reinterpret_cast<RowRec*>(smem);
+    RecT<T>* rc = reinterpret_cast<RecT<T>*>(smem);
     {
-        const double4* src = reinterpret_cast<const double4*>(A.rec + 2 * base + C * Lm);
-        double4* dst = reinterpret_cast<double4*>(rc);
-        const int nq = Lm * static_cast<int>(sizeof(RowRec) / sizeof(double4));
+        static_assert(sizeof(RecT<T>) % sizeof(uint4) == 0, "records are copied in 16-byte units");
+        const uint4* src = reinterpret_cast<const uint4*>(chain_records<T>(A, 2 * base + C * Lm));
+        uint4* dst = reinterpret_cast<uint4*>(rc);
+        const int nq = Lm * static_cast<int>(sizeof(RecT<T>) / sizeof(uint4));
         for (int i = threadIdx.x; i < nq; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
@@ -376,6 +428,8 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
         ln[k].wzi = __builtin_fma(ln[k].p.wr, ln[k].p.zii, ln[k].p.wi * ln[k].p.zir);
         ln[k].zrf = static_cast<float>(ln[k].p.zr);
         ln[k].zif = static_cast<float>(ln[k].p.zi);
+        ln[k].zirf = static_cast<float>(ln[k].p.zir);
+        ln[k].ziif = static_cast<float>(ln[k].p.zii);
     }
 
     double2* red = reinterpret_cast<double2*>(smem + static_cast<size_t>(A.rec_bytes) +
@@ -401,7 +455,7 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
                 if constexpr (CKW == 2) c0[(P + k) * WAVE] = cp[k];
             }
         }
-        const RowRec* rs = rc + seg * S;
+        const RecT<T>* rs = rc + seg * S;
         if constexpr (SCHED == FUSED) {
             static_for<0, S>([&](auto Q) {
                 constexpr int jj = decltype(Q)::value;
@@ -533,7 +587,7 @@ void rexi_chain_batched_kernel(const SolveArgs* __restrict__ args, const int4* _
 // pole, one workgroup per (task, block of poles); depends on z, dt and the
 // operator only, so it is reused while they stay the same.
 template <typename T>
-__global__ __launch_bounds__(256) void rexi_factor_kernel(const RowRec* __restrict__ rec,
+__global__ __launch_bounds__(256) void rexi_factor_kernel(const RecT<T>* __restrict__ rec,
                                                           const PoleData* __restrict__ poles, Cx<T>* __restrict__ fact,
                                                           int L, int N, int npad, int fpb) {
     const int task = blockIdx.x / fpb;
@@ -546,11 +600,13 @@ __global__ __launch_bounds__(256) void rexi_factor_kernel(const RowRec* __restri
     ln.p = poles[n < N ? n : 0];
     ln.zrf = static_cast<float>(ln.p.zr);
     ln.zif = static_cast<float>(ln.p.zi);
-    const RowRec* rc = rec + 2 * base + C * Lm;
+    ln.zirf = static_cast<float>(ln.p.zir);
+    ln.ziif = static_cast<float>(ln.p.zii);
+    const RecT<T>* rc = rec + 2 * base + C * Lm;
     Cx<T>* out = fact + static_cast<size_t>(2 * base + C * Lm) * npad + n;
     Cx<T> cp{T(0), T(0)};
     for (int j = 0; j < Lm; ++j) {
-        const RowRec R = rc[j];
+        const RecT<T> R = rc[j];
         const Cx<T> p = ((j + C) & 1) == 0 ? pivot_row<T, true>(R, ln, cp) : pivot_row<T, false>(R, ln, cp);
         out[static_cast<size_t>(j) * npad] = p;
     }
@@ -619,7 +675,7 @@ int build_factors(swe_ctx* ctx, const SolveArgs& A, hipStream_t stream) {
     const int fpb = (A.npad + threads - 1) / threads;
     const unsigned blocks = static_cast<unsigned>(2 * (A.L + 1) * fpb);
     const int slot = prof_begin(ctx, REXI_KERNEL_FACTOR, stream);
-    hipLaunchKernelGGL((rexi_factor_kernel<T>), dim3(blocks), dim3(threads), 0, stream, A.rec, A.poles,
+    hipLaunchKernelGGL((rexi_factor_kernel<T>), dim3(blocks), dim3(threads), 0, stream, chain_records<T>(A, 0), A.poles,
                        reinterpret_cast<Cx<T>*>(ctx->d_fact), A.L, A.N, A.npad, fpb);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_FACTOR, slot, stream);
@@ -636,7 +692,7 @@ template <typename T, int S, int SCHED, int P>
 int configure(swe_ctx* ctx, SolveArgs& A, int waves, hipStream_t stream) {
     const int nseg = (A.L + 1 + S - 1) / S;
     A.nck_max = nseg > 2 ? nseg - 2 : 0;
-    A.rec_bytes = static_cast<int>(sizeof(RowRec)) * (A.L + 1);
+    A.rec_bytes = static_cast<int>(sizeof(RecT<T>)) * (A.L + 1);
     A.npb = (A.N + WAVE * P * waves - 1) / (WAVE * P * waves);
     constexpr int CKW = ckpt_words<SCHED>();
     if (SCHED != FUSED) {
@@ -750,7 +806,8 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
         for (int i = 0; i < count; ++i) {
             swe_ctx* c = mem[i].ctx;
             rows[i] = RowsArgs{reinterpret_cast<const double2*>(mem[i].U0), c->d_coef,
-                               reinterpret_cast<RowRec*>(c->d_rows), c->L, c->modes, mem[i].dt, c->H};
+                               reinterpret_cast<RowRec*>(c->d_rows), reinterpret_cast<RowRec32*>(c->d_rows32), c->L,
+                               c->modes, mem[i].dt, c->H};
             const int nparts = (mem[i].N + WAVE * P - 1) / (WAVE * P);
             sums[i] = SumArgs{reinterpret_cast<const double2*>(c->d_partial), reinterpret_cast<double2*>(mem[i].U1),
                               nparts > 1 ? 3 * c->modes : 0, nparts};
@@ -869,10 +926,12 @@ int launch_shape(swe_ctx* ctx, const SolveArgs& A, const Tuning& t, hipStream_t 
 // and (for more than one pole wave) the partial sums.
 int base_args(swe_ctx* ctx, int N, double dt, const double* U1, int P, SolveArgs& A, int& nparts) {
     if (!ctx->d_rows) {
-        if (hipMalloc(&ctx->d_rows, sizeof(RowRec) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess)
+        if (hipMalloc(&ctx->d_rows, sizeof(RowRec) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess ||
+            hipMalloc(&ctx->d_rows32, sizeof(RowRec32) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess)
             return fail(REXI_ENOMEM, "rexi solve: cannot allocate row records");
     }
     A.rec = reinterpret_cast<const RowRec*>(ctx->d_rows);
+    A.rec32 = reinterpret_cast<const RowRec32*>(ctx->d_rows32);
     A.poles = ctx->d_poles;
     A.L = ctx->L;
     A.modes = ctx->modes;
@@ -912,7 +971,7 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
     {
         hipLaunchKernelGGL(rexi_rows_kernel, dim3(ctx->L + 1), dim3(256), 0, stream,
                            reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
-                           ctx->L, ctx->modes, dt, ctx->H);
+                           reinterpret_cast<RowRec32*>(ctx->d_rows32), ctx->L, ctx->modes, dt, ctx->H);
         REXI_HIP(hipGetLastError());
     }
     const bool fp32 = (ctx->prec & REXI_PREC_FP32_SOLVE) != 0;
