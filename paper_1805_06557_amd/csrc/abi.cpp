@@ -366,11 +366,13 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     ctx->nlat = nlat;
     ctx->nlon = nlon;
     ctx->prec = prec;
-    // measured defaults at T255 / N = 800 (the autotuner refines them per problem)
+    // measured defaults at T255 / N = 800 (the autotuner refines them per problem):
+    // FP32 two poles per lane, 8-row segments, 4 waves; FP64 one pole, 16 rows, 2 waves
+    const bool fp32 = (prec & REXI_PREC_FP32_SOLVE) != 0;
     ctx->tune.solver = REXI_SOLVER_FUSED;
-    ctx->tune.poles_per_lane = 1;
-    ctx->tune.seg_rows = 16;
-    ctx->tune.waves = (prec & REXI_PREC_FP32_SOLVE) ? 4 : 2;
+    ctx->tune.poles_per_lane = fp32 ? 2 : 1;
+    ctx->tune.seg_rows = fp32 ? 8 : 16;
+    ctx->tune.waves = fp32 ? 4 : 2;
     ctx->a = a;
     ctx->g = g;
     ctx->H = H;
