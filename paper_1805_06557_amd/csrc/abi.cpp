@@ -184,6 +184,16 @@ int setup_sht(swe_ctx* ctx) {
         std::vector<int> segid(ctx->L + 2);
         for (int m = 0; m <= ctx->L + 1; ++m) segid[m] = m;
         if ((rc = upload(&ctx->d_tab_segid, segid.data(), segid.size())) != REXI_OK) return rc;
+        // analysis workgroups: four row tiles of one order each, orders with
+        // the most degrees first
+        std::vector<int> ablk;
+        for (int m = 0; m <= ctx->L; ++m)
+            for (int t = 0; t < (kp[2 * m] + kp[2 * m + 1]) / 16; t += 4) {
+                ablk.push_back(m);
+                ablk.push_back(t);
+            }
+        ctx->tab_nablk = static_cast<int>(ablk.size() / 2);
+        if ((rc = upload(&ctx->d_tab_ablk, ablk.data(), ablk.size())) != REXI_OK) return rc;
         for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_hsyn, &ctx->d_tab_pana, &ctx->d_tab_hana})
             if (hipMalloc(reinterpret_cast<void**>(t), sizeof(unsigned short) * ctx->tab_len) != hipSuccess)
                 return fail(REXI_ENOMEM, "swe_create: cannot allocate the split-precision Legendre tables");
@@ -422,7 +432,8 @@ int swe_destroy(swe_ctx* ctx) {
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
-                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid};
+                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid,
+                        ctx->d_tab_ablk};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {

@@ -201,7 +201,8 @@ struct swe_ctx {
     long long* d_tab_off = nullptr;   // [L+2]
     int* d_tab_segid = nullptr;       // [L+2] m: one Fourier row per order
     int* d_tab_kp = nullptr;          // [2 (L+1)]
-    int tab_hpad = 0, tab_kmax = 0;
+    int* d_tab_ablk = nullptr;        // [2 tab_nablk] analysis workgroups (m, first row tile)
+    int tab_hpad = 0, tab_kmax = 0, tab_nablk = 0;
     size_t tab_len = 0;               // shorts per table
     double* d_tmpA = nullptr;         // Strang intermediates [3][modes]
     double* d_tmpB = nullptr;

@@ -25,6 +25,8 @@ namespace rexi {
 namespace {
 
 constexpr int WAVE = 64;
+constexpr int KB_SYN = 8;    // table K steps loaded per batch, synthesis
+constexpr int KB_ANA = 12;   // and analysis
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -123,6 +125,11 @@ __device__ __forceinline__ void mfma3(f32x4& acc, const uint4& a, const uint4& b
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
 }
 
+// v if in, else zero (component selects, so no load is made conditional)
+__device__ __forceinline__ uint4 keep_if(bool in, const uint4 v) {
+    return make_uint4(in ? v.x : 0u, in ? v.y : 0u, in ? v.z : 0u, in ? v.w : 0u);
+}
+
 struct MfmaArgs {
     const unsigned short* __restrict__ p_syn;
     const unsigned short* __restrict__ h_syn;
@@ -130,6 +137,7 @@ struct MfmaArgs {
     const unsigned short* __restrict__ h_ana;
     const long long* __restrict__ off;
     const int* __restrict__ kp;
+    const int* __restrict__ ablk;       // analysis workgroups: (m, first tile) pairs
     const double* __restrict__ aon;     // [L+2] a / (l(l+1))
     const double* __restrict__ noa2;    // [L+2] l(l+1) / a^2
     const double* __restrict__ sint;    // [half]
@@ -226,6 +234,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     if (tile * 16 >= A.hpad) return;
     const int kq = lane >> 4;                       // K quarter of this lane
     f32x4 accP[2], accH[2];
+#pragma unroll
     for (int par = 0; par < 2; ++par) {
         accP[par] = f32x4{0.f, 0.f, 0.f, 0.f};
         accH[par] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -236,15 +245,30 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
         const unsigned short* ah = A.h_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
         const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
         const unsigned short* bh = xh + (par * 16 + (lane & 15)) * rowlen;
-        for (int ks = 0; ks < (K >> 4); ++ks) {
-            const int g = 4 * ks + kq;              // group of four rows for this lane
-            const uint4 a = *reinterpret_cast<const uint4*>(ap + ks * 512);
-            const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
-            mfma3(accP[par], a, b);
-            if constexpr (KIND == 1) {
-                const uint4 a2 = *reinterpret_cast<const uint4*>(ah + ks * 512);
-                const uint4 b2 = *reinterpret_cast<const uint4*>(bh + 8 * g);
-                mfma3(accH[par], a2, b2);
+        // table operands in batches of KB steps, all loads of a batch issued
+        // before its products (a serial load-multiply chain leaves the
+        // small-m workgroups, the longest ones, waiting on memory latency);
+        // steps past the end reload the last block and multiply a zero operand
+        const int nks = K >> 4;
+        for (int k0 = 0; k0 < nks; k0 += KB_SYN) {
+            uint4 a[KB_SYN], a2[KB_SYN];
+#pragma unroll
+            for (int u = 0; u < KB_SYN; ++u) {
+                const int ks = min(k0 + u, nks - 1);
+                a[u] = *reinterpret_cast<const uint4*>(ap + ks * 512);
+                if constexpr (KIND == 1) a2[u] = *reinterpret_cast<const uint4*>(ah + ks * 512);
+            }
+            __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
+#pragma unroll
+            for (int u = 0; u < KB_SYN; ++u) {
+                const bool in = k0 + u < nks;
+                const int g = 4 * min(k0 + u, nks - 1) + kq;   // group of four rows for this lane
+                const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
+                mfma3(accP[par], a[u], b);
+                if constexpr (KIND == 1) {
+                    const uint4 b2 = keep_if(in, *reinterpret_cast<const uint4*>(bh + 8 * g));
+                    mfma3(accH[par], a2[u], b2);
+                }
             }
         }
     }
@@ -270,8 +294,9 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 }
 
 // ----------------------------------------------------------------- analysis --
-// Workgroup: order m = blockIdx.x, 4 waves = 4 row tiles of 16 degrees of one
-// parity (tile 4 blockIdx.y + wave; even-parity tiles first).  LDS: the B
+// Workgroup: (order m, first tile t0) = ablk[blockIdx.x], 4 waves = row tiles
+// t0 .. t0 + 3 of 16 degrees of one parity (even-parity tiles first), so an
+// order with many degrees spreads over several workgroups.  LDS: the B
 // operands Y[fold][column][latitude] (latitudes in groups of four), fold 0 =
 // F(mu) + F(-mu), fold 1 = F(mu) - F(-mu), weighted.
 // KIND 0: O = sum_j w_j Pbar F (fields 8 blockIdx.z ..).  KIND 1: the
@@ -283,7 +308,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 template <int KIND>
 __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short ys[];
-    const int m = blockIdx.x;
+    const int m = A.ablk[2 * blockIdx.x], t0 = A.ablk[2 * blockIdx.x + 1];
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
@@ -359,7 +384,8 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int te = ke / 16, to = ko / 16;
-    for (int tile = threadIdx.x / WAVE; tile < te + to; tile += 4) {
+    const int tile = t0 + static_cast<int>(threadIdx.x) / WAVE;
+    if (tile < te + to) {
         const int par = tile < te ? 0 : 1;
         const int r0 = (par ? tile - te : tile) * 16;
         const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
@@ -371,15 +397,27 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
         const unsigned short* bp = yp + (par * 16 + (lane & 15)) * rowlen;
         const unsigned short* bh = yh + ((1 - par) * 16 + (lane & 15)) * rowlen;
         f32x4 accP = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
-        for (int js = 0; js < (A.hpad >> 4); ++js) {
-            const int g = 4 * js + kq;
-            const uint4 a = *reinterpret_cast<const uint4*>(ap + js * 512);
-            const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
-            mfma3(accP, a, b);
-            if constexpr (KIND == 1) {
-                const uint4 a2 = *reinterpret_cast<const uint4*>(ah + js * 512);
-                const uint4 b2 = *reinterpret_cast<const uint4*>(bh + 8 * g);
-                mfma3(accH, a2, b2);
+        // table operands in batches of KB steps (loads first, then products)
+        const int nks = A.hpad >> 4;
+        for (int k0 = 0; k0 < nks; k0 += KB_ANA) {
+            uint4 a[KB_ANA], a2[KB_ANA];
+#pragma unroll
+            for (int u = 0; u < KB_ANA; ++u) {
+                const int js = min(k0 + u, nks - 1);
+                a[u] = *reinterpret_cast<const uint4*>(ap + js * 512);
+                if constexpr (KIND == 1) a2[u] = *reinterpret_cast<const uint4*>(ah + js * 512);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < KB_ANA; ++u) {
+                const bool in = k0 + u < nks;
+                const int g = 4 * min(k0 + u, nks - 1) + kq;
+                const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
+                mfma3(accP, a[u], b);
+                if constexpr (KIND == 1) {
+                    const uint4 b2 = keep_if(in, *reinterpret_cast<const uint4*>(bh + 8 * g));
+                    mfma3(accH, a2[u], b2);
+                }
             }
         }
         const int c = lane & 15;
@@ -423,6 +461,7 @@ MfmaArgs mfma_args(const swe_ctx* ctx) {
     A.h_ana = ctx->d_tab_hana;
     A.off = ctx->d_tab_off;
     A.kp = ctx->d_tab_kp;
+    A.ablk = ctx->d_tab_ablk;
     A.aon = ctx->d_aon;
     A.noa2 = ctx->d_noa2;
     A.sint = ctx->d_sint;
@@ -514,7 +553,7 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     A.c1 = c1;
     A.nf = nf;
     const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.hpad) * (kind == 0 ? 1 : 2);
-    const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
+    const dim3 grid(ctx->tab_nablk, 1, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
     const void* fn = kind == 0 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0>)
                                : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1>);
