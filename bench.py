@@ -422,7 +422,7 @@ def main():
     stage_ms = {}
     for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, "sum_partials_kernel"),
                       (api.KERNEL_LEG_SYNTH, "legendre_synth_kernel"), (api.KERNEL_RING, "ring_kernel"),
-                      (api.KERNEL_LEG_ANAL, "legendre_anal_kernel"), (api.KERNEL_GATHER, "gather_fourier_kernel")]:
+                      (api.KERNEL_LEG_ANAL, "legendre_anal_kernel")]:
         ms, n = ctx.profile_read(kid)
         stage_ms[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                           "ms_per_launch": ms / max(n, 1)}

@@ -229,14 +229,12 @@ int setup_sht(swe_ctx* ctx) {
 int reserve_fourier(swe_ctx* ctx, int nf) {
     if (static_cast<size_t>(nf) <= ctx->four_cap) return REXI_OK;
     if (ctx->d_part) REXI_HIP(hipFree(ctx->d_part));
-    if (ctx->d_fin) REXI_HIP(hipFree(ctx->d_fin));
     if (ctx->d_fout) REXI_HIP(hipFree(ctx->d_fout));
-    ctx->d_part = ctx->d_fin = ctx->d_fout = nullptr;
+    ctx->d_part = ctx->d_fout = nullptr;
     ctx->four_cap = 0;
     const size_t pbytes = sizeof(double) * 2 * static_cast<size_t>(nf) * ctx->nseg * ctx->nlat;
     const size_t fbytes = sizeof(double) * 2 * static_cast<size_t>(nf) * (ctx->L + 1) * ctx->nlat;
-    if (hipMalloc(&ctx->d_part, pbytes) != hipSuccess || hipMalloc(&ctx->d_fin, fbytes) != hipSuccess ||
-        hipMalloc(&ctx->d_fout, fbytes) != hipSuccess)
+    if (hipMalloc(&ctx->d_part, pbytes) != hipSuccess || hipMalloc(&ctx->d_fout, fbytes) != hipSuccess)
         return fail(REXI_ENOMEM, "cannot allocate Fourier workspace");
     ctx->four_cap = static_cast<size_t>(nf);
     return REXI_OK;
@@ -245,17 +243,19 @@ int reserve_fourier(swe_ctx* ctx, int nf) {
 // One Heun step dU/dt = N(U) over tau on `stream`.
 bool split_legendre(const swe_ctx* ctx) { return (ctx->prec & REXI_PREC_BF16_SPLIT) != 0; }
 
-// Spectral fields -> Fourier coefficients [nf][nlat][L+1] in ctx->d_fin.
+// Spectral fields -> synthesis partials of the Fourier coefficients in
+// ctx->d_part (per degree segment; one segment per order in the split path).
 int to_fourier(swe_ctx* ctx, int kind, const double* spec, int nf, hipStream_t stream) {
-    const int nfo = kind == 0 ? nf : 4;
-    int rc;
-    if (split_legendre(ctx)) {
-        if ((rc = launch_legendre_synth_split(ctx, kind, spec, ctx->d_part, nf, stream)) != REXI_OK) return rc;
-        return launch_gather_fourier_with(ctx, ctx->d_part, ctx->d_fin, nfo, ctx->d_tab_segid, ctx->L + 1, stream);
-    }
-    rc = launch_legendre_synth(ctx, kind, spec, ctx->d_part, nf, stream);
-    if (rc != REXI_OK) return rc;
-    return launch_gather_fourier(ctx, ctx->d_part, ctx->d_fin, nfo, stream);
+    if (split_legendre(ctx)) return launch_legendre_synth_split(ctx, kind, spec, ctx->d_part, nf, stream);
+    return launch_legendre_synth(ctx, kind, spec, ctx->d_part, nf, stream);
+}
+
+// Ring stage on the partials to_fourier left in ctx->d_part (mode 0: to the
+// grid `gout`; mode 2: non-linear products into ctx->d_fout).
+int ring_from_part(swe_ctx* ctx, int mode, double* gout, int nf, hipStream_t stream, double two_omega = 0.0) {
+    const bool split = split_legendre(ctx);
+    return launch_ring(ctx, mode, ctx->d_part, split ? ctx->d_tab_segid : ctx->d_segbase, split ? ctx->L + 1 : ctx->nseg,
+                       ctx->d_fout, nullptr, gout, nf, stream, two_omega);
 }
 
 // Fourier coefficients (ctx->d_fout) -> spectral fields or the Runge-Kutta update.
@@ -272,8 +272,7 @@ int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t strea
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     if ((rc = to_fourier(ctx, 1, U, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
-        return rc;
+    if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
     return from_fourier(ctx, 1, nullptr, 0, nullptr, nullptr, nullptr, Nout, 1.0, 0.0, stream);
 }
 
@@ -304,14 +303,12 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
     if ((rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
-        return rc;
+    if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
     if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) != REXI_OK)
         return rc;
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
     if ((rc = to_fourier(ctx, 1, ctx->d_ustar, 3, stream)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 2, ctx->d_fin, ctx->d_fout, nullptr, nullptr, 0, stream, two_omega)) != REXI_OK)
-        return rc;
+    if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
     return from_fourier(ctx, 1, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau, stream);
 }
 
@@ -428,7 +425,7 @@ int swe_destroy(swe_ctx* ctx) {
     if (ctx->d_ckpt) (void)hipFree(ctx->d_ckpt);
     if (ctx->d_lgsum) (void)hipFree(ctx->d_lgsum);
     free_batch_plan(ctx);
-    void* sht_bufs[] = {ctx->d_fin, ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
+    void* sht_bufs[] = {ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
@@ -606,7 +603,7 @@ int sh_synthesis(swe_ctx* ctx, const double* spec, double* grid, int nf, hipStre
     int rc;
     if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
     if ((rc = to_fourier(ctx, 0, spec, nf, stream)) != REXI_OK) return rc;
-    return launch_ring(ctx, 0, ctx->d_fin, nullptr, nullptr, grid, nf, stream);
+    return ring_from_part(ctx, 0, grid, nf, stream);
 }
 
 int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStream_t stream) {
@@ -616,7 +613,7 @@ int sh_analysis(swe_ctx* ctx, const double* grid, double* spec, int nf, hipStrea
     DeviceGuard guard(ctx->device);
     int rc;
     if ((rc = reserve_fourier(ctx, nf)) != REXI_OK) return rc;
-    if ((rc = launch_ring(ctx, 1, nullptr, ctx->d_fout, grid, nullptr, nf, stream)) != REXI_OK) return rc;
+    if ((rc = launch_ring(ctx, 1, nullptr, nullptr, 0, ctx->d_fout, grid, nullptr, nf, stream)) != REXI_OK) return rc;
     return from_fourier(ctx, 0, spec, nf, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, stream);
 }
 

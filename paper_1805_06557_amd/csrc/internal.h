@@ -185,8 +185,7 @@ struct swe_ctx {
     double* d_twr = nullptr;          // [nlon/2] complex
     int* d_radix = nullptr;
     int npass = 0;
-    double* d_fin = nullptr;          // Fourier coefficients for the inverse FFTs [nf][nlat][L+1] complex
-    double* d_fout = nullptr;         // Fourier coefficients of the forward FFTs [nf][nlat][L+1] complex
+    double* d_fout = nullptr;         // Fourier coefficients of the forward FFTs [nf][L+1][nlat] complex
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
@@ -237,18 +236,13 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
                          const double* Nprev, double* Nsave, double* out, double c0, double c1,
                          hipStream_t stream);
 // Split-precision (bf16 hi/lo, matrix-core) Legendre stage: tables and the two
-// directions.  The synthesis writes the Fourier coefficients [nf][nlat][L+1]
-// [nf][L+1][nlat] (one row per order, gathered like segment partials).
+// directions.  The synthesis writes the Fourier coefficients [nf][L+1][nlat]:
+// one partial row per order, read by the ring kernel with segbase[m] = m.
 int build_split_tables(swe_ctx* ctx, hipStream_t stream);
 int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, double* four, int nf,
                                 hipStream_t stream);
 int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                                const double* Nprev, double* Nsave, double* out, double c0, double c1,
-                               hipStream_t stream);
-// Sums segment partials and transposes them to [nf][nlat][L+1].
-int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream);
-// The same with another segmentation (segbase[m] .. segbase[m+1] - 1 are the rows of order m).
-int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
                                hipStream_t stream);
 // The REXI stage of the gravity-wave part L_g alone (Coriolis-free): per degree
 // l a 2x2 system in (h, delta), zeta multiplied by S(0); the sums over poles are
@@ -257,7 +251,7 @@ int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
 // out = x + a y over n doubles (out may equal x or y).
 int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
-int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
-                hipStream_t stream, double two_omega = 0.0);
+int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
+                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega = 0.0);
 
 }  // namespace rexi

@@ -18,10 +18,13 @@
 // through LDS (each lane writes its contributions for a few degrees, threads
 // then read them transposed).
 //
-// Ring stage: one workgroup per latitude circle; the real FFTs of length nlon
-// run as complex Stockham FFTs of length nlon/2 (radix 4, 2 and 3) in LDS, with
-// the non-linear products formed pointwise between the inverse and forward
-// transforms, so grid fields never go to HBM.
+// Ring stage: one workgroup per latitude circle; it sums the synthesis partials
+// of each order into the ring's Fourier coefficients, the real FFTs of length
+// nlon run as complex Stockham FFTs of length nlon/2 (radix 4, 2 and 3) in LDS,
+// and the non-linear products are formed pointwise between the inverse and
+// forward transforms, so grid fields never go to HBM.  Fourier coefficients in
+// HBM are order-major ([field][m][latitude]): the Legendre kernels, whose lanes
+// are latitudes, read and write them contiguously.
 #include <type_traits>
 
 #include "internal.h"
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(WAVE) void legendre_synth_kernel(SynArgs S) {
 //   followed by the Runge-Kutta update out = U0 + c0 N (+ c1 Nprev), and Nsave = N.
 struct AnaArgs {
     LegArgs g;
-    const double2* __restrict__ four;   // [nf][nlat][L+1]
+    const double2* __restrict__ four;   // [nf][L+1][nlat]
     double2* __restrict__ spec;         // KIND 0: [nf][modes]
     // KIND 1 epilogue
     const double2* __restrict__ U0;     // [3][modes] or nullptr (zero)
@@ -276,9 +279,9 @@ __device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, bool
 #pragma unroll
     for (int f = 0; f < NIN; ++f) {
         const int fld = KIND == 0 ? blockIdx.y : f;
-        const size_t fb = static_cast<size_t>(fld) * A.nlat;
-        const double2 nn = P.four[(fb + j) * (A.L + 1) + m];
-        const double2 ss = P.four[(fb + A.nlat - 1 - j) * (A.L + 1) + m];
+        const double2* fr = P.four + (static_cast<size_t>(fld) * (A.L + 1) + m) * A.nlat;
+        const double2 nn = fr[j];
+        const double2 ss = fr[A.nlat - 1 - j];
         const double wt = (KIND == 0 || f == 4) ? wj : wdiv;
         Sv[f] = scale2(cadd(nn, ss), wt * sc);
         Dv[f] = scale2(csub(nn, ss), wt * sc);
@@ -430,8 +433,13 @@ struct RingArgs {
     const double* __restrict__ mu;     // [half] sin(latitude), northern
     const int* __restrict__ radix;     // [npass]
     int npass, L, nlat, nlon, half;
-    const double2* __restrict__ fin;   // Fourier coefficients [nf_in][nlat][L+1]
-    double2* __restrict__ fout;        // Fourier coefficients [nf_out][nlat][L+1]
+    // inverse input: synthesis partials [nf_in][nseg][nlat]; the Fourier
+    // coefficient F_m of a latitude is the sum over segments segbase[m] ..
+    // segbase[m + 1] - 1
+    const double2* __restrict__ part;
+    const int* __restrict__ segbase;   // [L+2]
+    int nseg;
+    double2* __restrict__ fout;        // Fourier coefficients [nf_out][L+1][nlat] (order-major)
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
     int nf;
@@ -601,8 +609,22 @@ __device__ __forceinline__ void fft_lds_ct(double2* const* a, double2* const* sc
     for (int i = 0; i < narr; ++i) res[i] = (np & 1) ? dst[i] : src[i];
 }
 
-// Loads F_m (m <= L) of one latitude (a contiguous row) and builds the
-// half-length spectrum Z of the inverse real FFT:
+// Fourier coefficients F_m (m <= L) of latitude j for fields f0 .. f0 + nb - 1
+// into the LDS rows x[b]: each the sum of its order's segment partials.
+__device__ void load_coeffs(const RingArgs& A, int f0, int nb, int j, double2* const* x) {
+    const int n = nb * (A.L + 1);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int b = t / (A.L + 1), m = t - b * (A.L + 1);
+        const double2* pf = A.part + static_cast<size_t>(f0 + b) * A.nseg * A.nlat + j;
+        double2 acc = make_double2(0.0, 0.0);
+        const int g1 = A.segbase[m + 1];
+        for (int g = A.segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
+        x[b][m] = acc;
+    }
+}
+
+// From the LDS row F_m (m <= L) of one latitude, the half-length spectrum Z of
+// the inverse real FFT:
 //   Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/nlon} (X_k - conj X_{M-k}),
 // X_0 taken real, X_k = 0 for k > L.
 __device__ void load_inverse(const double2* frow, double2* z, const RingArgs& A) {
@@ -624,6 +646,7 @@ __device__ void load_inverse(const double2* frow, double2* z, const RingArgs& A)
 
 // From Z = FFT_M(x viewed as complex), the coefficients F_m = X_m / nlon, m <= L:
 // X_m = (Z_m + conj Z_{M-m})/2 - (i/2) e^{-2 pi i m/nlon} (Z_m - conj Z_{M-m}).
+// frow points at F_0 of the latitude; consecutive orders are nlat apart.
 __device__ void store_forward(const double2* Z, double2* frow, const RingArgs& A) {
     const int M = A.nlon / 2;
     const double inv = 1.0 / static_cast<double>(A.nlon);
@@ -636,7 +659,7 @@ __device__ void store_forward(const double2* Z, double2* frow, const RingArgs& A
         const double2 t = cmul(wk, d);
         // X = s/2 - i t/2
         const double2 X = make_double2(0.5 * (s.x + t.y), 0.5 * (s.y - t.x));
-        frow[k] = scale2(X, inv);
+        frow[static_cast<size_t>(k) * A.nlat] = scale2(X, inv);
     }
 }
 
@@ -657,13 +680,21 @@ __device__ __forceinline__ void ring_fft(double2* const* a, double2* const* scra
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs: each XCD gets a
+// contiguous band of latitudes, so the rings that share cache lines of the
+// order-major buffers meet in one L2.
+__device__ __forceinline__ int ring_of_block(int b, int nlat) {
+    if (nlat % 8) return b;
+    return (b % 8) * (nlat / 8) + b / 8;
+}
+
 template <int MODE, int MC>
 __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
     extern __shared__ __align__(16) double2 lds[];
     const int M = A.nlon / 2;
-    const int j = blockIdx.x;
-    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // one field of [nlat][L+1]
-    const size_t row = static_cast<size_t>(j) * (A.L + 1);
+    const int j = ring_of_block(blockIdx.x, A.nlat);
+    const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // one field of [L+1][nlat]
+    const size_t row = static_cast<size_t>(j);
     double2* arr[2 * MAXB];
 #pragma unroll
     for (int i = 0; i < 2 * MAXB; ++i) arr[i] = lds + i * M;
@@ -675,7 +706,9 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
     if constexpr (MODE == 0) {
         for (int f0 = 0; f0 < A.nf; f0 += MAXB) {
             const int nb = min(MAXB, A.nf - f0);
-            for (int b = 0; b < nb; ++b) load_inverse(A.fin + (f0 + b) * fstride + row, arr[b], A);
+            load_coeffs(A, f0, nb, j, arr + MAXB);
+            __syncthreads();
+            for (int b = 0; b < nb; ++b) load_inverse(arr[MAXB + b], arr[b], A);
             __syncthreads();
             ring_fft<MC>(arr, arr + MAXB, nb, A, twl, true, res);
             for (int b = 0; b < nb; ++b) {
@@ -698,7 +731,9 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
             __syncthreads();
         }
     } else {
-        for (int f = 0; f < 4; ++f) load_inverse(A.fin + f * fstride + row, arr[f], A);
+        load_coeffs(A, 0, 4, j, arr + MAXB);
+        __syncthreads();
+        for (int f = 0; f < 4; ++f) load_inverse(arr[MAXB + f], arr[f], A);
         __syncthreads();
         ring_fft<MC>(arr, arr + MAXB, 4, A, twl, true, res);
         // the four arrays not holding results are free
@@ -753,54 +788,7 @@ __global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
     }
 }
 
-// Sums the synthesis partials of each order over its degree segments and
-// transposes [nf][nseg][nlat] -> [nf][nlat][L+1] through LDS, so that the ring
-// kernel reads one contiguous row per latitude.  Block: (field, 16 orders,
-// 64 latitudes), 256 threads.
-constexpr int GM = 16, GJ = 64;
-__global__ __launch_bounds__(256) void gather_fourier_kernel(const double2* __restrict__ part,
-                                                             double2* __restrict__ four,
-                                                             const int* __restrict__ segbase, int L, int nlat,
-                                                             int nseg) {
-    __shared__ double2 tile[GM][GJ + 1];
-    const int f = blockIdx.z;
-    const int m0 = blockIdx.y * GM, j0 = blockIdx.x * GJ;
-    const double2* pf = part + static_cast<size_t>(f) * nseg * nlat;
-    for (int x = threadIdx.x; x < GM * GJ; x += blockDim.x) {
-        const int mi = x / GJ, jj = x % GJ;
-        const int m = m0 + mi, j = j0 + jj;
-        double2 acc = make_double2(0.0, 0.0);
-        if (m <= L && j < nlat) {
-            const int g1 = segbase[m + 1];
-            for (int g = segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * nlat + j]);
-        }
-        tile[mi][jj] = acc;
-    }
-    __syncthreads();
-    double2* ff = four + static_cast<size_t>(f) * nlat * (L + 1);
-    for (int x = threadIdx.x; x < GM * GJ; x += blockDim.x) {
-        const int jj = x / GM, mi = x % GM;
-        const int m = m0 + mi, j = j0 + jj;
-        if (m <= L && j < nlat) ff[static_cast<size_t>(j) * (L + 1) + m] = tile[mi][jj];
-    }
-}
-
 }  // namespace
-
-int launch_gather_fourier(swe_ctx* ctx, const double* part, double* four, int nf, hipStream_t stream) {
-    return launch_gather_fourier_with(ctx, part, four, nf, ctx->d_segbase, ctx->nseg, stream);
-}
-
-int launch_gather_fourier_with(swe_ctx* ctx, const double* part, double* four, int nf, const int* segbase, int nseg,
-                               hipStream_t stream) {
-    const dim3 grid((ctx->nlat + GJ - 1) / GJ, (ctx->L + 1 + GM - 1) / GM, nf);
-    const int slot = prof_begin(ctx, REXI_KERNEL_GATHER, stream);
-    hipLaunchKernelGGL(gather_fourier_kernel, grid, dim3(256), 0, stream, reinterpret_cast<const double2*>(part),
-                       reinterpret_cast<double2*>(four), segbase, ctx->L, ctx->nlat, nseg);
-    REXI_HIP(hipGetLastError());
-    prof_end(ctx, REXI_KERNEL_GATHER, slot, stream);
-    return REXI_OK;
-}
 
 namespace {
 // out = x + a y over n doubles (spectral-state combinations of the time steppers).
@@ -958,11 +946,13 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
     return REXI_OK;
 }
 
-int launch_ring(swe_ctx* ctx, int mode, const double* fin, double* fout, const double* gin, double* gout, int nf,
-                hipStream_t stream, double two_omega) {
+int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
+                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega) {
     RingArgs R = ring_args(ctx);
     R.two_omega = two_omega;
-    R.fin = reinterpret_cast<const double2*>(fin);
+    R.part = reinterpret_cast<const double2*>(part);
+    R.segbase = segbase;
+    R.nseg = nseg;
     R.fout = reinterpret_cast<double2*>(fout);
     R.gin = gin;
     R.gout = gout;

@@ -148,7 +148,7 @@ struct MfmaArgs {
     const double2* __restrict__ spec;   // KIND 0: [nf][modes]; KIND 1: state [3][modes]
     double2* __restrict__ four_out;     // [nfo][L+1][nlat]
     // analysis
-    const double2* __restrict__ four_in;  // [nfi][nlat][L+1]
+    const double2* __restrict__ four_in;  // [nfi][L+1][nlat]
     double2* __restrict__ spec_out;       // KIND 0: [nf][modes]
     const double2* __restrict__ U0;       // KIND 1 epilogue, [3][modes]
     const double2* __restrict__ Nprev;
@@ -325,9 +325,9 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
         if (j < A.half) {
             const double wj = A.w[j];
             auto fold = [&](int f, double wt, double2& S, double2& D) {
-                const size_t fb = static_cast<size_t>(f) * A.nlat;
-                const double2 nn = A.four_in[(fb + j) * (A.L + 1) + m];
-                const double2 ss = A.four_in[(fb + A.nlat - 1 - j) * (A.L + 1) + m];
+                const double2* fr = A.four_in + (static_cast<size_t>(f) * (A.L + 1) + m) * A.nlat;
+                const double2 nn = fr[j];
+                const double2 ss = fr[A.nlat - 1 - j];
                 S = make_double2((nn.x + ss.x) * wt, (nn.y + ss.y) * wt);
                 D = make_double2((nn.x - ss.x) * wt, (nn.y - ss.y) * wt);
             };
