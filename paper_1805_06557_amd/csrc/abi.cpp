@@ -203,11 +203,7 @@ int setup_sht(swe_ctx* ctx) {
     // FFT of nlon reals = complex FFT of M = nlon/2 points, M = 2^a 3^b
     const int M = ctx->nlon / 2;
     std::vector<int> radix;
-    int rem = M;
-    while (rem % 4 == 0) { radix.push_back(4); rem /= 4; }
-    while (rem % 2 == 0) { radix.push_back(2); rem /= 2; }
-    while (rem % 3 == 0) { radix.push_back(3); rem /= 3; }
-    if (rem != 1) return fail(REXI_EINVAL, "swe_create: nlon/2 must be of the form 2^a 3^b");
+    if ((rc = ring_plan(M, radix)) != REXI_OK) return rc;
     ctx->npass = static_cast<int>(radix.size());
     if ((rc = upload(&ctx->d_radix, radix.data(), radix.size())) != REXI_OK) return rc;
     std::vector<double> tw, twr;

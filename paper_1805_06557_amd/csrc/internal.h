@@ -250,6 +250,8 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
 int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream);
 // out = x + a y over n doubles (out may equal x or y).
 int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
+// Radix sequence of the longitude FFT of M = nlon/2 complex points.
+int ring_plan(int M, std::vector<int>& radix);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
                 const double* gin, double* gout, int nf, hipStream_t stream, double two_omega = 0.0);

@@ -446,237 +446,279 @@ struct RingArgs {
     double two_omega;                  // mode 2: 2 Omega adds f = 2 Omega mu to zeta (absolute vorticity)
 };
 
-// One Stockham pass of radix R over M complex points, for narr arrays at once
-// (one barrier per pass for all of them): src[a] -> dst[a].
-template <int R>
-__device__ __forceinline__ void fft_pass(double2* const* src, double2* const* dst, int narr, int M, int Ns,
-                                         const double* tw, bool inverse) {
+// LDS arrays hold one padding slot per 8 complex values, so that the strided
+// accesses of a Stockham pass spread over the banks.
+__device__ __forceinline__ int pad8(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int padded_len(int M) { return M + (M >> 3) + 1; }
+
+constexpr int RING_WAVES = 5;        // one wave per field of the forward transforms
+constexpr int RING_MMAX_RT = 1024;   // longest FFT of the runtime-length path
+
+// The lane index as a value the compiler cannot relate to other uses of it.
+// Each pass indexes with its own copy: index arithmetic simplified under one
+// pass's bound (jb < nb) must not be reused by a pass with a larger bound.
+__device__ __forceinline__ int opaque_lane(int lane) {
+    asm volatile("" : "+v"(lane));
+    return lane;
+}
+
+// Makes the LDS writes of every lane of the wave visible to the other lanes'
+// later reads (the wave's LDS operations execute in order; this stops the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- small DFTs, natural order: X_k = sum_n v_n e^{-+ 2 pi i n k / R}
+// (minus sign: forward; plus: INV)
+template <bool INV>
+__device__ __forceinline__ double2 mul_mi(double2 x) {   // x (-i) forward, x (+i) inverse
+    return INV ? make_double2(-x.y, x.x) : make_double2(x.y, -x.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(double2& a0, double2& a1, double2& a2) {
+    constexpr double s = INV ? 0.86602540378443864676 : -0.86602540378443864676;
+    const double2 t1 = cadd(a1, a2), t2 = csub(a1, a2);
+    const double2 m1 = make_double2(__builtin_fma(-0.5, t1.x, a0.x), __builtin_fma(-0.5, t1.y, a0.y));
+    const double2 m2 = make_double2(-s * t2.y, s * t2.x);   // i s t2
+    a0 = cadd(a0, t1);
+    a1 = cadd(m1, m2);
+    a2 = csub(m1, m2);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+    const double2 s0 = cadd(a0, a2), s1 = csub(a0, a2), s2 = cadd(a1, a3), s3 = mul_mi<INV>(csub(a1, a3));
+    a0 = cadd(s0, s2);
+    a2 = csub(s0, s2);
+    a1 = cadd(s1, s3);
+    a3 = csub(s1, s3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(double2* v) {
+    if constexpr (R == 2) {
+        const double2 t = v[0];
+        v[0] = cadd(t, v[1]);
+        v[1] = csub(t, v[1]);
+    } else if constexpr (R == 3) {
+        dft3<INV>(v[0], v[1], v[2]);
+    } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3]);
+    } else if constexpr (R == 6) {
+        // X_k = E_k + w6^k O_k, X_{k+3} = E_k - w6^k O_k (E, O: 3-point DFTs of
+        // the even and odd samples)
+        double2 e0 = v[0], e1 = v[2], e2 = v[4], o0 = v[1], o1 = v[3], o2 = v[5];
+        dft3<INV>(e0, e1, e2);
+        dft3<INV>(o0, o1, o2);
+        constexpr double h = 0.86602540378443864676;
+        o1 = cmul(o1, make_double2(0.5, INV ? h : -h));
+        o2 = cmul(o2, make_double2(-0.5, INV ? h : -h));
+        v[0] = cadd(e0, o0);
+        v[3] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[4] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[5] = csub(e2, o2);
+    } else {
+        static_assert(R == 8, "radix 2, 3, 4, 6 or 8");
+        // X_k = E_k + w8^k O_k, X_{k+4} = E_k - w8^k O_k
+        double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+        dft4<INV>(e0, e1, e2, e3);
+        dft4<INV>(o0, o1, o2, o3);
+        constexpr double c = 0.70710678118654752440;
+        o1 = INV ? make_double2(c * (o1.x - o1.y), c * (o1.x + o1.y)) : make_double2(c * (o1.x + o1.y), c * (o1.y - o1.x));
+        o2 = mul_mi<INV>(o2);
+        o3 = INV ? make_double2(-c * (o3.x + o3.y), c * (o3.x - o3.y)) : make_double2(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+        v[0] = cadd(e0, o0);
+        v[4] = csub(e0, o0);
+        v[1] = cadd(e1, o1);
+        v[5] = csub(e1, o1);
+        v[2] = cadd(e2, o2);
+        v[6] = csub(e2, o2);
+        v[3] = cadd(e3, o3);
+        v[7] = csub(e3, o3);
+    }
+}
+
+// Radix of the next Stockham pass when rem = M / Ns points per sub-transform
+// remain (host and device use the same rule).
+__host__ __device__ constexpr int ring_radix(int rem) {
+    return rem == 6 ? 6 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 6 == 0 ? 6 : rem % 2 == 0 ? 2 : 3;
+}
+
+// One Stockham pass of radix R over the M complex values of the wave's LDS
+// array x (padded), in place: every lane first reads and transforms all its
+// butterflies, then writes them.  Ns = product of the radices already applied;
+// tw: e^{-2 pi i k / M} (padded).  MC, NSC: compile-time M and Ns (0: runtime).
+template <int R, bool INV, int MC, int NSC>
+__device__ __forceinline__ void wave_pass(double2* x, int Mr, int Nsr, const double2* tw, int lane) {
+    const int M = MC > 0 ? MC : Mr;
+    const int Ns = NSC > 0 ? NSC : Nsr;
     const int nb = M / R;
     const int twstep = M / (Ns * R);
-    const int total = nb * narr;
-    for (int x = threadIdx.x; x < total; x += blockDim.x) {
-        const int a = x / nb;
-        const int jb = x - a * nb;
-        const double2* sa = src[a];
-        double2* da = dst[a];
-        const int k = jb % Ns;
-        double2 v[R];
+    constexpr int BPL = ((MC > 0 ? MC : RING_MMAX_RT) / R + WAVE - 1) / WAVE;   // butterflies per lane
+    lane = opaque_lane(lane);
+    double2 v[BPL][R];
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            v[t] = sa[jb + t * nb];
-            if (t > 0) {
-                const int ti = (t * k * twstep) % M;
-                double2 wv = make_double2(tw[2 * ti], tw[2 * ti + 1]);
-                if (inverse) wv.y = -wv.y;
-                v[t] = cmul(v[t], wv);
+    for (int b = 0; b < BPL; ++b) {
+        const int jb = lane + b * WAVE;
+        if (jb < nb) {
+            const int k = jb % Ns;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                double2 val = x[pad8(jb + t * nb)];
+                if (t > 0 && (NSC != 1)) {
+                    double2 w = tw[pad8(t * k * twstep)];
+                    if (INV) w.y = -w.y;
+                    val = cmul(val, w);
+                }
+                v[b][t] = val;
             }
+            dft<R, INV>(v[b]);
         }
-        if constexpr (R == 2) {
-            const double2 a0 = v[0], b0 = v[1];
-            v[0] = cadd(a0, b0);
-            v[1] = csub(a0, b0);
-        } else if constexpr (R == 4) {
-            const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-            const double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
-            // multiply b1 by -i (forward) or +i (inverse)
-            const double2 b1r = inverse ? make_double2(-b1.y, b1.x) : make_double2(b1.y, -b1.x);
-            v[0] = cadd(a0, b0);
-            v[2] = csub(a0, b0);
-            v[1] = cadd(a1, b1r);
-            v[3] = csub(a1, b1r);
-        } else {  // R == 3
-            const double c = -0.5;
-            const double s = inverse ? 0.86602540378443864676 : -0.86602540378443864676;
-            const double2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
-            const double2 m1 = make_double2(__builtin_fma(c, t1.x, v[0].x), __builtin_fma(c, t1.y, v[0].y));
-            const double2 m2 = make_double2(-s * t2.y, s * t2.x);   // i s t2
-            v[0] = cadd(v[0], t1);
-            v[1] = cadd(m1, m2);
-            v[2] = csub(m1, m2);
-        }
-        const int base = (jb / Ns) * Ns * R + k;
+    }
+    wave_sync();
 #pragma unroll
-        for (int t = 0; t < R; ++t) da[base + t * Ns] = v[t];
+    for (int b = 0; b < BPL; ++b) {
+        const int jb = lane + b * WAVE;
+        if (jb < nb) {
+            const int k = jb % Ns;
+            const int base = (jb / Ns) * Ns * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) x[pad8(base + t * Ns)] = v[b][t];
+        }
+    }
+    wave_sync();
+}
+
+// Complex FFT of length M of the wave's array x: compile-time M ...
+template <int M, int NS, bool INV>
+__device__ __forceinline__ void wave_fft_ct(double2* x, const double2* tw, int lane) {
+    if constexpr (NS < M) {
+        constexpr int R = ring_radix(M / NS);
+        static_assert((M / NS) % R == 0, "FFT length must be 2^a 3^b");
+        wave_pass<R, INV, M, NS>(x, M, NS, tw, lane);
+        wave_fft_ct<M, NS * R, INV>(x, tw, lane);
     }
 }
 
-constexpr int MAXB = 4;   // arrays transformed together
-
-// Complex FFTs of length M of narr (<= MAXB) arrays in LDS, ping-ponging with
-// the scratch arrays; res[a] receives the buffer holding the result of array a.
-__device__ void fft_lds(double2* const* a, double2* const* scratch, int narr, const RingArgs& A, bool inverse,
-                        double2** res) {
+// ... or runtime M (passes from the context's radix list).
+template <bool INV>
+__device__ void wave_fft_rt(double2* x, const RingArgs& A, const double2* tw, int lane) {
     const int M = A.nlon / 2;
     int Ns = 1;
-    double2* src[MAXB];
-    double2* dst[MAXB];
-    for (int i = 0; i < MAXB; ++i) {
-        src[i] = i < narr ? a[i] : a[0];
-        dst[i] = i < narr ? scratch[i] : scratch[0];
-    }
     for (int p = 0; p < A.npass; ++p) {
         const int R = A.radix[p];
-        if (R == 4) fft_pass<4>(src, dst, narr, M, Ns, A.tw, inverse);
-        else if (R == 2) fft_pass<2>(src, dst, narr, M, Ns, A.tw, inverse);
-        else fft_pass<3>(src, dst, narr, M, Ns, A.tw, inverse);
-        __syncthreads();
+        if (R == 8) wave_pass<8, INV, 0, 0>(x, M, Ns, tw, lane);
+        else if (R == 6) wave_pass<6, INV, 0, 0>(x, M, Ns, tw, lane);
+        else if (R == 4) wave_pass<4, INV, 0, 0>(x, M, Ns, tw, lane);
+        else if (R == 2) wave_pass<2, INV, 0, 0>(x, M, Ns, tw, lane);
+        else wave_pass<3, INV, 0, 0>(x, M, Ns, tw, lane);
         Ns *= R;
-        for (int i = 0; i < MAXB; ++i) {
-            double2* t = src[i];
-            src[i] = dst[i];
-            dst[i] = t;
-        }
-    }
-    for (int i = 0; i < narr; ++i) res[i] = src[i];
-}
-
-// Compile-time-length variant: the pass sequence (radix 4, then 2, then 3) is
-// fixed by M, every index division is by a constant, and the twiddles are read
-// from LDS.  The result is in `a` after an even number of passes, else in `scratch`.
-template <int R, int M, int NS, bool INV>
-__device__ __forceinline__ void fft_pass_ct(double2* const* src, double2* const* dst, int narr, const double2* tw) {
-    constexpr int nb = M / R;
-    constexpr int twstep = M / (NS * R);
-    const int total = nb * narr;
-    for (int x = threadIdx.x; x < total; x += blockDim.x) {
-        const int a = x / nb;
-        const int jb = x - a * nb;
-        const double2* sa = src[a];
-        double2* da = dst[a];
-        const int k = jb % NS;
-        double2 v[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            v[t] = sa[jb + t * nb];
-            if (t > 0) {
-                double2 wv = tw[t * k * twstep];
-                if (INV) wv.y = -wv.y;
-                v[t] = cmul(v[t], wv);
-            }
-        }
-        if constexpr (R == 2) {
-            const double2 a0 = v[0], b0 = v[1];
-            v[0] = cadd(a0, b0);
-            v[1] = csub(a0, b0);
-        } else if constexpr (R == 4) {
-            const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-            const double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
-            const double2 b1r = INV ? make_double2(-b1.y, b1.x) : make_double2(b1.y, -b1.x);
-            v[0] = cadd(a0, b0);
-            v[2] = csub(a0, b0);
-            v[1] = cadd(a1, b1r);
-            v[3] = csub(a1, b1r);
-        } else {
-            constexpr double c = -0.5;
-            constexpr double s = INV ? 0.86602540378443864676 : -0.86602540378443864676;
-            const double2 t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
-            const double2 m1 = make_double2(__builtin_fma(c, t1.x, v[0].x), __builtin_fma(c, t1.y, v[0].y));
-            const double2 m2 = make_double2(-s * t2.y, s * t2.x);
-            v[0] = cadd(v[0], t1);
-            v[1] = cadd(m1, m2);
-            v[2] = csub(m1, m2);
-        }
-        const int base = (jb / NS) * NS * R + k;
-#pragma unroll
-        for (int t = 0; t < R; ++t) da[base + t * NS] = v[t];
     }
 }
 
-template <int M, int NS, bool INV>
-__device__ __forceinline__ int fft_passes_ct(double2* const* src, double2* const* dst, int narr, const double2* tw) {
-    if constexpr (NS >= M) {
-        return 0;
+template <int MC, bool INV>
+__device__ __forceinline__ void wave_fft(double2* x, const RingArgs& A, const double2* tw, int lane) {
+    if constexpr (MC > 0) wave_fft_ct<MC, 1, INV>(x, tw, lane);
+    else wave_fft_rt<INV>(x, A, tw, lane);
+}
+
+// Fourier coefficients F_m (m <= L) of field f at latitude j into the wave's
+// array x: each the sum of its order's segment partials (the first segment of
+// every order the lane holds is loaded before any is added).
+template <int MC>
+__device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j, double2* x, int lane) {
+    const double2* pf = A.part + static_cast<size_t>(f) * A.nseg * A.nlat + j;
+    lane = opaque_lane(lane);
+    if constexpr (MC > 0) {
+        constexpr int MPL = (MC + WAVE - 1) / WAVE;   // orders per lane (L < M)
+        double2 acc[MPL];
+        int g0[MPL], g1[MPL];
+#pragma unroll
+        for (int i = 0; i < MPL; ++i) {
+            const int m = lane + i * WAVE;
+            const bool ok = m <= A.L;
+            g0[i] = ok ? A.segbase[m] : 0;
+            g1[i] = ok ? A.segbase[m + 1] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < MPL; ++i)
+            acc[i] = g0[i] < g1[i] ? pf[static_cast<size_t>(g0[i]) * A.nlat] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < MPL; ++i) {
+            for (int g = g0[i] + 1; g < g1[i]; ++g) acc[i] = cadd(acc[i], pf[static_cast<size_t>(g) * A.nlat]);
+            const int m = lane + i * WAVE;
+            if (m <= A.L) x[pad8(m)] = acc[i];
+        }
     } else {
-        constexpr int rem = M / NS;
-        constexpr int R = (rem % 4 == 0) ? 4 : (rem % 2 == 0) ? 2 : 3;
-        static_assert(rem % R == 0, "FFT length must be 2^a 3^b");
-        fft_pass_ct<R, M, NS, INV>(src, dst, narr, tw);
-        __syncthreads();
-        return 1 + fft_passes_ct<M, NS * R, INV>(dst, src, narr, tw);
+        for (int m = lane; m <= A.L; m += WAVE) {
+            double2 acc = make_double2(0.0, 0.0);
+            const int g1 = A.segbase[m + 1];
+            for (int g = A.segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
+            x[pad8(m)] = acc;
+        }
     }
+    wave_sync();
 }
 
-template <int M, bool INV>
-__device__ __forceinline__ void fft_lds_ct(double2* const* a, double2* const* scratch, int narr, const double2* tw,
-                                           double2** res) {
-    double2* src[MAXB];
-    double2* dst[MAXB];
-    for (int i = 0; i < MAXB; ++i) {
-        src[i] = i < narr ? a[i] : a[0];
-        dst[i] = i < narr ? scratch[i] : scratch[0];
-    }
-    const int np = fft_passes_ct<M, 1, INV>(src, dst, narr, tw);
-    for (int i = 0; i < narr; ++i) res[i] = (np & 1) ? dst[i] : src[i];
-}
-
-// Fourier coefficients F_m (m <= L) of latitude j for fields f0 .. f0 + nb - 1
-// into the LDS rows x[b]: each the sum of its order's segment partials.
-__device__ void load_coeffs(const RingArgs& A, int f0, int nb, int j, double2* const* x) {
-    const int n = nb * (A.L + 1);
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const int b = t / (A.L + 1), m = t - b * (A.L + 1);
-        const double2* pf = A.part + static_cast<size_t>(f0 + b) * A.nseg * A.nlat + j;
-        double2 acc = make_double2(0.0, 0.0);
-        const int g1 = A.segbase[m + 1];
-        for (int g = A.segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
-        x[b][m] = acc;
-    }
-}
-
-// From the LDS row F_m (m <= L) of one latitude, the half-length spectrum Z of
-// the inverse real FFT:
+// In place on the wave's array: F_m (m <= L) -> the half-length spectrum Z of
+// the inverse real FFT,
 //   Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/nlon} (X_k - conj X_{M-k}),
-// X_0 taken real, X_k = 0 for k > L.
-__device__ void load_inverse(const double2* frow, double2* z, const RingArgs& A) {
-    const int M = A.nlon / 2;
-    for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        double2 xk = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
-        if (k <= A.L) xk = frow[k];
-        const int kr = M - k;                      // 1..M
-        if (kr <= A.L && kr < M) xr = frow[kr];
-        if (k == 0) xk.y = 0.0;
-        const double2 xrc = conj2(xr);
-        const double2 s = cadd(xk, xrc);
-        const double2 d = csub(xk, xrc);
-        const double2 wk = make_double2(A.twr[2 * k], -A.twr[2 * k + 1]);  // e^{+2 pi i k / nlon}
-        const double2 t = cmul(wk, d);
-        z[k] = make_double2(s.x - t.y, s.y + t.x);                             // s + i t
+// X_0 taken real, X_k = 0 for k > L.  twr: e^{-2 pi i k / nlon} (padded).
+template <int MC>
+__device__ __forceinline__ void wave_pack_inverse(const RingArgs& A, double2* x, const double2* twr, int lane) {
+    const int M = MC > 0 ? MC : A.nlon / 2;
+    constexpr int KPL = ((MC > 0 ? MC : RING_MMAX_RT) + WAVE - 1) / WAVE;
+    lane = opaque_lane(lane);
+    double2 z[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + i * WAVE;
+        if (k < M) {
+            double2 xk = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
+            if (k <= A.L) xk = x[pad8(k)];
+            const int kr = M - k;                      // 1..M
+            if (kr <= A.L && kr < M) xr = x[pad8(kr)];
+            if (k == 0) xk.y = 0.0;
+            const double2 xrc = conj2(xr);
+            const double2 sm = cadd(xk, xrc);
+            const double2 df = csub(xk, xrc);
+            const double2 tk = twr[pad8(k)];
+            const double2 t = cmul(make_double2(tk.x, -tk.y), df);   // e^{+2 pi i k / nlon} d
+            z[i] = make_double2(sm.x - t.y, sm.y + t.x);             // s + i t
+        }
     }
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + i * WAVE;
+        if (k < M) x[pad8(k)] = z[i];
+    }
+    wave_sync();
 }
 
-// From Z = FFT_M(x viewed as complex), the coefficients F_m = X_m / nlon, m <= L:
-// X_m = (Z_m + conj Z_{M-m})/2 - (i/2) e^{-2 pi i m/nlon} (Z_m - conj Z_{M-m}).
-// frow points at F_0 of the latitude; consecutive orders are nlat apart.
-__device__ void store_forward(const double2* Z, double2* frow, const RingArgs& A) {
+// From Z = FFT_M(grid row viewed as complex) in the wave's array, the
+// coefficients F_m = X_m / nlon, m <= L,
+//   X_m = (Z_m + conj Z_{M-m})/2 - (i/2) e^{-2 pi i m/nlon} (Z_m - conj Z_{M-m}),
+// written to frow[m nlat] (order-major buffer).
+__device__ __forceinline__ void wave_store_forward(const RingArgs& A, const double2* x, const double2* twr,
+                                                   double2* frow, int lane) {
     const int M = A.nlon / 2;
     const double inv = 1.0 / static_cast<double>(A.nlon);
-    for (int k = threadIdx.x; k <= A.L; k += blockDim.x) {
-        const double2 zk = Z[k];
-        const double2 zr = conj2(Z[k == 0 ? 0 : M - k]);
-        const double2 s = cadd(zk, zr);
-        const double2 d = csub(zk, zr);
-        const double2 wk = make_double2(A.twr[2 * k], A.twr[2 * k + 1]);   // e^{-2 pi i k / nlon}
-        const double2 t = cmul(wk, d);
-        // X = s/2 - i t/2
-        const double2 X = make_double2(0.5 * (s.x + t.y), 0.5 * (s.y - t.x));
+    lane = opaque_lane(lane);
+    for (int k = lane; k <= A.L; k += WAVE) {
+        const double2 zk = x[pad8(k)];
+        const double2 zr = conj2(x[pad8(k == 0 ? 0 : M - k)]);
+        const double2 sm = cadd(zk, zr);
+        const double2 df = csub(zk, zr);
+        const double2 t = cmul(twr[pad8(k)], df);
+        const double2 X = make_double2(0.5 * (sm.x + t.y), 0.5 * (sm.y - t.x));   // s/2 - i t/2
         frow[static_cast<size_t>(k) * A.nlat] = scale2(X, inv);
-    }
-}
-
-// MODE 0: inverse only (Fourier -> grid), nf fields, MAXB at a time.
-// MODE 1: forward only (grid -> Fourier), nf fields, MAXB at a time.
-// MODE 2: non-linear products: inverse of h, zeta, U, V; pointwise
-//         hU, hV, zU, zV, KE = (U^2 + V^2) / (2 cos^2 phi); forward of those five.
-// LDS: 2 MAXB arrays of nlon/2 complex values.
-// Transforms of `narr` arrays: compile-time length MC when nonzero, else runtime.
-template <int MC>
-__device__ __forceinline__ void ring_fft(double2* const* a, double2* const* scratch, int narr, const RingArgs& A,
-                                         const double2* twl, bool inverse, double2** res) {
-    if constexpr (MC > 0) {
-        if (inverse) fft_lds_ct<MC, true>(a, scratch, narr, twl, res);
-        else fft_lds_ct<MC, false>(a, scratch, narr, twl, res);
-    } else {
-        fft_lds(a, scratch, narr, A, inverse, res);
     }
 }
 
@@ -688,103 +730,84 @@ __device__ __forceinline__ int ring_of_block(int b, int nlat) {
     return (b % 8) * (nlat / 8) + b / 8;
 }
 
+// One workgroup per latitude ring, RING_WAVES waves, each transforming one
+// field in its own LDS array with wave-local synchronisation only.
+// MODE 0: inverse only (Fourier -> grid), nf fields.
+// MODE 1: forward only (grid -> Fourier), nf fields.
+// MODE 2: non-linear products: inverse of h, zeta, U, V (waves 0-3); pointwise
+//         hU, hV, zU, zV, KE = (U^2 + V^2) / (2 cos^2 phi) (whole workgroup);
+//         forward of those five (waves 0-4).
+// LDS: RING_WAVES padded arrays of M complex values, then the twiddles
+// e^{-2 pi i k / M} and e^{-2 pi i k / nlon} (padded).
 template <int MODE, int MC>
-__global__ __launch_bounds__(256) void ring_kernel(RingArgs A) {
+__global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
     extern __shared__ __align__(16) double2 lds[];
-    const int M = A.nlon / 2;
+    const int M = MC > 0 ? MC : A.nlon / 2;
+    const int PL = padded_len(M);
     const int j = ring_of_block(blockIdx.x, A.nlat);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // one field of [L+1][nlat]
-    const size_t row = static_cast<size_t>(j);
-    double2* arr[2 * MAXB];
-#pragma unroll
-    for (int i = 0; i < 2 * MAXB; ++i) arr[i] = lds + i * M;
-    double2* res[MAXB];
-    double2* twl = lds + 2 * MAXB * M;               // twiddles (compile-time lengths only)
-    if constexpr (MC > 0) {
-        for (int k = threadIdx.x; k < M; k += blockDim.x) twl[k] = make_double2(A.tw[2 * k], A.tw[2 * k + 1]);
+    double2* tw = lds + RING_WAVES * PL;
+    double2* twr = tw + PL;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        tw[pad8(k)] = make_double2(A.tw[2 * k], A.tw[2 * k + 1]);
+        twr[pad8(k)] = make_double2(A.twr[2 * k], A.twr[2 * k + 1]);
     }
+    double2* x = lds + wv * PL;
     if constexpr (MODE == 0) {
-        for (int f0 = 0; f0 < A.nf; f0 += MAXB) {
-            const int nb = min(MAXB, A.nf - f0);
-            load_coeffs(A, f0, nb, j, arr + MAXB);
-            __syncthreads();
-            for (int b = 0; b < nb; ++b) load_inverse(arr[MAXB + b], arr[b], A);
-            __syncthreads();
-            ring_fft<MC>(arr, arr + MAXB, nb, A, twl, true, res);
-            for (int b = 0; b < nb; ++b) {
-                double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f0 + b) * A.nlat + j) * A.nlon);
-                for (int k = threadIdx.x; k < M; k += blockDim.x) g[k] = res[b][k];
-            }
-            __syncthreads();
+        __syncthreads();
+        for (int f = wv; f < A.nf; f += RING_WAVES) {
+            wave_load_coeffs<MC>(A, f, j, x, lane);
+            wave_pack_inverse<MC>(A, x, twr, lane);
+            wave_fft<MC, true>(x, A, tw, lane);
+            double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
+            for (int k = lane; k < M; k += WAVE) g[k] = x[pad8(k)];
+            wave_sync();
         }
     } else if constexpr (MODE == 1) {
-        for (int f0 = 0; f0 < A.nf; f0 += MAXB) {
-            const int nb = min(MAXB, A.nf - f0);
-            for (int b = 0; b < nb; ++b) {
-                const double2* g =
-                    reinterpret_cast<const double2*>(A.gin + (static_cast<size_t>(f0 + b) * A.nlat + j) * A.nlon);
-                for (int k = threadIdx.x; k < M; k += blockDim.x) arr[b][k] = g[k];
-            }
-            __syncthreads();
-            ring_fft<MC>(arr, arr + MAXB, nb, A, twl, false, res);
-            for (int b = 0; b < nb; ++b) store_forward(res[b], A.fout + (f0 + b) * fstride + row, A);
-            __syncthreads();
+        __syncthreads();
+        for (int f = wv; f < A.nf; f += RING_WAVES) {
+            const double2* g =
+                reinterpret_cast<const double2*>(A.gin + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
+            for (int k = lane; k < M; k += WAVE) x[pad8(k)] = g[k];
+            wave_sync();
+            wave_fft<MC, false>(x, A, tw, lane);
+            wave_store_forward(A, x, twr, A.fout + f * fstride + j, lane);
+            wave_sync();
         }
     } else {
-        load_coeffs(A, 0, 4, j, arr + MAXB);
-        __syncthreads();
-        for (int f = 0; f < 4; ++f) load_inverse(arr[MAXB + f], arr[f], A);
-        __syncthreads();
-        ring_fft<MC>(arr, arr + MAXB, 4, A, twl, true, res);
-        // the four arrays not holding results are free
-        double2* freea[MAXB];
-        {
-            int nfree = 0;
-            for (int i = 0; i < 2 * MAXB; ++i) {
-                bool used = false;
-                for (int b = 0; b < MAXB; ++b) used |= (arr[i] == res[b]);
-                if (!used) freea[nfree++] = arr[i];
-            }
+        if (wv < 4) wave_load_coeffs<MC>(A, wv, j, x, lane);
+        __syncthreads();                                   // twiddles
+        if (wv < 4) {
+            wave_pack_inverse<MC>(A, x, twr, lane);
+            wave_fft<MC, true>(x, A, tw, lane);
         }
+        __syncthreads();
+        // grid values: complex slot e of an array holds the grid points 2e, 2e + 1
         const int jn = j < A.half ? j : A.nlat - 1 - j;
         const double sn = A.sint[jn];
         const double kefac = 0.5 / (sn * sn);
         const double fcor = A.two_omega * (j < A.half ? A.mu[jn] : -A.mu[jn]);   // 0 unless L_c joins N
-        double* h = reinterpret_cast<double*>(res[0]);
-        double* z = reinterpret_cast<double*>(res[1]);
-        const double* U = reinterpret_cast<const double*>(res[2]);
-        double* V = reinterpret_cast<double*>(res[3]);
-        double* ke = reinterpret_cast<double*>(freea[0]);
-        double* hv = reinterpret_cast<double*>(freea[1]);
-        for (int k = threadIdx.x; k < A.nlon; k += blockDim.x) {
-            const double u = U[k], v = V[k], hh = h[k], zz = z[k] + fcor;
-            ke[k] = __builtin_fma(u, u, v * v) * kefac;
-            hv[k] = hh * v;
-            V[k] = zz * v;          // zeta V
-            h[k] = hh * u;          // h U
-            z[k] = zz * u;          // zeta U
+        double2* ah = lds;                 // h  -> hU
+        double2* az = lds + PL;            // zeta -> zeta U
+        double2* aU = lds + 2 * PL;        // U  -> hV
+        double2* aV = lds + 3 * PL;        // V  -> zeta V
+        double2* ak = lds + 4 * PL;        //    -> KE
+        for (int e = threadIdx.x; e < M; e += blockDim.x) {
+            const int pe = pad8(e);
+            const double2 u = aU[pe], v = aV[pe], hh = ah[pe], z0 = az[pe];
+            const double2 zz = make_double2(z0.x + fcor, z0.y + fcor);
+            ak[pe] = make_double2(__builtin_fma(u.x, u.x, v.x * v.x) * kefac, __builtin_fma(u.y, u.y, v.y * v.y) * kefac);
+            aU[pe] = make_double2(hh.x * v.x, hh.y * v.y);
+            aV[pe] = make_double2(zz.x * v.x, zz.y * v.y);
+            ah[pe] = make_double2(hh.x * u.x, hh.y * u.y);
+            az[pe] = make_double2(zz.x * u.x, zz.y * u.y);
         }
         __syncthreads();
-        // forward transforms in two batches: (hU, hV, zU) then (zV, KE);
-        // output fields 0 hU, 1 hV, 2 zU, 3 zV, 4 KE
-        {
-            double2* in3[MAXB] = {res[0], freea[1], res[1], res[1]};
-            double2* sc3[MAXB] = {res[2], freea[2], freea[3], freea[3]};
-            double2* out3[MAXB];
-            ring_fft<MC>(in3, sc3, 3, A, twl, false, out3);
-            store_forward(out3[0], A.fout + 0 * fstride + row, A);
-            store_forward(out3[1], A.fout + 1 * fstride + row, A);
-            store_forward(out3[2], A.fout + 2 * fstride + row, A);
-        }
-        __syncthreads();   // batch 1 outputs are read before their arrays become scratch
-        {
-            double2* in2[MAXB] = {res[3], freea[0], res[3], res[3]};
-            double2* sc2[MAXB] = {res[2], freea[2], res[2], res[2]};
-            double2* out2[MAXB];
-            ring_fft<MC>(in2, sc2, 2, A, twl, false, out2);
-            store_forward(out2[0], A.fout + 3 * fstride + row, A);
-            store_forward(out2[1], A.fout + 4 * fstride + row, A);
-        }
+        // output fields 0 hU, 1 hV, 2 zU, 3 zV, 4 KE: wave w transforms field w
+        double2* xf = lds + (wv == 1 ? 2 : wv == 2 ? 1 : wv) * PL;
+        wave_fft<MC, false>(xf, A, tw, lane);
+        wave_store_forward(A, xf, twr, A.fout + wv * fstride + j, lane);
     }
 }
 
@@ -845,7 +868,7 @@ static RingArgs ring_args(const swe_ctx* ctx) {
 
 static int ring_lds_bytes(const swe_ctx* ctx, int /*mode*/) {
     const int M = ctx->nlon / 2;
-    return (2 * MAXB + 1) * M * static_cast<int>(sizeof(double2));
+    return (RING_WAVES + 2) * padded_len(M) * static_cast<int>(sizeof(double2));
 }
 
 template <int MODE>
@@ -869,9 +892,23 @@ static int allow_lds(const void* fn, size_t bytes, const char* what) {
     return REXI_OK;
 }
 
+int ring_plan(int M, std::vector<int>& radix) {
+    radix.clear();
+    int rem = M;
+    while (rem > 1) {
+        const int R = ring_radix(rem);
+        if (rem % R) return fail(REXI_EINVAL, "swe_create: nlon/2 must be of the form 2^a 3^b");
+        radix.push_back(R);
+        rem /= R;
+    }
+    return REXI_OK;
+}
+
 int sht_configure_kernels(swe_ctx* ctx) {
     int rc;
     const int M = ctx->nlon / 2;
+    if (ring_fn<2>(M) == ring_fn<2>(0) && M > RING_MMAX_RT)
+        return fail(REXI_ENOTSUP, "swe_create: nlon/2 beyond 1024 outside the compiled FFT lengths");
     if ((rc = allow_lds(ring_fn<0>(M), ring_lds_bytes(ctx, 0), "the longitude FFT")) != REXI_OK) return rc;
     if ((rc = allow_lds(ring_fn<1>(M), ring_lds_bytes(ctx, 1), "the longitude FFT")) != REXI_OK) return rc;
     if ((rc = allow_lds(ring_fn<2>(M), ring_lds_bytes(ctx, 2), "the longitude FFT")) != REXI_OK) return rc;
@@ -962,7 +999,7 @@ int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, 
     const int M = ctx->nlon / 2;
     const void* fn = mode == 0 ? ring_fn<0>(M) : (mode == 1 ? ring_fn<1>(M) : ring_fn<2>(M));
     void* kargs[] = {&R};
-    REXI_HIP(hipLaunchKernel(fn, dim3(ctx->nlat), dim3(256), kargs, lds, stream));
+    REXI_HIP(hipLaunchKernel(fn, dim3(ctx->nlat), dim3(RING_WAVES * WAVE), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_RING, slot, stream);
     return REXI_OK;
