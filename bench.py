@@ -151,22 +151,22 @@ def _split_blocks(L, nlat):
     hpad = (nlat // 2 + 15) // 16 * 16
     rows = 0
     for m in range(L + 1):
-        Lm = L - m + 1
-        rows += ((Lm + 1) // 2 + 15) // 16 * 16 + (Lm // 2 + 15) // 16 * 16
+        n = L - m + 2                      # degrees m .. L+1
+        rows += ((n + 1) // 2 + 15) // 16 * 16 + (n // 2 + 15) // 16 * 16
     return hpad, rows
 
 
 def split_mfma_flops(L, nlat):
     """Matrix-core flops of one split-precision Legendre launch of the non-linear
-    set (Pbar and H products, three bf16 products each, 16x16x16 tiles incl. padding)."""
+    set (one Pbar product, three bf16 products, 16x16x16 tiles incl. padding)."""
     hpad, rows = _split_blocks(L, nlat)
-    return 2 * 3 * (hpad // 16) * (rows // 16) * 2 * 16 * 16 * 16
+    return 3 * (hpad // 16) * (rows // 16) * 2 * 16 * 16 * 16
 
 
 def split_table_bytes(L, nlat):
-    """Bytes of the two tables (Pbar, H; hi and lo) one such launch streams."""
+    """Bytes of the Pbar table (hi and lo) one such launch streams."""
     hpad, rows = _split_blocks(L, nlat)
-    return 2 * rows * hpad * 2 * 2
+    return rows * hpad * 2 * 2
 
 
 def step_error_vs_fp64(ctx, w, alpha, beta):

@@ -164,14 +164,15 @@ int setup_sht(swe_ctx* ctx) {
     if ((rc = upload(&ctx->d_seed_p, sg.seed_p.data(), sg.seed_p.size())) != REXI_OK) return rc;
     if ((rc = upload(&ctx->d_seed_e, sg.seed_e.data(), sg.seed_e.size())) != REXI_OK) return rc;
     if (ctx->prec & REXI_PREC_BF16_SPLIT) {
-        // row blocks per (m, parity of l - m) padded to 16, latitudes padded to 16
+        // row blocks per (m, parity of l - m) for degrees m .. L+1, padded to 16;
+        // latitudes padded to 16
         const int half = ctx->nlat / 2;
         ctx->tab_hpad = (half + 15) / 16 * 16;
         std::vector<int> kp(2 * (ctx->L + 1));
         std::vector<long long> off(ctx->L + 2, 0);
         int kmax = 16;
         for (int m = 0; m <= ctx->L; ++m) {
-            const int Lm = ctx->L - m + 1;
+            const int Lm = ctx->L - m + 2;
             kp[2 * m] = ((Lm + 1) / 2 + 15) / 16 * 16;
             kp[2 * m + 1] = (Lm / 2 + 15) / 16 * 16;
             kmax = std::max(kmax, std::max(kp[2 * m], kp[2 * m + 1]));
@@ -184,17 +185,7 @@ int setup_sht(swe_ctx* ctx) {
         std::vector<int> segid(ctx->L + 2);
         for (int m = 0; m <= ctx->L + 1; ++m) segid[m] = m;
         if ((rc = upload(&ctx->d_tab_segid, segid.data(), segid.size())) != REXI_OK) return rc;
-        // analysis workgroups: four row tiles of one order each, orders with
-        // the most degrees first
-        std::vector<int> ablk;
-        for (int m = 0; m <= ctx->L; ++m)
-            for (int t = 0; t < (kp[2 * m] + kp[2 * m + 1]) / 16; t += 4) {
-                ablk.push_back(m);
-                ablk.push_back(t);
-            }
-        ctx->tab_nablk = static_cast<int>(ablk.size() / 2);
-        if ((rc = upload(&ctx->d_tab_ablk, ablk.data(), ablk.size())) != REXI_OK) return rc;
-        for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_hsyn, &ctx->d_tab_pana, &ctx->d_tab_hana})
+        for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_pana})
             if (hipMalloc(reinterpret_cast<void**>(t), sizeof(unsigned short) * ctx->tab_len) != hipSuccess)
                 return fail(REXI_ENOMEM, "swe_create: cannot allocate the split-precision Legendre tables");
         if ((rc = build_split_tables(ctx, nullptr)) != REXI_OK) return rc;
@@ -425,8 +416,7 @@ int swe_destroy(swe_ctx* ctx) {
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
-                        ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid,
-                        ctx->d_tab_ablk};
+                        ctx->d_tab_pana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {

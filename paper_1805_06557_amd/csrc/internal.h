@@ -189,19 +189,17 @@ struct swe_ctx {
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
-    // split-precision Legendre tables (REXI_PREC_BF16_SPLIT): Pbar and H as bf16
-    // (hi, lo) pairs in a latitude-major (synthesis) and a degree-major
-    // (analysis) layout; order m starts at tab_off[m], each (m, parity) block
-    // has tab_kp[2m + parity] rows (padded to 16) by tab_hpad latitudes
+    // split-precision Legendre table (REXI_PREC_BF16_SPLIT): Pbar for degrees
+    // m .. L+1 as bf16 (hi, lo) pairs in a latitude-major (synthesis) and a
+    // degree-major (analysis) layout; order m starts at tab_off[m], each
+    // (m, parity) block has tab_kp[2m + parity] rows (padded to 16) by tab_hpad
+    // latitudes
     unsigned short* d_tab_psyn = nullptr;
-    unsigned short* d_tab_hsyn = nullptr;
     unsigned short* d_tab_pana = nullptr;
-    unsigned short* d_tab_hana = nullptr;
     long long* d_tab_off = nullptr;   // [L+2]
     int* d_tab_segid = nullptr;       // [L+2] m: one Fourier row per order
     int* d_tab_kp = nullptr;          // [2 (L+1)]
-    int* d_tab_ablk = nullptr;        // [2 tab_nablk] analysis workgroups (m, first row tile)
-    int tab_hpad = 0, tab_kmax = 0, tab_nablk = 0;
+    int tab_hpad = 0, tab_kmax = 0;
     size_t tab_len = 0;               // shorts per table
     double* d_tmpA = nullptr;         // Strang intermediates [3][modes]
     double* d_tmpB = nullptr;

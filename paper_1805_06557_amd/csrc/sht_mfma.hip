@@ -1,22 +1,28 @@
 // Legendre stage on the matrix cores, split BF16 precision (REXI_PREC_BF16_SPLIT).
 //
 // For one zonal order m the Legendre transforms are dense products with the
-// matrix T[l][j] = Pbar_lm(mu_j) (and H_lm(mu_j) = (1-mu_j^2) dPbar_lm/dmu for
-// the vector fields) over the northern Gauss latitudes j (Section 3.2):
+// matrix T[l][j] = Pbar_lm(mu_j) over the northern Gauss latitudes j
+// (Section 3.2):
 //   synthesis  F[j][c] = sum_l T[l][j] X[l][c]      (K = degrees)
 //   analysis   O[l][c] = sum_j T[l][j] Y[j][c]      (K = latitudes)
-// The degrees of each parity of l - m form their own row block (the southern
-// hemisphere follows from Pbar(-mu) = (-1)^{l-m} Pbar(mu), H with the opposite
-// sign), so a 16-row tile is all even or all odd.  T is tabulated once per
-// context in two layouts, each in MFMA operand order (synthesis: M = latitude,
-// K = degree; analysis: M = degree, K = latitude): every (tile, K step) is a
-// contiguous block of 64 lanes x 16 bytes, so a wave reads one operand with one
-// coalesced 1 KB load.  Every value x is stored as x_hi = bf16(x),
-// x_lo = bf16(x - x_hi), interleaved in groups of four (hi[4], lo[4]); a
-// product is accumulated in FP32 as a_hi b_hi + a_hi b_lo + a_lo b_hi with
-// v_mfma_f32_16x16x16_bf16 (relative error about 2^-16 per product, plus FP32
-// accumulation).  The table entries come from the same exponent-tracked FP64
-// recurrence as the FP64 path, seeded per 64-degree segment.
+// The vector fields also need H_lm = (1-mu^2) dPbar_lm/dmu, which the degree
+// recurrence gives as H_l = hA_l Pbar_{l+1} + hB_l Pbar_{l-1}.  No H table is
+// kept: the synthesis moves the two terms onto the coefficients
+// (sum_l H_l X_l = sum_l Pbar_l (hA_{l-1} X_{l-1} + hB_{l+1} X_{l+1})), and the
+// analysis forms sum_j Pbar_l Y_j for every degree up to L+1 and combines the
+// rows l+1 and l-1 afterwards.  The degrees of each parity of l - m form their
+// own row block (the southern hemisphere follows from
+// Pbar(-mu) = (-1)^{l-m} Pbar(mu)), so a 16-row tile is all even or all odd.
+// T is tabulated once per context, degrees m .. L+1, in two layouts, each in
+// MFMA operand order (synthesis: M = latitude, K = degree; analysis: M =
+// degree, K = latitude): every (tile, K step) is a contiguous block of 64 lanes
+// x 16 bytes, so a wave reads one operand with one coalesced 1 KB load.  Every
+// value x is stored as x_hi = bf16(x), x_lo = bf16(x - x_hi), interleaved in
+// groups of four (hi[4], lo[4]); a product is accumulated in FP32 as
+// a_hi b_hi + a_hi b_lo + a_lo b_hi with v_mfma_f32_16x16x16_bf16 (relative
+// error about 2^-16 per product, plus FP32 accumulation).  The table entries
+// come from the same exponent-tracked FP64 recurrence as the FP64 path, seeded
+// per 64-degree segment.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -60,15 +66,36 @@ struct TabArgs {
     const long long* __restrict__ off;   // [L+2] start of order m in every table (shorts)
     const int* __restrict__ kp;          // [2 (L+1)] padded rows of (m, parity)
     unsigned short* __restrict__ p_syn;  // [m][parity][j][rows]  (rows in groups of 4)
-    unsigned short* __restrict__ h_syn;
     unsigned short* __restrict__ p_ana;  // [m][parity][rows][j]  (latitudes in groups of 4)
-    unsigned short* __restrict__ h_ana;
     int L, half, hpad, nseg;
 };
 
+// Pbar_lm(mu_j) (row i = l - m) into both tables, split into bf16 hi and lo.
+__device__ __forceinline__ void put_entry(const TabArgs& A, int m, int i, int j, double v) {
+    const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
+    const int par = i & 1, r = i >> 1;
+    const int K = par ? ko : ke;
+    const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
+    // operand order: each (tile, K step) holds 64 lanes x (hi[4], lo[4]), so a
+    // wave's operand load is one contiguous 1 KB read
+    // synthesis (M = latitude j, K = row r): lane (j % 16) + 16 ((r % 16) / 4), element r % 4
+    const long long ps = blk + ((static_cast<long long>(j >> 4) * (K >> 4) + (r >> 4)) * 64 + (j & 15) +
+                                16 * ((r & 15) >> 2)) * 8 + (r & 3);
+    // analysis (M = row r, K = latitude j): lane (r % 16) + 16 ((j % 16) / 4), element j % 4
+    const long long pa = blk + ((static_cast<long long>(r >> 4) * (A.hpad >> 4) + (j >> 4)) * 64 + (r & 15) +
+                                16 * ((j & 15) >> 2)) * 8 + (j & 3);
+    unsigned short hi, lo;
+    split_bf16(v, hi, lo);
+    A.p_syn[ps] = hi;
+    A.p_syn[ps + 4] = lo;
+    A.p_ana[pa] = hi;
+    A.p_ana[pa + 4] = lo;
+}
+
 // One thread per (degree segment, northern latitude): the FP64 recurrence of
-// the segment, written to the four tables.  Padding rows and latitudes stay
-// zero (the tables are cleared before).
+// the segment, written to both tables; the last segment of an order also
+// writes degree L+1.  Padding rows and latitudes stay zero (the tables are
+// cleared before).
 __global__ __launch_bounds__(256) void leg_table_kernel(TabArgs A) {
     const int gs = blockIdx.x;
     const int j = blockIdx.y * blockDim.x + threadIdx.x;
@@ -79,38 +106,14 @@ __global__ __launch_bounds__(256) void leg_table_kernel(TabArgs A) {
     double pm = A.seed_pm[k], p = A.seed_p[k];
     const int e = A.seed_e[k];
     const double mu = A.mu[j];
-    const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     for (int d = 0; d < n; ++d) {
-        const int i = i0 + d;                       // l - m
-        const LegCoef c = A.rec[base + i];
+        const LegCoef c = A.rec[base + i0 + d];
         const double pn = __builtin_fma(c.A * mu, p, -(c.B * pm));
-        const double h = __builtin_fma(c.hA, pn, c.hB * pm);
-        const double pv = ldexp(p, e), hv = ldexp(h, e);
-        const int par = i & 1, r = i >> 1;
-        const int K = par ? ko : ke;
-        const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-        unsigned short hi, lo;
-        // operand order: each (tile, K step) holds 64 lanes x (hi[4], lo[4]), so a
-        // wave's operand load is one contiguous 1 KB read
-        // synthesis (M = latitude j, K = row r): lane (j % 16) + 16 ((r % 16) / 4), element r % 4
-        const long long ps = blk + ((static_cast<long long>(j >> 4) * (K >> 4) + (r >> 4)) * 64 +
-                                    (j & 15) + 16 * ((r & 15) >> 2)) * 8 + (r & 3);
-        // analysis (M = row r, K = latitude j): lane (r % 16) + 16 ((j % 16) / 4), element j % 4
-        const long long pa = blk + ((static_cast<long long>(r >> 4) * (A.hpad >> 4) + (j >> 4)) * 64 +
-                                    (r & 15) + 16 * ((j & 15) >> 2)) * 8 + (j & 3);
-        split_bf16(pv, hi, lo);
-        A.p_syn[ps] = hi;
-        A.p_syn[ps + 4] = lo;
-        A.p_ana[pa] = hi;
-        A.p_ana[pa + 4] = lo;
-        split_bf16(hv, hi, lo);
-        A.h_syn[ps] = hi;
-        A.h_syn[ps + 4] = lo;
-        A.h_ana[pa] = hi;
-        A.h_ana[pa + 4] = lo;
+        put_entry(A, m, i0 + d, j, ldexp(p, e));
         pm = p;
         p = pn;
     }
+    if (i0 + n == A.L - m + 1) put_entry(A, m, i0 + n, j, ldexp(p, e));
 }
 
 __device__ __forceinline__ void mfma3(f32x4& acc, const uint4& a, const uint4& b) {
@@ -132,12 +135,10 @@ __device__ __forceinline__ uint4 keep_if(bool in, const uint4 v) {
 
 struct MfmaArgs {
     const unsigned short* __restrict__ p_syn;
-    const unsigned short* __restrict__ h_syn;
     const unsigned short* __restrict__ p_ana;
-    const unsigned short* __restrict__ h_ana;
     const long long* __restrict__ off;
     const int* __restrict__ kp;
-    const int* __restrict__ ablk;       // analysis workgroups: (m, first tile) pairs
+    const LegCoef* __restrict__ rec;    // [modes] recurrence and H coefficients
     const double* __restrict__ aon;     // [L+2] a / (l(l+1))
     const double* __restrict__ noa2;    // [L+2] l(l+1) / a^2
     const double* __restrict__ sint;    // [half]
@@ -160,8 +161,11 @@ struct MfmaArgs {
 // ---------------------------------------------------------------- synthesis --
 // Workgroup: order m = blockIdx.x, 4 waves = 4 tiles of 16 northern latitudes
 // (tile 4 blockIdx.y + wave); KIND 0: fields 8 blockIdx.z .. 8 blockIdx.z + 7.
-// LDS: the B operands X[parity][column][row] (rows in groups of four) for the
-// Pbar product and (KIND 1) the H product.
+// LDS: the B operand X[parity][column][row] (rows in groups of four).
+// KIND 1 columns: h, zeta, U, V (real and imaginary parts), with
+//   U_l = -i m delta_l a/N_l + hA_{l-1} zeta_{l-1} a/N_{l-1} + hB_{l+1} zeta_{l+1} a/N_{l+1},
+//   V_l = -i m zeta_l a/N_l - hA_{l-1} delta_{l-1} a/N_{l-1} - hB_{l+1} delta_{l+1} a/N_{l+1}
+// (N_l = l(l+1)), rows up to degree L+1.
 template <int KIND>
 __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short xs[];
@@ -171,7 +175,6 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int rowlen = 2 * A.kmax;                  // shorts per LDS column row
     unsigned short* xp = xs;                        // [2][16][rowlen]
-    unsigned short* xh = xs + 2 * 16 * rowlen;      // KIND 1 only
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
     // stage: one thread per (parity, row) forms the row's 16 columns, zero where
@@ -179,12 +182,11 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
         const int par = rp / A.kmax, r = rp - par * A.kmax;
         const int i = 2 * r + par;                  // l - m
-        double vp[16], vh[16];
+        double vp[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) vp[c] = vh[c] = 0.0;
-        if (i < Lm) {
-            const int l = m + i;
-            if constexpr (KIND == 0) {
+        for (int c = 0; c < 16; ++c) vp[c] = 0.0;
+        if constexpr (KIND == 0) {
+            if (i < Lm) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     if (f0 + q < A.nf) {
@@ -193,26 +195,39 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                         vp[2 * q + 1] = v.y;
                     }
                 }
-            } else {
+            }
+        } else if (i <= Lm) {
+            double2 U = make_double2(0.0, 0.0), V = make_double2(0.0, 0.0);
+            if (i < Lm) {
                 const double2 ch = A.spec[base + i];
                 const double2 cz = A.spec[A.modes + base + i];
                 const double2 cd = A.spec[2 * A.modes + base + i];
-                const double aon = A.aon[l], maon = dm * aon;
-                // Pbar columns: h, zeta, U_P = -i delta m a/N, V_P = -i zeta m a/N
-                // H columns (at the U, V positions): U_H = zeta a/N, V_H = -delta a/N
+                const double maon = dm * A.aon[m + i];
                 vp[0] = ch.x;
                 vp[1] = ch.y;
                 vp[2] = cz.x;
                 vp[3] = cz.y;
-                vp[4] = cd.y * maon;
-                vp[5] = -cd.x * maon;
-                vp[6] = cz.y * maon;
-                vp[7] = -cz.x * maon;
-                vh[4] = cz.x * aon;
-                vh[5] = cz.y * aon;
-                vh[6] = -cd.x * aon;
-                vh[7] = -cd.y * aon;
+                U = make_double2(cd.y * maon, -cd.x * maon);
+                V = make_double2(cz.y * maon, -cz.x * maon);
             }
+            if (i >= 1) {                           // hA_{l-1} H-term of degree l-1
+                const double t = A.rec[base + i - 1].hA * A.aon[m + i - 1];
+                const double2 cz = A.spec[A.modes + base + i - 1];
+                const double2 cd = A.spec[2 * A.modes + base + i - 1];
+                U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
+                V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
+            }
+            if (i + 1 < Lm) {                       // hB_{l+1} H-term of degree l+1
+                const double t = A.rec[base + i + 1].hB * A.aon[m + i + 1];
+                const double2 cz = A.spec[A.modes + base + i + 1];
+                const double2 cd = A.spec[2 * A.modes + base + i + 1];
+                U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
+                V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
+            }
+            vp[4] = U.x;
+            vp[5] = U.y;
+            vp[6] = V.x;
+            vp[7] = V.y;
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -221,11 +236,6 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
             split_bf16(vp[c], hi, lo);
             xp[o + grp_hi(r)] = hi;
             xp[o + grp_lo(r)] = lo;
-            if constexpr (KIND == 1) {
-                split_bf16(vh[c], hi, lo);
-                xh[o + grp_hi(r)] = hi;
-                xh[o + grp_lo(r)] = lo;
-            }
         }
     }
     __syncthreads();
@@ -233,30 +243,26 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     const int tile = blockIdx.y * 4 + threadIdx.x / WAVE;
     if (tile * 16 >= A.hpad) return;
     const int kq = lane >> 4;                       // K quarter of this lane
-    f32x4 accP[2], accH[2];
+    f32x4 acc[2];
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
-        accP[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-        accH[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
         const int K = par ? ko : ke;
         const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
         // operand blocks of this latitude tile: 64 lanes x 8 shorts per K step
         const unsigned short* ap = A.p_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
-        const unsigned short* ah = A.h_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
         const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
-        const unsigned short* bh = xh + (par * 16 + (lane & 15)) * rowlen;
         // table operands in batches of KB steps, all loads of a batch issued
         // before its products (a serial load-multiply chain leaves the
         // small-m workgroups, the longest ones, waiting on memory latency);
         // steps past the end reload the last block and multiply a zero operand
         const int nks = K >> 4;
         for (int k0 = 0; k0 < nks; k0 += KB_SYN) {
-            uint4 a[KB_SYN], a2[KB_SYN];
+            uint4 a[KB_SYN];
 #pragma unroll
             for (int u = 0; u < KB_SYN; ++u) {
                 const int ks = min(k0 + u, nks - 1);
                 a[u] = *reinterpret_cast<const uint4*>(ap + ks * 512);
-                if constexpr (KIND == 1) a2[u] = *reinterpret_cast<const uint4*>(ah + ks * 512);
             }
             __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
 #pragma unroll
@@ -264,11 +270,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                 const bool in = k0 + u < nks;
                 const int g = 4 * min(k0 + u, nks - 1) + kq;   // group of four rows for this lane
                 const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
-                mfma3(accP[par], a[u], b);
-                if constexpr (KIND == 1) {
-                    const uint4 b2 = keep_if(in, *reinterpret_cast<const uint4*>(bh + 8 * g));
-                    mfma3(accH[par], a2[u], b2);
-                }
+                mfma3(acc[par], a[u], b);
             }
         }
     }
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     const int f = KIND == 0 ? f0 + (c >> 1) : (c >> 1);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const float e = accP[0][t] + accH[1][t], o = accP[1][t] + accH[0][t];   // even, odd in mu
+        const float e = acc[0][t], o = acc[1][t];   // even, odd in mu
         const double vn = static_cast<double>(e) + static_cast<double>(o);
         const double vs = static_cast<double>(e) - static_cast<double>(o);
         const double vn_im = __shfl(vn, lane + 1 < WAVE ? lane + 1 : lane);
@@ -294,118 +296,116 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 }
 
 // ----------------------------------------------------------------- analysis --
-// Workgroup: (order m, first tile t0) = ablk[blockIdx.x], 4 waves = row tiles
-// t0 .. t0 + 3 of 16 degrees of one parity (even-parity tiles first), so an
-// order with many degrees spreads over several workgroups.  LDS: the B
-// operands Y[fold][column][latitude] (latitudes in groups of four), fold 0 =
-// F(mu) + F(-mu), fold 1 = F(mu) - F(-mu), weighted.
-// KIND 0: O = sum_j w_j Pbar F (fields 8 blockIdx.z ..).  KIND 1: the
-// non-linear tendency from the Fourier coefficients of hU, hV, zU, zV, KE:
-//   Pbar columns: m hU.y, -m hU.x, m zU.y, -m zU.x, -m zV.y, m zV.x, KE.x, KE.y
-//   H columns:    hV.x, hV.y, zV.x, zV.y, zU.x, zU.y
-// N_h = cols 0-1, N_zeta = cols 2-3, N_delta = cols 4-5 + l(l+1)/a^2 cols 6-7,
-// then out = U0 + c0 N + c1 Nprev and Nsave = N (FP64).
+// Workgroup: order m = blockIdx.x, ANA_WAVES waves taking the row tiles of 16
+// degrees of one parity (even-parity tiles first) in turn.  LDS: the B operand
+// Y[fold][column][latitude] (latitudes in groups of four), fold 0 =
+// F(mu) + F(-mu), fold 1 = F(mu) - F(-mu), weighted; rows of a parity pair
+// with the fold of that parity.  KIND 0: O = sum_j w_j Pbar F (fields
+// 8 blockIdx.z ..), written from the accumulators.  KIND 1: the non-linear
+// tendency from the Fourier coefficients of hU, hV, zU, zV, KE:
+//   columns 0-7 (Pbar terms): m hU.y, -m hU.x, m zU.y, -m zU.x, -m zV.y, m zV.x, KE.x, KE.y
+//   columns 8-13 (H terms):   hV.x, hV.y, zV.x, zV.y, zU.x, zU.y
+// The products Z[l][c] of every degree up to L+1 go to LDS; then output
+// column k (0-5) of degree l is
+//   Z[l][k] + hA_l Z[l+1][8+k] + hB_l Z[l-1][8+k] (+ l(l+1)/a^2 Z[l][k+2], k >= 4)
+// giving N_h (k 0-1), N_zeta (2-3), N_delta (4-5); then out = U0 + c0 N + c1 Nprev
+// and Nsave = N (FP64).
+constexpr int ANA_WAVES = 16;
+
 template <int KIND>
-__global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
+__global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short ys[];
-    const int m = A.ablk[2 * blockIdx.x], t0 = A.ablk[2 * blockIdx.x + 1];
+    const int m = blockIdx.x;
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int rowlen = 2 * A.hpad;
-    unsigned short* yp = ys;                        // [2][16][rowlen]
-    unsigned short* yh = ys + 2 * 16 * rowlen;      // KIND 1 only
+    unsigned short* yp = ys;                                        // [2][16][rowlen]
+    float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
-    // stage: one thread per northern latitude forms its 16 columns for both folds
-    for (int j = threadIdx.x; j < A.hpad; j += blockDim.x) {
-        double sp[16], dp[16], sh[16], dh[16];   // Pbar columns (fold S, D), H columns (fold S, D)
-#pragma unroll
-        for (int c = 0; c < 16; ++c) sp[c] = dp[c] = sh[c] = dh[c] = 0.0;
-        if (j < A.half) {
+    // stage: one thread per (latitude, input field) forms that field's columns
+    // for both folds (zero for padding latitudes and absent fields)
+    constexpr int NFLD = KIND == 0 ? 8 : 5;
+    for (int it = threadIdx.x; it < A.hpad * NFLD; it += blockDim.x) {
+        const int j = it / NFLD, q = it - j * NFLD;
+        double2 S = make_double2(0.0, 0.0), D = make_double2(0.0, 0.0);
+        const int fld = KIND == 0 ? f0 + q : q;
+        if (j < A.half && (KIND == 1 || fld < A.nf)) {
             const double wj = A.w[j];
-            auto fold = [&](int f, double wt, double2& S, double2& D) {
-                const double2* fr = A.four_in + (static_cast<size_t>(f) * (A.L + 1) + m) * A.nlat;
-                const double2 nn = fr[j];
-                const double2 ss = fr[A.nlat - 1 - j];
-                S = make_double2((nn.x + ss.x) * wt, (nn.y + ss.y) * wt);
-                D = make_double2((nn.x - ss.x) * wt, (nn.y - ss.y) * wt);
-            };
-            if constexpr (KIND == 0) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (f0 + q < A.nf) {
-                        double2 S, D;
-                        fold(f0 + q, wj, S, D);
-                        sp[2 * q] = S.x;
-                        sp[2 * q + 1] = S.y;
-                        dp[2 * q] = D.x;
-                        dp[2 * q + 1] = D.y;
-                    }
-                }
-            } else {
-                const double wdiv = wj / (A.a * A.sint[j] * A.sint[j]);
-                double2 hUs, hUd, hVs, hVd, zUs, zUd, zVs, zVd, kes, ked;
-                fold(0, wdiv, hUs, hUd);
-                fold(1, wdiv, hVs, hVd);
-                fold(2, wdiv, zUs, zUd);
-                fold(3, wdiv, zVs, zVd);
-                fold(4, wj, kes, ked);
-                sp[0] = dm * hUs.y;  dp[0] = dm * hUd.y;  sh[0] = hVs.x; dh[0] = hVd.x;
-                sp[1] = -dm * hUs.x; dp[1] = -dm * hUd.x; sh[1] = hVs.y; dh[1] = hVd.y;
-                sp[2] = dm * zUs.y;  dp[2] = dm * zUd.y;  sh[2] = zVs.x; dh[2] = zVd.x;
-                sp[3] = -dm * zUs.x; dp[3] = -dm * zUd.x; sh[3] = zVs.y; dh[3] = zVd.y;
-                sp[4] = -dm * zVs.y; dp[4] = -dm * zVd.y; sh[4] = zUs.x; dh[4] = zUd.x;
-                sp[5] = dm * zVs.x;  dp[5] = dm * zVd.x;  sh[5] = zUs.y; dh[5] = zUd.y;
-                sp[6] = kes.x;       dp[6] = ked.x;
-                sp[7] = kes.y;       dp[7] = ked.y;
+            const double wt = (KIND == 0 || q == 4) ? wj : wj / (A.a * A.sint[j] * A.sint[j]);
+            const double2* fr = A.four_in + (static_cast<size_t>(fld) * (A.L + 1) + m) * A.nlat;
+            const double2 nn = fr[j];
+            const double2 ss = fr[A.nlat - 1 - j];
+            S = make_double2((nn.x + ss.x) * wt, (nn.y + ss.y) * wt);
+            D = make_double2((nn.x - ss.x) * wt, (nn.y - ss.y) * wt);
+        }
+        // (column, value) pairs of this field, fold S then D
+        int col[4];
+        double vs[4], vd[4];
+        int nc = 2;
+        if constexpr (KIND == 0) {
+            col[0] = 2 * q; vs[0] = S.x; vd[0] = D.x;
+            col[1] = 2 * q + 1; vs[1] = S.y; vd[1] = D.y;
+        } else {
+            if (q == 0) {          // hU: Pbar columns 0, 1
+                col[0] = 0; vs[0] = dm * S.y; vd[0] = dm * D.y;
+                col[1] = 1; vs[1] = -dm * S.x; vd[1] = -dm * D.x;
+            } else if (q == 1) {   // hV: H columns 8, 9
+                col[0] = 8; vs[0] = S.x; vd[0] = D.x;
+                col[1] = 9; vs[1] = S.y; vd[1] = D.y;
+            } else if (q == 2) {   // zU: Pbar columns 2, 3; H columns 12, 13
+                col[0] = 2; vs[0] = dm * S.y; vd[0] = dm * D.y;
+                col[1] = 3; vs[1] = -dm * S.x; vd[1] = -dm * D.x;
+                col[2] = 12; vs[2] = S.x; vd[2] = D.x;
+                col[3] = 13; vs[3] = S.y; vd[3] = D.y;
+                nc = 4;
+            } else if (q == 3) {   // zV: Pbar columns 4, 5; H columns 10, 11
+                col[0] = 4; vs[0] = -dm * S.y; vd[0] = -dm * D.y;
+                col[1] = 5; vs[1] = dm * S.x; vd[1] = dm * D.x;
+                col[2] = 10; vs[2] = S.x; vd[2] = D.x;
+                col[3] = 11; vs[3] = S.y; vd[3] = D.y;
+                nc = 4;
+            } else {               // KE: Pbar columns 6, 7; columns 14, 15 stay zero
+                col[0] = 6; vs[0] = S.x; vd[0] = D.x;
+                col[1] = 7; vs[1] = S.y; vd[1] = D.y;
+                col[2] = 14; vs[2] = 0.0; vd[2] = 0.0;
+                col[3] = 15; vs[3] = 0.0; vd[3] = 0.0;
+                nc = 4;
             }
         }
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
+        for (int u = 0; u < nc; ++u) {
             unsigned short hi, lo;
-            const int o0 = c * rowlen, o1 = (16 + c) * rowlen;
-            split_bf16(sp[c], hi, lo);
+            const int o0 = col[u] * rowlen, o1 = (16 + col[u]) * rowlen;
+            split_bf16(vs[u], hi, lo);
             yp[o0 + grp_hi(j)] = hi;
             yp[o0 + grp_lo(j)] = lo;
-            split_bf16(dp[c], hi, lo);
+            split_bf16(vd[u], hi, lo);
             yp[o1 + grp_hi(j)] = hi;
             yp[o1 + grp_lo(j)] = lo;
-            if constexpr (KIND == 1) {
-                split_bf16(sh[c], hi, lo);
-                yh[o0 + grp_hi(j)] = hi;
-                yh[o0 + grp_lo(j)] = lo;
-                split_bf16(dh[c], hi, lo);
-                yh[o1 + grp_hi(j)] = hi;
-                yh[o1 + grp_lo(j)] = lo;
-            }
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
     const int te = ke / 16, to = ko / 16;
-    const int tile = t0 + static_cast<int>(threadIdx.x) / WAVE;
-    if (tile < te + to) {
+    const int kq = lane >> 4;
+    const int c = lane & 15;
+    for (int tile = threadIdx.x / WAVE; tile < te + to; tile += ANA_WAVES) {
         const int par = tile < te ? 0 : 1;
         const int r0 = (par ? tile - te : tile) * 16;
         const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-        const int kq = lane >> 4;
         // operand blocks of this row tile: 64 lanes x 8 shorts per K step
         const unsigned short* ap = A.p_ana + blk + (static_cast<long long>(r0 >> 4) * (A.hpad >> 4) * 64 + lane) * 8;
-        const unsigned short* ah = A.h_ana + blk + (static_cast<long long>(r0 >> 4) * (A.hpad >> 4) * 64 + lane) * 8;
-        // Pbar of parity par pairs with fold par; H (opposite parity) with fold 1 - par
-        const unsigned short* bp = yp + (par * 16 + (lane & 15)) * rowlen;
-        const unsigned short* bh = yh + ((1 - par) * 16 + (lane & 15)) * rowlen;
-        f32x4 accP = {0.f, 0.f, 0.f, 0.f}, accH = {0.f, 0.f, 0.f, 0.f};
+        const unsigned short* bp = yp + (par * 16 + c) * rowlen;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         // table operands in batches of KB steps (loads first, then products)
         const int nks = A.hpad >> 4;
         for (int k0 = 0; k0 < nks; k0 += KB_ANA) {
-            uint4 a[KB_ANA], a2[KB_ANA];
+            uint4 a[KB_ANA];
 #pragma unroll
             for (int u = 0; u < KB_ANA; ++u) {
                 const int js = min(k0 + u, nks - 1);
                 a[u] = *reinterpret_cast<const uint4*>(ap + js * 512);
-                if constexpr (KIND == 1) a2[u] = *reinterpret_cast<const uint4*>(ah + js * 512);
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -413,42 +413,44 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
                 const bool in = k0 + u < nks;
                 const int g = 4 * min(k0 + u, nks - 1) + kq;
                 const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
-                mfma3(accP, a[u], b);
-                if constexpr (KIND == 1) {
-                    const uint4 b2 = keep_if(in, *reinterpret_cast<const uint4*>(bh + 8 * g));
-                    mfma3(accH, a2[u], b2);
-                }
+                mfma3(acc, a[u], b);
             }
-        }
-        const int c = lane & 15;
-        float ke_t[4];
-        if constexpr (KIND == 1) {
-            // the KE columns 6, 7 are added to columns 4, 5 (same rows, two lanes up)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) ke_t[t] = __shfl(accP[t], lane + 2 < WAVE ? lane + 2 : lane);
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int r = r0 + 4 * kq + t;
             const int i = 2 * r + par;                  // l - m
-            if (i >= Lm) continue;
-            const size_t idx = static_cast<size_t>(base) + i;
             if constexpr (KIND == 0) {
                 const int f = f0 + (c >> 1);
-                if (f >= A.nf) continue;
-                reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + idx)[c & 1] =
-                    static_cast<double>(accP[t]);
+                if (i >= Lm || f >= A.nf) continue;
+                reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + base + i)[c & 1] =
+                    static_cast<double>(acc[t]);
             } else {
-                if (c >= 6) continue;
-                double v = static_cast<double>(accP[t]) + static_cast<double>(accH[t]);
-                if (c >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(ke_t[t]), v);
-                const int f = c >> 1, part = c & 1;
-                const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-                double o = __builtin_fma(A.c0, v, A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0);
-                if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
-                if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
-                reinterpret_cast<double*>(A.out)[e2] = o;
+                zs[(par * A.kmax + r) * 16 + c] = acc[t];
             }
+        }
+    }
+    if constexpr (KIND == 1) {
+        __syncthreads();
+        // one thread per (degree, output column)
+        for (int it = threadIdx.x; it < Lm * 6; it += blockDim.x) {
+            const int i = it / 6, k = it - i * 6;
+            const float* zrow = zs + ((i & 1) * A.kmax + (i >> 1)) * 16;
+            const float* zup = zs + (((i + 1) & 1) * A.kmax + ((i + 1) >> 1)) * 16;   // degree l+1 (<= L+1)
+            const LegCoef rc = A.rec[base + i];
+            double v = static_cast<double>(zrow[k]);
+            v = __builtin_fma(rc.hA, static_cast<double>(zup[8 + k]), v);
+            if (i >= 1) {
+                const float* zdn = zs + (((i - 1) & 1) * A.kmax + ((i - 1) >> 1)) * 16;
+                v = __builtin_fma(rc.hB, static_cast<double>(zdn[8 + k]), v);
+            }
+            if (k >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(zrow[k + 2]), v);
+            const int f = k >> 1, part = k & 1;
+            const size_t e2 = (static_cast<size_t>(f) * A.modes + base + i) * 2 + part;
+            double o = __builtin_fma(A.c0, v, A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0);
+            if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
+            if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
+            reinterpret_cast<double*>(A.out)[e2] = o;
         }
     }
 }
@@ -456,12 +458,10 @@ __global__ __launch_bounds__(256) void leg_anal_mfma_kernel(MfmaArgs A) {
 MfmaArgs mfma_args(const swe_ctx* ctx) {
     MfmaArgs A{};
     A.p_syn = ctx->d_tab_psyn;
-    A.h_syn = ctx->d_tab_hsyn;
     A.p_ana = ctx->d_tab_pana;
-    A.h_ana = ctx->d_tab_hana;
     A.off = ctx->d_tab_off;
     A.kp = ctx->d_tab_kp;
-    A.ablk = ctx->d_tab_ablk;
+    A.rec = ctx->d_rec;
     A.aon = ctx->d_aon;
     A.noa2 = ctx->d_noa2;
     A.sint = ctx->d_sint;
@@ -501,16 +501,13 @@ int build_split_tables(swe_ctx* ctx, hipStream_t stream) {
     T.off = ctx->d_tab_off;
     T.kp = ctx->d_tab_kp;
     T.p_syn = ctx->d_tab_psyn;
-    T.h_syn = ctx->d_tab_hsyn;
     T.p_ana = ctx->d_tab_pana;
-    T.h_ana = ctx->d_tab_hana;
     T.L = ctx->L;
     T.half = ctx->nlat / 2;
     T.hpad = ctx->tab_hpad;
     T.nseg = ctx->nseg;
     const size_t bytes = sizeof(unsigned short) * static_cast<size_t>(ctx->tab_len);
-    for (unsigned short* p : {ctx->d_tab_psyn, ctx->d_tab_hsyn, ctx->d_tab_pana, ctx->d_tab_hana})
-        REXI_HIP(hipMemsetAsync(p, 0, bytes, stream));
+    for (unsigned short* p : {ctx->d_tab_psyn, ctx->d_tab_pana}) REXI_HIP(hipMemsetAsync(p, 0, bytes, stream));
     hipLaunchKernelGGL(leg_table_kernel, dim3(ctx->nseg, (T.half + 255) / 256), dim3(256), 0, stream, T);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
@@ -522,7 +519,7 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     A.spec = reinterpret_cast<const double2*>(spec);
     A.four_out = reinterpret_cast<double2*>(four);
     A.nf = nf;
-    const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.kmax) * (kind == 0 ? 1 : 2);
+    const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.kmax);
     const int tiles = A.hpad / 16;
     const dim3 grid(ctx->L + 1, (tiles + 3) / 4, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
@@ -552,17 +549,18 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     A.c0 = c0;
     A.c1 = c1;
     A.nf = nf;
-    const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.hpad) * (kind == 0 ? 1 : 2);
-    const dim3 grid(ctx->tab_nablk, 1, kind == 0 ? (nf + 7) / 8 : 1);
+    size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.hpad);
+    if (kind == 1) lds += sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax);
+    const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
     const void* fn = kind == 0 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0>)
                                : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1>);
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
     if (kind == 0)
-        hipLaunchKernelGGL(leg_anal_mfma_kernel<0>, grid, dim3(256), lds, stream, A);
+        hipLaunchKernelGGL(leg_anal_mfma_kernel<0>, grid, dim3(ANA_WAVES * WAVE), lds, stream, A);
     else
-        hipLaunchKernelGGL(leg_anal_mfma_kernel<1>, grid, dim3(256), lds, stream, A);
+        hipLaunchKernelGGL(leg_anal_mfma_kernel<1>, grid, dim3(ANA_WAVES * WAVE), lds, stream, A);
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
     return REXI_OK;
