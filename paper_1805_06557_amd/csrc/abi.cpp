@@ -182,9 +182,6 @@ int setup_sht(swe_ctx* ctx) {
         ctx->tab_len = static_cast<size_t>(off[ctx->L + 1]);
         if ((rc = upload(&ctx->d_tab_kp, kp.data(), kp.size())) != REXI_OK) return rc;
         if ((rc = upload(&ctx->d_tab_off, off.data(), off.size())) != REXI_OK) return rc;
-        std::vector<int> segid(ctx->L + 2);
-        for (int m = 0; m <= ctx->L + 1; ++m) segid[m] = m;
-        if ((rc = upload(&ctx->d_tab_segid, segid.data(), segid.size())) != REXI_OK) return rc;
         for (unsigned short** t : {&ctx->d_tab_psyn, &ctx->d_tab_pana})
             if (hipMalloc(reinterpret_cast<void**>(t), sizeof(unsigned short) * ctx->tab_len) != hipSuccess)
                 return fail(REXI_ENOMEM, "swe_create: cannot allocate the split-precision Legendre tables");
@@ -198,7 +195,7 @@ int setup_sht(swe_ctx* ctx) {
     ctx->npass = static_cast<int>(radix.size());
     if ((rc = upload(&ctx->d_radix, radix.data(), radix.size())) != REXI_OK) return rc;
     std::vector<double> tw, twr;
-    build_twiddles(M, tw);
+    if ((rc = ring_twiddles(M, radix, tw)) != REXI_OK) return rc;
     build_twiddles(ctx->nlon, twr);
     twr.resize(2 * static_cast<size_t>(M));
     if ((rc = upload(&ctx->d_tw, tw.data(), tw.size())) != REXI_OK) return rc;
@@ -241,7 +238,7 @@ int to_fourier(swe_ctx* ctx, int kind, const double* spec, int nf, hipStream_t s
 // grid `gout`; mode 2: non-linear products into ctx->d_fout).
 int ring_from_part(swe_ctx* ctx, int mode, double* gout, int nf, hipStream_t stream, double two_omega = 0.0) {
     const bool split = split_legendre(ctx);
-    return launch_ring(ctx, mode, ctx->d_part, split ? ctx->d_tab_segid : ctx->d_segbase, split ? ctx->L + 1 : ctx->nseg,
+    return launch_ring(ctx, mode, ctx->d_part, split ? nullptr : ctx->d_segbase, split ? ctx->L + 1 : ctx->nseg,
                        ctx->d_fout, nullptr, gout, nf, stream, two_omega);
 }
 
@@ -416,7 +413,7 @@ int swe_destroy(swe_ctx* ctx) {
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
                         ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
-                        ctx->d_tab_pana, ctx->d_tab_off, ctx->d_tab_kp, ctx->d_tab_segid};
+                        ctx->d_tab_pana, ctx->d_tab_off, ctx->d_tab_kp};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
     for (int k = 0; k < REXI_KERNEL_COUNT; ++k) {

@@ -181,7 +181,7 @@ struct swe_ctx {
     int* d_seed_e = nullptr;          // [nseg][nlat/2]
     double* d_part = nullptr;         // synthesis partial sums [nf][nseg][nlat] complex
     size_t part_cap = 0;              // fields the partial buffer can hold
-    double* d_tw = nullptr;           // [nlon/2] complex
+    double* d_tw = nullptr;           // [nlon/2] complex, pass twiddles of the longitude FFT
     double* d_twr = nullptr;          // [nlon/2] complex
     int* d_radix = nullptr;
     int npass = 0;
@@ -197,7 +197,6 @@ struct swe_ctx {
     unsigned short* d_tab_psyn = nullptr;
     unsigned short* d_tab_pana = nullptr;
     long long* d_tab_off = nullptr;   // [L+2]
-    int* d_tab_segid = nullptr;       // [L+2] m: one Fourier row per order
     int* d_tab_kp = nullptr;          // [2 (L+1)]
     int tab_hpad = 0, tab_kmax = 0;
     size_t tab_len = 0;               // shorts per table
@@ -235,7 +234,7 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
                          hipStream_t stream);
 // Split-precision (bf16 hi/lo, matrix-core) Legendre stage: tables and the two
 // directions.  The synthesis writes the Fourier coefficients [nf][L+1][nlat]:
-// one partial row per order, read by the ring kernel with segbase[m] = m.
+// one partial row per order (the ring kernel reads them with segbase = nullptr).
 int build_split_tables(swe_ctx* ctx, hipStream_t stream);
 int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, double* four, int nf,
                                 hipStream_t stream);
@@ -250,6 +249,8 @@ int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
 int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
 // Radix sequence of the longitude FFT of M = nlon/2 complex points.
 int ring_plan(int M, std::vector<int>& radix);
+// Twiddles of every pass of that plan, pass-major ([M] complex).
+int ring_twiddles(int M, const std::vector<int>& radix, std::vector<double>& tw);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
 int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
                 const double* gin, double* gout, int nf, hipStream_t stream, double two_omega = 0.0);

@@ -427,7 +427,7 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
 
 // ============================================================ ring FFTs ==
 struct RingArgs {
-    const double* __restrict__ tw;     // [M] complex e^{-2 pi i k / M}
+    const double* __restrict__ tw;     // [M] complex: the twiddles of every FFT pass (ring_twiddles)
     const double* __restrict__ twr;    // [M] complex e^{-2 pi i k / nlon}
     const double* __restrict__ sint;   // [half]
     const double* __restrict__ mu;     // [half] sin(latitude), northern
@@ -437,7 +437,7 @@ struct RingArgs {
     // coefficient F_m of a latitude is the sum over segments segbase[m] ..
     // segbase[m + 1] - 1
     const double2* __restrict__ part;
-    const int* __restrict__ segbase;   // [L+2]
+    const int* __restrict__ segbase;   // [L+2]; nullptr: one segment per order (segbase[m] = m)
     int nseg;
     double2* __restrict__ fout;        // Fourier coefficients [nf_out][L+1][nlat] (order-major)
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
@@ -553,13 +553,14 @@ __host__ __device__ constexpr int ring_radix(int rem) {
 // One Stockham pass of radix R over the M complex values of the wave's LDS
 // array x (padded), in place: every lane first reads and transforms all its
 // butterflies, then writes them.  Ns = product of the radices already applied;
-// tw: e^{-2 pi i k / M} (padded).  MC, NSC: compile-time M and Ns (0: runtime).
+// the pass's twiddles e^{-2 pi i t k / (Ns R)} are tw[Ns - 1 + (t - 1) Ns + k]
+// (consecutive k, so consecutive lanes read consecutive entries).  MC, NSC:
+// compile-time M and Ns (0: runtime).
 template <int R, bool INV, int MC, int NSC>
 __device__ __forceinline__ void wave_pass(double2* x, int Mr, int Nsr, const double2* tw, int lane) {
     const int M = MC > 0 ? MC : Mr;
     const int Ns = NSC > 0 ? NSC : Nsr;
     const int nb = M / R;
-    const int twstep = M / (Ns * R);
     constexpr int BPL = ((MC > 0 ? MC : RING_MMAX_RT) / R + WAVE - 1) / WAVE;   // butterflies per lane
     lane = opaque_lane(lane);
     double2 v[BPL][R];
@@ -572,7 +573,7 @@ __device__ __forceinline__ void wave_pass(double2* x, int Mr, int Nsr, const dou
             for (int t = 0; t < R; ++t) {
                 double2 val = x[pad8(jb + t * nb)];
                 if (t > 0 && (NSC != 1)) {
-                    double2 w = tw[pad8(t * k * twstep)];
+                    double2 w = tw[Ns - 1 + (t - 1) * Ns + k];
                     if (INV) w.y = -w.y;
                     val = cmul(val, w);
                 }
@@ -643,8 +644,8 @@ __device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j
         for (int i = 0; i < MPL; ++i) {
             const int m = lane + i * WAVE;
             const bool ok = m <= A.L;
-            g0[i] = ok ? A.segbase[m] : 0;
-            g1[i] = ok ? A.segbase[m + 1] : 0;
+            g0[i] = !ok ? 0 : (A.segbase ? A.segbase[m] : m);
+            g1[i] = !ok ? 0 : (A.segbase ? A.segbase[m + 1] : m + 1);
         }
 #pragma unroll
         for (int i = 0; i < MPL; ++i)
@@ -658,8 +659,8 @@ __device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j
     } else {
         for (int m = lane; m <= A.L; m += WAVE) {
             double2 acc = make_double2(0.0, 0.0);
-            const int g1 = A.segbase[m + 1];
-            for (int g = A.segbase[m]; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
+            const int g1 = A.segbase ? A.segbase[m + 1] : m + 1;
+            for (int g = A.segbase ? A.segbase[m] : m; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
             x[pad8(m)] = acc;
         }
     }
@@ -688,7 +689,7 @@ __device__ __forceinline__ void wave_pack_inverse(const RingArgs& A, double2* x,
             const double2 xrc = conj2(xr);
             const double2 sm = cadd(xk, xrc);
             const double2 df = csub(xk, xrc);
-            const double2 tk = twr[pad8(k)];
+            const double2 tk = twr[k];
             const double2 t = cmul(make_double2(tk.x, -tk.y), df);   // e^{+2 pi i k / nlon} d
             z[i] = make_double2(sm.x - t.y, sm.y + t.x);             // s + i t
         }
@@ -716,7 +717,7 @@ __device__ __forceinline__ void wave_store_forward(const RingArgs& A, const doub
         const double2 zr = conj2(x[pad8(k == 0 ? 0 : M - k)]);
         const double2 sm = cadd(zk, zr);
         const double2 df = csub(zk, zr);
-        const double2 t = cmul(twr[pad8(k)], df);
+        const double2 t = cmul(twr[k], df);
         const double2 X = make_double2(0.5 * (sm.x + t.y), 0.5 * (sm.y - t.x));   // s/2 - i t/2
         frow[static_cast<size_t>(k) * A.nlat] = scale2(X, inv);
     }
@@ -737,8 +738,8 @@ __device__ __forceinline__ int ring_of_block(int b, int nlat) {
 // MODE 2: non-linear products: inverse of h, zeta, U, V (waves 0-3); pointwise
 //         hU, hV, zU, zV, KE = (U^2 + V^2) / (2 cos^2 phi) (whole workgroup);
 //         forward of those five (waves 0-4).
-// LDS: RING_WAVES padded arrays of M complex values, then the twiddles
-// e^{-2 pi i k / M} and e^{-2 pi i k / nlon} (padded).
+// LDS: RING_WAVES padded arrays of M complex values, then the pass twiddles
+// and e^{-2 pi i k / nlon}, k < M.
 template <int MODE, int MC>
 __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
     extern __shared__ __align__(16) double2 lds[];
@@ -748,10 +749,10 @@ __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const size_t fstride = static_cast<size_t>(A.L + 1) * A.nlat;   // one field of [L+1][nlat]
     double2* tw = lds + RING_WAVES * PL;
-    double2* twr = tw + PL;
+    double2* twr = tw + M;
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
-        tw[pad8(k)] = make_double2(A.tw[2 * k], A.tw[2 * k + 1]);
-        twr[pad8(k)] = make_double2(A.twr[2 * k], A.twr[2 * k + 1]);
+        tw[k] = make_double2(A.tw[2 * k], A.tw[2 * k + 1]);
+        twr[k] = make_double2(A.twr[2 * k], A.twr[2 * k + 1]);
     }
     double2* x = lds + wv * PL;
     if constexpr (MODE == 0) {
@@ -868,7 +869,7 @@ static RingArgs ring_args(const swe_ctx* ctx) {
 
 static int ring_lds_bytes(const swe_ctx* ctx, int /*mode*/) {
     const int M = ctx->nlon / 2;
-    return (RING_WAVES + 2) * padded_len(M) * static_cast<int>(sizeof(double2));
+    return (RING_WAVES * padded_len(M) + 2 * M) * static_cast<int>(sizeof(double2));
 }
 
 template <int MODE>
@@ -888,6 +889,27 @@ static int allow_lds(const void* fn, size_t bytes, const char* what) {
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(REXI_ENOTSUP, std::string("swe_create: ") + what + " of this grid needs more LDS than available");
+    }
+    return REXI_OK;
+}
+
+int ring_twiddles(int M, const std::vector<int>& radix, std::vector<double>& tw) {
+    // e^{-2 pi i t k / (Ns R)} = e^{-2 pi i (t k M / (Ns R)) / M}, from the
+    // length-M table, at Ns - 1 + (t - 1) Ns + k for every pass (R, Ns)
+    std::vector<double> full;
+    build_twiddles(M, full);
+    tw.assign(2 * static_cast<size_t>(M), 0.0);
+    int Ns = 1;
+    for (int R : radix) {
+        const int twstep = M / (Ns * R);
+        for (int t = 1; t < R; ++t)
+            for (int k = 0; k < Ns; ++k) {
+                const size_t dst = static_cast<size_t>(Ns - 1 + (t - 1) * Ns + k);
+                const size_t src = static_cast<size_t>((t * k * twstep) % M);
+                tw[2 * dst] = full[2 * src];
+                tw[2 * dst + 1] = full[2 * src + 1];
+            }
+        Ns *= R;
     }
     return REXI_OK;
 }
