@@ -128,6 +128,11 @@ __device__ __forceinline__ void mfma3(f32x4& acc, const uint4& a, const uint4& b
     acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
 }
 
+// Shorts per LDS row of a B operand holding n K-values (hi, lo): 4n bytes
+// plus 16, so that the rows the 16 column lanes of a quarter-wave read start
+// an odd number of 16-byte bank groups apart (no bank conflicts).
+__host__ __device__ constexpr int lds_row(int n) { return 2 * n + 8; }
+
 // v if in, else zero (component selects, so no load is made conditional)
 __device__ __forceinline__ uint4 keep_if(bool in, const uint4 v) {
     return make_uint4(in ? v.x : 0u, in ? v.y : 0u, in ? v.z : 0u, in ? v.w : 0u);
@@ -173,7 +178,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
-    const int rowlen = 2 * A.kmax;                  // shorts per LDS column row
+    const int rowlen = lds_row(A.kmax);             // shorts per LDS column row
     unsigned short* xp = xs;                        // [2][16][rowlen]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
-    const int rowlen = 2 * A.hpad;
+    const int rowlen = lds_row(A.hpad);
     unsigned short* yp = ys;                                        // [2][16][rowlen]
     float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
@@ -519,7 +524,7 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     A.spec = reinterpret_cast<const double2*>(spec);
     A.four_out = reinterpret_cast<double2*>(four);
     A.nf = nf;
-    const size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.kmax);
+    const size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.kmax));
     const int tiles = A.hpad / 16;
     const dim3 grid(ctx->L + 1, (tiles + 3) / 4, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
@@ -549,7 +554,7 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     A.c0 = c0;
     A.c1 = c1;
     A.nf = nf;
-    size_t lds = sizeof(unsigned short) * 2 * 16 * 2 * static_cast<size_t>(A.hpad);
+    size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.hpad));
     if (kind == 1) lds += sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax);
     const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
     int rc;
