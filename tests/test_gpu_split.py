@@ -121,6 +121,42 @@ def test_split_matches_fp64_path_at_t255():
     assert max(e) <= 24 * u_split(L, nlat), e
 
 
+def test_split_t511_round_trip_and_step():
+    """T511 on 1536 x 768 (the analysis workgroup then needs more than 64 KB of
+    LDS): synthesis then analysis of band-limited fields returns them to
+    16 u_split(K) of each field's largest coefficient (Gauss quadrature makes
+    the exact round trip the identity), and one non-linear step matches the
+    FP64 path (pinned to the oracle) to the bar of the T255 case."""
+    api = _api()
+    L, nlat, nlon = 511, 768, 1536
+    rng = np.random.default_rng(511)
+    nf = 2
+    spec = np.stack([random_field(L, rng, 1.0) for _ in range(nf)])
+    ctx = api.SWE(L, nlat, nlon, prec=api.PREC_BF16_SPLIT)
+    ds = torch.from_numpy(spec).cuda()
+    dg = torch.empty((nf, nlat, nlon), dtype=torch.float64, device="cuda")
+    ctx.sh_synthesis(ds, dg, nf)
+    back = torch.empty_like(ds)
+    ctx.sh_analysis(dg, back, nf)
+    e = _rel(back.cpu().numpy(), spec)
+    print("T511 split round trip", e)
+    assert max(e) <= 16 * u_split(L, nlat), e
+    U0 = jet_state(L, 4)
+    d0 = torch.from_numpy(U0).cuda()
+    outs = []
+    for prec in (0, api.PREC_BF16_SPLIT):
+        c = api.SWE(L, nlat, nlon, prec=prec)
+        d1 = torch.empty_like(d0)
+        c.nonlinear_step(900.0, d0, d1)
+        outs.append(d1.cpu().numpy())
+        c.close()
+    g = Grid(L, nlat, nlon, Params())
+    e = _scaled(outs[1] - U0, outs[0] - U0, 900.0 * _term_scales(g, U0))
+    print("T511 heun increment vs FP64 path", e, "relative to the increment", _rel(outs[1] - U0, outs[0] - U0))
+    assert max(e) <= 24 * u_split(L, nlat), e
+    ctx.close()
+
+
 def test_fp16_split_is_not_built():
     api = _api()
     with pytest.raises(api.RexiError) as ei:
