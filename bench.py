@@ -498,7 +498,9 @@ def main():
                         + (f" on {w.nlon}x{w.nlat} Gauss grid" if full else "")
                         + f", dt={w.dt:g} s, N={w.N} poles (p0={w.p0:g}, y={w.y:.4g}), "
                         + ("FP32 banded solves + FP64 beta sum" if fp32 else "FP64 solves")
-                        + (", FP64 transforms" if full else ""),
+                        + ((", split-BF16 Legendre + FP64 FFTs" if w.prec & api.PREC_BF16_SPLIT else
+                            ", split-FP16 Legendre + FP64 FFTs" if w.prec & api.PREC_FP16_SPLIT else
+                            ", FP64 transforms") if full else ""),
             "L": w.L, "N": w.N, "dt": w.dt, "stage": stage,
         },
         "sim_time_per_wall": w.dt / (ms_per_step * 1e-3),
@@ -523,12 +525,12 @@ def main():
     }
     if full and w.prec:
         out["step_error_vs_fp64_path"] = step_error_vs_fp64(ctx, w, alpha, beta)
-    if full and (w.prec & api.PREC_BF16_SPLIT):
+    if full and (w.prec & (api.PREC_BF16_SPLIT | api.PREC_FP16_SPLIT)):
         syn = stage_ms["legendre_synth_kernel"]["ms_per_launch"]
         ana = stage_ms["legendre_anal_kernel"]["ms_per_launch"]
         fl = split_mfma_flops(w.L, w.nlat)
         out["legendre_mfma"] = {
-            "precision": "bf16 hi/lo split, 3 products, FP32 accumulation",
+            "precision": ("bf16" if w.prec & api.PREC_BF16_SPLIT else "fp16") + " hi/lo split, 3 products, FP32 accumulation",
             "mfma_flops_per_launch": fl,
             "synth_TFLOP_s": fl / (syn * 1e-3) / 1e12, "anal_TFLOP_s": fl / (ana * 1e-3) / 1e12,
             "peak_TFLOP_s": PEAK_BF16_MFMA,

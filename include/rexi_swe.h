@@ -51,9 +51,16 @@ enum {
 enum { REXI_FN_EXP = 0, REXI_FN_PSI1 = 1, REXI_FN_PSI2 = 2 };
 
 /* Precision modes of a context (bit flags; 0 = everything in FP64).
- * REXI_PREC_FP32_SOLVE: the banded REXI solves run in complex FP32; diagonals
- *   and right-hand sides are formed in FP64 and rounded once, the
- *   beta-weighted sum accumulates in FP64. */
+ * REXI_PREC_FP32_SOLVE: the banded REXI solves run in complex FP32; the row
+ *   data are formed in FP64 and rounded once, the beta-weighted sum
+ *   accumulates in FP64.
+ * REXI_PREC_BF16_SPLIT, REXI_PREC_FP16_SPLIT (exclusive): the Legendre
+ *   contractions of the transforms (Section 3.2) run on the matrix cores with
+ *   every operand split into two 16-bit values (hi + lo) and three products
+ *   accumulated in FP32: relative error per product about 2^-16 (BF16) or
+ *   2^-21 (FP16; data columns scaled by exact powers of two into FP16's
+ *   range), plus FP32 accumulation over the latitudes or degrees.  FFTs,
+ *   products and the time stepping stay FP64. */
 enum {
     REXI_PREC_FP64 = 0,
     REXI_PREC_FP32_SOLVE = 1,

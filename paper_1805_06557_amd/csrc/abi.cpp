@@ -163,7 +163,7 @@ int setup_sht(swe_ctx* ctx) {
     if ((rc = upload(&ctx->d_seed_pm, sg.seed_pm.data(), sg.seed_pm.size())) != REXI_OK) return rc;
     if ((rc = upload(&ctx->d_seed_p, sg.seed_p.data(), sg.seed_p.size())) != REXI_OK) return rc;
     if ((rc = upload(&ctx->d_seed_e, sg.seed_e.data(), sg.seed_e.size())) != REXI_OK) return rc;
-    if (ctx->prec & REXI_PREC_BF16_SPLIT) {
+    if (ctx->prec & (REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT)) {
         // row blocks per (m, parity of l - m) for degrees m .. L+1, padded to 16;
         // latitudes padded to 16
         const int half = ctx->nlat / 2;
@@ -225,7 +225,7 @@ int reserve_fourier(swe_ctx* ctx, int nf) {
 }
 
 // One Heun step dU/dt = N(U) over tau on `stream`.
-bool split_legendre(const swe_ctx* ctx) { return (ctx->prec & REXI_PREC_BF16_SPLIT) != 0; }
+bool split_legendre(const swe_ctx* ctx) { return (ctx->prec & (REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT)) != 0; }
 
 // Spectral fields -> synthesis partials of the Fourier coefficients in
 // ctx->d_part (per degree segment; one segment per order in the split path).
@@ -348,8 +348,6 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
         return fail(REXI_EINVAL, "swe_create: unknown precision flags");
     if ((prec & REXI_PREC_BF16_SPLIT) && (prec & REXI_PREC_FP16_SPLIT))
         return fail(REXI_EINVAL, "swe_create: BF16 and FP16 Legendre modes are exclusive");
-    if (prec & REXI_PREC_FP16_SPLIT)
-        return fail(REXI_ENOTSUP, "swe_create: the FP16 split Legendre stage is not built (BF16 split is)");
 
     swe_ctx* ctx = new (std::nothrow) swe_ctx;
     if (!ctx) return fail(REXI_ENOMEM, "swe_create: out of host memory");

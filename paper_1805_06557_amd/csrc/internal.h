@@ -189,8 +189,8 @@ struct swe_ctx {
     size_t four_cap = 0;              // fields each Fourier buffer can hold
     double* d_ustar = nullptr;        // Runge-Kutta stage [3][modes]
     double* d_n0 = nullptr;           // first tendency [3][modes]
-    // split-precision Legendre table (REXI_PREC_BF16_SPLIT): Pbar for degrees
-    // m .. L+1 as bf16 (hi, lo) pairs in a latitude-major (synthesis) and a
+    // split-precision Legendre table (REXI_PREC_BF16_SPLIT or _FP16_SPLIT):
+    // Pbar for degrees m .. L+1 as 16-bit (hi, lo) pairs in a latitude-major (synthesis) and a
     // degree-major (analysis) layout; order m starts at tab_off[m], each
     // (m, parity) block has tab_kp[2m + parity] rows (padded to 16) by tab_hpad
     // latitudes

@@ -1,4 +1,5 @@
-// Legendre stage on the matrix cores, split BF16 precision (REXI_PREC_BF16_SPLIT).
+// Legendre stage on the matrix cores, split 16-bit precision: BF16
+// (REXI_PREC_BF16_SPLIT) or FP16 (REXI_PREC_FP16_SPLIT).
 //
 // For one zonal order m the Legendre transforms are dense products with the
 // matrix T[l][j] = Pbar_lm(mu_j) over the northern Gauss latitudes j
@@ -17,13 +18,20 @@
 // MFMA operand order (synthesis: M = latitude, K = degree; analysis: M =
 // degree, K = latitude): every (tile, K step) is a contiguous block of 64 lanes
 // x 16 bytes, so a wave reads one operand with one coalesced 1 KB load.  Every
-// value x is stored as x_hi = bf16(x), x_lo = bf16(x - x_hi), interleaved in
-// groups of four (hi[4], lo[4]); a product is accumulated in FP32 as
-// a_hi b_hi + a_hi b_lo + a_lo b_hi with v_mfma_f32_16x16x16_bf16 (relative
-// error about 2^-16 per product, plus FP32 accumulation).  The table entries
+// value x is stored as x_hi = t(x), x_lo = t(x - x_hi) for the 16-bit type t,
+// interleaved in groups of four (hi[4], lo[4]); a product is accumulated in
+// FP32 as a_hi b_hi + a_hi b_lo + a_lo b_hi with v_mfma_f32_16x16x16_bf16 or
+// _f16 (relative error about 2^-16 per product for BF16, 2^-21 for FP16, plus
+// FP32 accumulation).  FP16's exponent range is narrow, so in FP16 mode every
+// column of the data operand is scaled by a power of two that brings its
+// largest magnitude into [1/2, 1) (exact; undone on the FP32 sums), and the
+// table entries (|Pbar| < 64) fit as they are.  The table entries
 // come from the same exponent-tracked FP64 recurrence as the FP64 path, seeded
 // per 64-degree segment.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -35,6 +43,7 @@ constexpr int KB_SYN = 8;    // table K steps loaded per batch, synthesis
 constexpr int KB_ANA = 12;   // and analysis
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bf16 bits, round to nearest even (finite inputs)
@@ -48,6 +57,23 @@ __device__ __forceinline__ float bf16_value(unsigned short b) { return __uint_as
 __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
     hi = bf16_bits(static_cast<float>(x));
     lo = bf16_bits(static_cast<float>(x - static_cast<double>(bf16_value(hi))));
+}
+
+// x -> (hi, lo), both fp16: hi = fp16(x), lo = fp16(x - hi), residual in FP64.
+__device__ __forceinline__ void split_f16(double x, unsigned short& hi, unsigned short& lo) {
+    const _Float16 h = static_cast<_Float16>(x);
+    const _Float16 l = static_cast<_Float16>(x - static_cast<double>(h));
+    __builtin_memcpy(&hi, &h, 2);
+    __builtin_memcpy(&lo, &l, 2);
+}
+
+// The 16-bit operand type of a split Legendre stage.
+struct Bf16 {};
+struct F16 {};
+
+template <class E>
+__device__ __forceinline__ void split16(double x, unsigned short& hi, unsigned short& lo) {
+    if constexpr (std::is_same<E, F16>::value) split_f16(x, hi, lo); else split_bf16(x, hi, lo);
 }
 
 // Element k of a row stored as groups of four (hi[4], lo[4]): offsets in shorts.
@@ -70,7 +96,8 @@ struct TabArgs {
     int L, half, hpad, nseg;
 };
 
-// Pbar_lm(mu_j) (row i = l - m) into both tables, split into bf16 hi and lo.
+// Pbar_lm(mu_j) (row i = l - m) into both tables, split into 16-bit hi and lo.
+template <class E>
 __device__ __forceinline__ void put_entry(const TabArgs& A, int m, int i, int j, double v) {
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int par = i & 1, r = i >> 1;
@@ -85,7 +112,7 @@ __device__ __forceinline__ void put_entry(const TabArgs& A, int m, int i, int j,
     const long long pa = blk + ((static_cast<long long>(r >> 4) * (A.hpad >> 4) + (j >> 4)) * 64 + (r & 15) +
                                 16 * ((j & 15) >> 2)) * 8 + (j & 3);
     unsigned short hi, lo;
-    split_bf16(v, hi, lo);
+    split16<E>(v, hi, lo);
     A.p_syn[ps] = hi;
     A.p_syn[ps + 4] = lo;
     A.p_ana[pa] = hi;
@@ -96,6 +123,7 @@ __device__ __forceinline__ void put_entry(const TabArgs& A, int m, int i, int j,
 // the segment, written to both tables; the last segment of an order also
 // writes degree L+1.  Padding rows and latitudes stay zero (the tables are
 // cleared before).
+template <class E>
 __global__ __launch_bounds__(256) void leg_table_kernel(TabArgs A) {
     const int gs = blockIdx.x;
     const int j = blockIdx.y * blockDim.x + threadIdx.x;
@@ -109,23 +137,69 @@ __global__ __launch_bounds__(256) void leg_table_kernel(TabArgs A) {
     for (int d = 0; d < n; ++d) {
         const LegCoef c = A.rec[base + i0 + d];
         const double pn = __builtin_fma(c.A * mu, p, -(c.B * pm));
-        put_entry(A, m, i0 + d, j, ldexp(p, e));
+        put_entry<E>(A, m, i0 + d, j, ldexp(p, e));
         pm = p;
         p = pn;
     }
-    if (i0 + n == A.L - m + 1) put_entry(A, m, i0 + n, j, ldexp(p, e));
+    if (i0 + n == A.L - m + 1) put_entry<E>(A, m, i0 + n, j, ldexp(p, e));
 }
 
+template <class E>
 __device__ __forceinline__ void mfma3(f32x4& acc, const uint4& a, const uint4& b) {
     // a, b: (hi[4], lo[4]) as 16 bytes
-    bf16x4 ah, al, bh, bl;
-    __builtin_memcpy(&ah, &a.x, 8);
-    __builtin_memcpy(&al, &a.z, 8);
-    __builtin_memcpy(&bh, &b.x, 8);
-    __builtin_memcpy(&bl, &b.z, 8);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    if constexpr (std::is_same<E, F16>::value) {
+        f16x4 ah, al, bh, bl;
+        __builtin_memcpy(&ah, &a.x, 8);
+        __builtin_memcpy(&al, &a.z, 8);
+        __builtin_memcpy(&bh, &b.x, 8);
+        __builtin_memcpy(&bl, &b.z, 8);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, acc, 0, 0, 0);
+    } else {
+        bf16x4 ah, al, bh, bl;
+        __builtin_memcpy(&ah, &a.x, 8);
+        __builtin_memcpy(&al, &a.z, 8);
+        __builtin_memcpy(&bh, &b.x, 8);
+        __builtin_memcpy(&bl, &b.z, 8);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    }
+}
+
+// Per-column power-of-two scales of the data operand (FP16 mode): cmax holds
+// this thread's largest |value| per column; the workgroup's maxima go through
+// red ([waves][16] floats) and every thread receives sc[c] = 2^-e with
+// max |column c| in [2^(e-1), 2^e) (1 for an all-zero column).  Columns NC ..
+// 15 are known to be zero and are not reduced.
+template <int NC>
+__device__ __forceinline__ void column_scales(float* cmax, float* red, float* sc) {
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int c = NC; c < 16; ++c) cmax[c] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float v = cmax[c];
+#pragma unroll
+        for (int msk = 1; msk < WAVE; msk <<= 1) v = fmaxf(v, __shfl_xor(v, msk));
+        cmax[c] = v;
+    }
+    if (lane < 16) {
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) v = lane == c ? cmax[c] : v;
+        red[wv * 16 + lane] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float v = 0.f;
+        for (int w = 0; w < nw; ++w) v = fmaxf(v, red[w * 16 + threadIdx.x]);
+        int e = 0;
+        if (v > 0.f) (void)frexpf(v, &e);
+        sc[threadIdx.x] = ldexpf(1.0f, -max(e, -100));   // columns below 2^-101 stay unscaled
+    }
+    __syncthreads();
 }
 
 // Shorts per LDS row of a B operand holding n K-values (hi, lo): 4n bytes
@@ -171,9 +245,11 @@ struct MfmaArgs {
 //   U_l = -i m delta_l a/N_l + hA_{l-1} zeta_{l-1} a/N_{l-1} + hB_{l+1} zeta_{l+1} a/N_{l+1},
 //   V_l = -i m zeta_l a/N_l - hA_{l-1} delta_{l-1} a/N_{l-1} - hB_{l+1} delta_{l+1} a/N_{l+1}
 // (N_l = l(l+1)), rows up to degree L+1.
-template <int KIND>
+template <int KIND, class E>
 __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short xs[];
+    constexpr bool SCALED = std::is_same<E, F16>::value;
+    __shared__ float sred[4 * 16], sc[16];
     const int m = blockIdx.x;
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
@@ -182,12 +258,11 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     unsigned short* xp = xs;                        // [2][16][rowlen]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
-    // stage: one thread per (parity, row) forms the row's 16 columns, zero where
-    // there is no degree or column
-    for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+    // the 16 column values of staging row rp (parity, row), zero where there is
+    // no degree or column
+    auto row_values = [&](int rp, double* vp) {
         const int par = rp / A.kmax, r = rp - par * A.kmax;
         const int i = 2 * r + par;                  // l - m
-        double vp[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) vp[c] = 0.0;
         if constexpr (KIND == 0) {
@@ -234,13 +309,50 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
             vp[6] = V.x;
             vp[7] = V.y;
         }
+    };
+    if constexpr (SCALED) {
+        // the values go to LDS as FP32 (24 bits, more than the split keeps)
+        // with their column maxima; then they are scaled and split
+        float* stage = reinterpret_cast<float*>(xs + 2 * 16 * rowlen);   // [16][2 kmax]
+        float cmax[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            unsigned short hi, lo;
-            const int o = (par * 16 + c) * rowlen;
-            split_bf16(vp[c], hi, lo);
-            xp[o + grp_hi(r)] = hi;
-            xp[o + grp_lo(r)] = lo;
+        for (int c = 0; c < 16; ++c) cmax[c] = 0.f;
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+            double vp[16];
+            row_values(rp, vp);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const float v = static_cast<float>(vp[c]);
+                stage[c * 2 * A.kmax + rp] = v;
+                cmax[c] = fmaxf(cmax[c], fabsf(v));
+            }
+        }
+        column_scales<KIND == 0 ? 16 : 8>(cmax, sred, sc);
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+            const int par = rp / A.kmax, r = rp - par * A.kmax;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                unsigned short hi, lo;
+                const int o = (par * 16 + c) * rowlen;
+                split16<E>(static_cast<double>(stage[c * 2 * A.kmax + rp] * sc[c]), hi, lo);
+                xp[o + grp_hi(r)] = hi;
+                xp[o + grp_lo(r)] = lo;
+            }
+        }
+    } else {
+        // stage: one thread per (parity, row) writes the row's 16 columns
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+            const int par = rp / A.kmax, r = rp - par * A.kmax;
+            double vp[16];
+            row_values(rp, vp);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                unsigned short hi, lo;
+                const int o = (par * 16 + c) * rowlen;
+                split16<E>(vp[c], hi, lo);
+                xp[o + grp_hi(r)] = hi;
+                xp[o + grp_lo(r)] = lo;
+            }
         }
     }
     __syncthreads();
@@ -275,7 +387,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                 const bool in = k0 + u < nks;
                 const int g = 4 * min(k0 + u, nks - 1) + kq;   // group of four rows for this lane
                 const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
-                mfma3(acc[par], a[u], b);
+                mfma3<E>(acc[par], a[u], b);
             }
         }
     }
@@ -284,11 +396,12 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     // complex value into row (field, m) of the Fourier buffer [nfo][L+1][nlat]
     const int c = lane & 15;
     const int f = KIND == 0 ? f0 + (c >> 1) : (c >> 1);
+    const double unscale = SCALED ? 1.0 / static_cast<double>(sc[c]) : 1.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const float e = acc[0][t], o = acc[1][t];   // even, odd in mu
-        const double vn = static_cast<double>(e) + static_cast<double>(o);
-        const double vs = static_cast<double>(e) - static_cast<double>(o);
+        const double vn = (static_cast<double>(e) + static_cast<double>(o)) * unscale;
+        const double vs = (static_cast<double>(e) - static_cast<double>(o)) * unscale;
         const double vn_im = __shfl(vn, lane + 1 < WAVE ? lane + 1 : lane);
         const double vs_im = __shfl(vs, lane + 1 < WAVE ? lane + 1 : lane);
         const int j = tile * 16 + 4 * kq + t;
@@ -317,9 +430,11 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 // and Nsave = N (FP64).
 constexpr int ANA_WAVES = 16;
 
-template <int KIND>
+template <int KIND, class E>
 __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short ys[];
+    constexpr bool SCALED = std::is_same<E, F16>::value;
+    __shared__ float sred[ANA_WAVES * 16], sc[16];
     const int m = blockIdx.x;
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
@@ -329,10 +444,11 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
-    // stage: one thread per (latitude, input field) forms that field's columns
-    // for both folds (zero for padding latitudes and absent fields)
+    // staging item it = (latitude j, input field q): that field's columns for
+    // both folds (zero for padding latitudes and absent fields), handed to
+    // emit(column, S-fold value, D-fold value)
     constexpr int NFLD = KIND == 0 ? 8 : 5;
-    for (int it = threadIdx.x; it < A.hpad * NFLD; it += blockDim.x) {
+    auto stage_item = [&](int it, auto&& emit) {
         const int j = it / NFLD, q = it - j * NFLD;
         double2 S = make_double2(0.0, 0.0), D = make_double2(0.0, 0.0);
         const int fld = KIND == 0 ? f0 + q : q;
@@ -345,50 +461,78 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             S = make_double2((nn.x + ss.x) * wt, (nn.y + ss.y) * wt);
             D = make_double2((nn.x - ss.x) * wt, (nn.y - ss.y) * wt);
         }
-        // (column, value) pairs of this field, fold S then D
-        int col[4];
-        double vs[4], vd[4];
-        int nc = 2;
+        // (column, S-fold value, D-fold value) of this field
         if constexpr (KIND == 0) {
-            col[0] = 2 * q; vs[0] = S.x; vd[0] = D.x;
-            col[1] = 2 * q + 1; vs[1] = S.y; vd[1] = D.y;
+            emit(j, 2 * q, S.x, D.x);
+            emit(j, 2 * q + 1, S.y, D.y);
         } else {
             if (q == 0) {          // hU: Pbar columns 0, 1
-                col[0] = 0; vs[0] = dm * S.y; vd[0] = dm * D.y;
-                col[1] = 1; vs[1] = -dm * S.x; vd[1] = -dm * D.x;
+                emit(j, 0, dm * S.y, dm * D.y);
+                emit(j, 1, -dm * S.x, -dm * D.x);
             } else if (q == 1) {   // hV: H columns 8, 9
-                col[0] = 8; vs[0] = S.x; vd[0] = D.x;
-                col[1] = 9; vs[1] = S.y; vd[1] = D.y;
+                emit(j, 8, S.x, D.x);
+                emit(j, 9, S.y, D.y);
             } else if (q == 2) {   // zU: Pbar columns 2, 3; H columns 12, 13
-                col[0] = 2; vs[0] = dm * S.y; vd[0] = dm * D.y;
-                col[1] = 3; vs[1] = -dm * S.x; vd[1] = -dm * D.x;
-                col[2] = 12; vs[2] = S.x; vd[2] = D.x;
-                col[3] = 13; vs[3] = S.y; vd[3] = D.y;
-                nc = 4;
+                emit(j, 2, dm * S.y, dm * D.y);
+                emit(j, 3, -dm * S.x, -dm * D.x);
+                emit(j, 12, S.x, D.x);
+                emit(j, 13, S.y, D.y);
             } else if (q == 3) {   // zV: Pbar columns 4, 5; H columns 10, 11
-                col[0] = 4; vs[0] = -dm * S.y; vd[0] = -dm * D.y;
-                col[1] = 5; vs[1] = dm * S.x; vd[1] = dm * D.x;
-                col[2] = 10; vs[2] = S.x; vd[2] = D.x;
-                col[3] = 11; vs[3] = S.y; vd[3] = D.y;
-                nc = 4;
+                emit(j, 4, -dm * S.y, -dm * D.y);
+                emit(j, 5, dm * S.x, dm * D.x);
+                emit(j, 10, S.x, D.x);
+                emit(j, 11, S.y, D.y);
             } else {               // KE: Pbar columns 6, 7; columns 14, 15 stay zero
-                col[0] = 6; vs[0] = S.x; vd[0] = D.x;
-                col[1] = 7; vs[1] = S.y; vd[1] = D.y;
-                col[2] = 14; vs[2] = 0.0; vd[2] = 0.0;
-                col[3] = 15; vs[3] = 0.0; vd[3] = 0.0;
-                nc = 4;
+                emit(j, 6, S.x, D.x);
+                emit(j, 7, S.y, D.y);
+                emit(j, 14, 0.0, 0.0);
+                emit(j, 15, 0.0, 0.0);
             }
         }
-        for (int u = 0; u < nc; ++u) {
+    };
+    if constexpr (SCALED) {
+        // the values go to LDS as FP32 (24 bits, more than the split keeps)
+        // with their column maxima; then they are scaled and split.  The FP32
+        // buffer [16][2][hpad] shares the region of zs, which is written only
+        // after the products.
+        float* stage = zs;
+        float cmax[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) cmax[k] = 0.f;
+        for (int it = threadIdx.x; it < A.hpad * NFLD; it += blockDim.x)
+            stage_item(it, [&](int j, int col, double vs, double vd) {
+                const float s0 = static_cast<float>(vs), s1 = static_cast<float>(vd);
+                stage[(col * 2) * A.hpad + j] = s0;
+                stage[(col * 2 + 1) * A.hpad + j] = s1;
+                const float v = fmaxf(fabsf(s0), fabsf(s1));
+#pragma unroll
+                for (int k = 0; k < 16; ++k) cmax[k] = col == k ? fmaxf(cmax[k], v) : cmax[k];
+            });
+        column_scales<KIND == 0 ? 16 : 14>(cmax, sred, sc);
+        for (int it = threadIdx.x; it < A.hpad * 16; it += blockDim.x) {
+            const int col = it / A.hpad, j = it - col * A.hpad;
             unsigned short hi, lo;
-            const int o0 = col[u] * rowlen, o1 = (16 + col[u]) * rowlen;
-            split_bf16(vs[u], hi, lo);
+            const int o0 = col * rowlen, o1 = (16 + col) * rowlen;
+            split16<E>(static_cast<double>(stage[(col * 2) * A.hpad + j] * sc[col]), hi, lo);
             yp[o0 + grp_hi(j)] = hi;
             yp[o0 + grp_lo(j)] = lo;
-            split_bf16(vd[u], hi, lo);
+            split16<E>(static_cast<double>(stage[(col * 2 + 1) * A.hpad + j] * sc[col]), hi, lo);
             yp[o1 + grp_hi(j)] = hi;
             yp[o1 + grp_lo(j)] = lo;
         }
+        __syncthreads();   // stage (= zs) is free again only after every split
+    } else {
+        for (int it = threadIdx.x; it < A.hpad * NFLD; it += blockDim.x)
+            stage_item(it, [&](int j, int col, double vs, double vd) {
+                unsigned short hi, lo;
+                const int o0 = col * rowlen, o1 = (16 + col) * rowlen;
+                split16<E>(vs, hi, lo);
+                yp[o0 + grp_hi(j)] = hi;
+                yp[o0 + grp_lo(j)] = lo;
+                split16<E>(vd, hi, lo);
+                yp[o1 + grp_hi(j)] = hi;
+                yp[o1 + grp_lo(j)] = lo;
+            });
     }
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
@@ -418,7 +562,7 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
                 const bool in = k0 + u < nks;
                 const int g = 4 * min(k0 + u, nks - 1) + kq;
                 const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
-                mfma3(acc, a[u], b);
+                mfma3<E>(acc, a[u], b);
             }
         }
 #pragma unroll
@@ -429,7 +573,7 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
                 const int f = f0 + (c >> 1);
                 if (i >= Lm || f >= A.nf) continue;
                 reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + base + i)[c & 1] =
-                    static_cast<double>(acc[t]);
+                    static_cast<double>(acc[t]) / (SCALED ? static_cast<double>(sc[c]) : 1.0);
             } else {
                 zs[(par * A.kmax + r) * 16 + c] = acc[t];
             }
@@ -443,13 +587,20 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             const float* zrow = zs + ((i & 1) * A.kmax + (i >> 1)) * 16;
             const float* zup = zs + (((i + 1) & 1) * A.kmax + ((i + 1) >> 1)) * 16;   // degree l+1 (<= L+1)
             const LegCoef rc = A.rec[base + i];
-            double v = static_cast<double>(zrow[k]);
-            v = __builtin_fma(rc.hA, static_cast<double>(zup[8 + k]), v);
+            // undo the column scales (1 unless FP16)
+            const double uP = SCALED ? 1.0 / static_cast<double>(sc[k]) : 1.0;
+            const double uH = SCALED ? 1.0 / static_cast<double>(sc[8 + k]) : 1.0;
+            double v = static_cast<double>(zrow[k]) * uP;
+            double hsum = rc.hA * static_cast<double>(zup[8 + k]);
             if (i >= 1) {
                 const float* zdn = zs + (((i - 1) & 1) * A.kmax + ((i - 1) >> 1)) * 16;
-                v = __builtin_fma(rc.hB, static_cast<double>(zdn[8 + k]), v);
+                hsum = __builtin_fma(rc.hB, static_cast<double>(zdn[8 + k]), hsum);
             }
-            if (k >= 4) v = __builtin_fma(A.noa2[m + i], static_cast<double>(zrow[k + 2]), v);
+            v = __builtin_fma(hsum, uH, v);
+            if (k >= 4) {
+                const double uK = SCALED ? 1.0 / static_cast<double>(sc[k + 2]) : 1.0;
+                v = __builtin_fma(A.noa2[m + i] * uK, static_cast<double>(zrow[k + 2]), v);
+            }
             const int f = k >> 1, part = k & 1;
             const size_t e2 = (static_cast<size_t>(f) * A.modes + base + i) * 2 + part;
             double o = __builtin_fma(A.c0, v, A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0);
@@ -513,7 +664,10 @@ int build_split_tables(swe_ctx* ctx, hipStream_t stream) {
     T.nseg = ctx->nseg;
     const size_t bytes = sizeof(unsigned short) * static_cast<size_t>(ctx->tab_len);
     for (unsigned short* p : {ctx->d_tab_psyn, ctx->d_tab_pana}) REXI_HIP(hipMemsetAsync(p, 0, bytes, stream));
-    hipLaunchKernelGGL(leg_table_kernel, dim3(ctx->nseg, (T.half + 255) / 256), dim3(256), 0, stream, T);
+    if (ctx->prec & REXI_PREC_FP16_SPLIT)
+        hipLaunchKernelGGL(leg_table_kernel<F16>, dim3(ctx->nseg, (T.half + 255) / 256), dim3(256), 0, stream, T);
+    else
+        hipLaunchKernelGGL(leg_table_kernel<Bf16>, dim3(ctx->nseg, (T.half + 255) / 256), dim3(256), 0, stream, T);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
@@ -524,18 +678,20 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     A.spec = reinterpret_cast<const double2*>(spec);
     A.four_out = reinterpret_cast<double2*>(four);
     A.nf = nf;
-    const size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.kmax));
+    size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.kmax));
+    if (ctx->prec & REXI_PREC_FP16_SPLIT) lds += sizeof(float) * 16 * 2 * static_cast<size_t>(A.kmax);
     const int tiles = A.hpad / 16;
     const dim3 grid(ctx->L + 1, (tiles + 3) / 4, kind == 0 ? (nf + 7) / 8 : 1);
+    const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
+    const void* fn = kind == 0 ? (f16 ? reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, F16>)
+                                      : reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, Bf16>))
+                               : (f16 ? reinterpret_cast<const void*>(&leg_synth_mfma_kernel<1, F16>)
+                                      : reinterpret_cast<const void*>(&leg_synth_mfma_kernel<1, Bf16>));
     int rc;
-    const void* fn = kind == 0 ? reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0>)
-                               : reinterpret_cast<const void*>(&leg_synth_mfma_kernel<1>);
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_SYNTH, stream);
-    if (kind == 0)
-        hipLaunchKernelGGL(leg_synth_mfma_kernel<0>, grid, dim3(256), lds, stream, A);
-    else
-        hipLaunchKernelGGL(leg_synth_mfma_kernel<1>, grid, dim3(256), lds, stream, A);
+    void* kargs[] = {&A};
+    REXI_HIP(hipLaunchKernel(fn, grid, dim3(256), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_SYNTH, slot, stream);
     return REXI_OK;
@@ -555,17 +711,21 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     A.c1 = c1;
     A.nf = nf;
     size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.hpad));
-    if (kind == 1) lds += sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax);
+    // zs (products, kind 1) and the FP16 mode's FP32 staging share one region
+    size_t zbytes = kind == 1 ? sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax) : 0;
+    if (ctx->prec & REXI_PREC_FP16_SPLIT) zbytes = std::max(zbytes, sizeof(float) * 16 * 2 * static_cast<size_t>(A.hpad));
+    lds += zbytes;
     const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
+    const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
+    const void* fn = kind == 0 ? (f16 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0, F16>)
+                                      : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0, Bf16>))
+                               : (f16 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1, F16>)
+                                      : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1, Bf16>));
     int rc;
-    const void* fn = kind == 0 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0>)
-                               : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1>);
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
-    if (kind == 0)
-        hipLaunchKernelGGL(leg_anal_mfma_kernel<0>, grid, dim3(ANA_WAVES * WAVE), lds, stream, A);
-    else
-        hipLaunchKernelGGL(leg_anal_mfma_kernel<1>, grid, dim3(ANA_WAVES * WAVE), lds, stream, A);
+    void* kargs[] = {&A};
+    REXI_HIP(hipLaunchKernel(fn, grid, dim3(ANA_WAVES * WAVE), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
     return REXI_OK;

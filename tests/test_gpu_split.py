@@ -1,11 +1,16 @@
-"""Split-precision (bf16 hi/lo on the matrix cores, FP32 accumulation) Legendre
-stage against the FP64 oracle.
+"""Split-precision (16-bit hi/lo on the matrix cores, FP32 accumulation) Legendre
+stage against the FP64 oracle, in both modes: BF16 and FP16.
 
 Stated tolerance: every product a b is formed as a_hi b_hi + a_hi b_lo + a_lo b_hi
-with |x - x_hi - x_lo| <= 2^-18 |x| (two round-to-nearest bf16 steps, 8 stored
-mantissa bits each) and accumulated in FP32 over K = max(L + 1, nlat/2) terms at
-most, so an output carries at most u_split(K) = 3 2^-18 + K 2^-24 times the sum
-of the magnitudes of its terms.  For these smooth and (l+1)^-2 spectra that sum
+with |x - x_hi - x_lo| <= v |x|, v = 2^-16 for BF16 (two round-to-nearest steps
+of 8 significant bits) and 2^-22 for FP16 (11 significant bits; the data columns
+are scaled by powers of two so that their largest entry lies in [1/2, 1), and
+entries below FP16's smallest subnormal 2^-24 flush, an absolute 2^-25 of the
+column's largest entry), so a product is off by at most 3 v of its magnitude
+(the dropped a_lo b_lo included) plus 2^-24 of the largest; the FP32
+accumulation over K = max(L + 1, nlat/2) terms adds K 2^-24.  An output thus
+carries at most u_split(K) = 3 v + (K + 1) 2^-24 times the sum of the
+magnitudes of its terms.  For these smooth and (l+1)^-2 spectra that sum
 stays within 16 times the field's largest value, so the transforms' bar is
 16 u_split(K) of each field's largest entry (measured errors, printed, are near
 1e-5).  The non-linear tendency sums terms that largely cancel (N_delta =
@@ -25,9 +30,19 @@ from paper_1805_06557_amd.inputs import jet_state, random_field
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-def u_split(L, nlat):
-    return 3 * 2.0 ** -18 + max(L + 1, nlat // 2) * 2.0 ** -24
+SPLIT_UNIT = {"bf16": 2.0 ** -16, "fp16": 2.0 ** -22}
+
+
+def u_split(L, nlat, mode="bf16"):
+    return 3 * SPLIT_UNIT[mode] + (max(L + 1, nlat // 2) + 1) * 2.0 ** -24
+
+
 GRIDS = [(31, 48, 96), (63, 96, 192), (127, 192, 384)]
+MODES = ["bf16", "fp16"]
+
+
+def _prec(api, mode):
+    return api.PREC_BF16_SPLIT if mode == "bf16" else api.PREC_FP16_SPLIT
 
 
 def _api():
@@ -58,50 +73,53 @@ def _scaled(got, ref, scale):
     return [float(np.abs(got[f] - ref[f]).max() / scale[f]) for f in range(3)]
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("L,nlat,nlon", GRIDS, ids=[f"T{g[0]}" for g in GRIDS])
-def test_split_transforms(L, nlat, nlon):
+def test_split_transforms(L, nlat, nlon, mode):
     api = _api()
     g = Grid(L, nlat, nlon, Params())
     rng = np.random.default_rng(300 + L)
     nf = 10                                    # more than one group of eight fields
     spec = np.stack([random_field(L, rng, 10.0 ** (k % 3)) for k in range(nf)])
-    ctx = api.SWE(L, nlat, nlon, prec=api.PREC_BF16_SPLIT)
+    ctx = api.SWE(L, nlat, nlon, prec=_prec(api, mode))
     ds = torch.from_numpy(spec).cuda()
     dg = torch.empty((nf, nlat, nlon), dtype=torch.float64, device="cuda")
     ctx.sh_synthesis(ds, dg, nf)
     ref = np.stack([g.synthesis(spec[f]) for f in range(nf)]).reshape(nf, -1)
     e = _rel(dg.cpu().numpy().reshape(nf, -1), ref)
-    print("synthesis", L, max(e))
-    assert max(e) <= 16 * u_split(L, nlat), e
+    print("synthesis", mode, L, max(e))
+    assert max(e) <= 16 * u_split(L, nlat, mode), e
     field = rng.standard_normal((nf, nlat, nlon))
     dso = torch.empty((nf, api.n_modes(L)), dtype=torch.complex128, device="cuda")
     ctx.sh_analysis(torch.from_numpy(field).cuda(), dso, nf)
     refa = np.stack([g.analysis(field[f]) for f in range(nf)])
     e = _rel(dso.cpu().numpy(), refa)
-    print("analysis", L, max(e))
-    assert max(e) <= 16 * u_split(L, nlat), e
+    print("analysis", mode, L, max(e))
+    assert max(e) <= 16 * u_split(L, nlat, mode), e
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("L,nlat,nlon", GRIDS[:2], ids=[f"T{g[0]}" for g in GRIDS[:2]])
-def test_split_heun_increment(L, nlat, nlon):
+def test_split_heun_increment(L, nlat, nlon, mode):
     api = _api()
     g = Grid(L, nlat, nlon, Params())
     U0 = jet_state(L, 3)
     tau = 900.0
     ref = onl.heun(g, U0, tau)
-    ctx = api.SWE(L, nlat, nlon, prec=api.PREC_BF16_SPLIT)
+    ctx = api.SWE(L, nlat, nlon, prec=_prec(api, mode))
     d0 = torch.from_numpy(U0).cuda()
     d1 = torch.empty_like(d0)
     ctx.nonlinear_step(tau, d0, d1)
     got = d1.cpu().numpy()
     e = _scaled(got - U0, ref - U0, tau * _term_scales(g, U0))
-    print("heun increment", L, e, "relative to the increment", _rel(got - U0, ref - U0))
-    assert max(e) <= 24 * u_split(L, nlat), e
+    print("heun increment", mode, L, e, "relative to the increment", _rel(got - U0, ref - U0))
+    assert max(e) <= 24 * u_split(L, nlat, mode), e
     ctx.close()
 
 
-def test_split_matches_fp64_path_at_t255():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_matches_fp64_path_at_t255(mode):
     """The T255 768 x 384 non-linear step with the split Legendre stage against
     the FP64 path (itself pinned to the oracle), per field, on the increment."""
     api = _api()
@@ -109,7 +127,7 @@ def test_split_matches_fp64_path_at_t255():
     U0 = jet_state(L, 2)
     d0 = torch.from_numpy(U0).cuda()
     outs = []
-    for prec in (0, api.PREC_BF16_SPLIT):
+    for prec in (0, _prec(api, mode)):
         ctx = api.SWE(L, nlat, nlon, prec=prec)
         d1 = torch.empty_like(d0)
         ctx.nonlinear_step(1800.0, d0, d1)
@@ -117,11 +135,12 @@ def test_split_matches_fp64_path_at_t255():
         ctx.close()
     g = Grid(L, nlat, nlon, Params())
     e = _scaled(outs[1] - U0, outs[0] - U0, 1800.0 * _term_scales(g, U0))
-    print("T255 heun increment vs FP64 path", e, "relative to the increment", _rel(outs[1] - U0, outs[0] - U0))
-    assert max(e) <= 24 * u_split(L, nlat), e
+    print("T255 heun increment vs FP64 path", mode, e, "relative to the increment", _rel(outs[1] - U0, outs[0] - U0))
+    assert max(e) <= 24 * u_split(L, nlat, mode), e
 
 
-def test_split_t511_round_trip_and_step():
+@pytest.mark.parametrize("mode", MODES)
+def test_split_t511_round_trip_and_step(mode):
     """T511 on 1536 x 768 (the analysis workgroup then needs more than 64 KB of
     LDS): synthesis then analysis of band-limited fields returns them to
     16 u_split(K) of each field's largest coefficient (Gauss quadrature makes
@@ -132,19 +151,19 @@ def test_split_t511_round_trip_and_step():
     rng = np.random.default_rng(511)
     nf = 2
     spec = np.stack([random_field(L, rng, 1.0) for _ in range(nf)])
-    ctx = api.SWE(L, nlat, nlon, prec=api.PREC_BF16_SPLIT)
+    ctx = api.SWE(L, nlat, nlon, prec=_prec(api, mode))
     ds = torch.from_numpy(spec).cuda()
     dg = torch.empty((nf, nlat, nlon), dtype=torch.float64, device="cuda")
     ctx.sh_synthesis(ds, dg, nf)
     back = torch.empty_like(ds)
     ctx.sh_analysis(dg, back, nf)
     e = _rel(back.cpu().numpy(), spec)
-    print("T511 split round trip", e)
-    assert max(e) <= 16 * u_split(L, nlat), e
+    print("T511 split round trip", mode, e)
+    assert max(e) <= 16 * u_split(L, nlat, mode), e
     U0 = jet_state(L, 4)
     d0 = torch.from_numpy(U0).cuda()
     outs = []
-    for prec in (0, api.PREC_BF16_SPLIT):
+    for prec in (0, _prec(api, mode)):
         c = api.SWE(L, nlat, nlon, prec=prec)
         d1 = torch.empty_like(d0)
         c.nonlinear_step(900.0, d0, d1)
@@ -152,13 +171,6 @@ def test_split_t511_round_trip_and_step():
         c.close()
     g = Grid(L, nlat, nlon, Params())
     e = _scaled(outs[1] - U0, outs[0] - U0, 900.0 * _term_scales(g, U0))
-    print("T511 heun increment vs FP64 path", e, "relative to the increment", _rel(outs[1] - U0, outs[0] - U0))
-    assert max(e) <= 24 * u_split(L, nlat), e
+    print("T511 heun increment vs FP64 path", mode, e, "relative to the increment", _rel(outs[1] - U0, outs[0] - U0))
+    assert max(e) <= 24 * u_split(L, nlat, mode), e
     ctx.close()
-
-
-def test_fp16_split_is_not_built():
-    api = _api()
-    with pytest.raises(api.RexiError) as ei:
-        api.SWE(31, 48, 96, prec=api.PREC_FP16_SPLIT)
-    assert ei.value.code == api.REXI_ENOTSUP
