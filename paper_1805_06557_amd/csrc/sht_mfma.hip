@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
         // table operands in batches of KB steps, all loads of a batch issued
         // before its products (a serial load-multiply chain leaves the
         // small-m workgroups, the longest ones, waiting on memory latency);
-        // steps past the end reload the last block and multiply a zero operand
+        // steps past the end reload the last block and are not multiplied
         const int nks = K >> 4;
         for (int k0 = 0; k0 < nks; k0 += KB_SYN) {
             uint4 a[KB_SYN];
@@ -384,10 +384,11 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
             __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
 #pragma unroll
             for (int u = 0; u < KB_SYN; ++u) {
-                const bool in = k0 + u < nks;
-                const int g = 4 * min(k0 + u, nks - 1) + kq;   // group of four rows for this lane
-                const uint4 b = keep_if(in, *reinterpret_cast<const uint4*>(bp + 8 * g));
-                mfma3<E>(acc[par], a[u], b);
+                if (k0 + u < nks) {                         // uniform: no products past the end
+                    const int g = 4 * (k0 + u) + kq;        // group of four rows for this lane
+                    const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
+                    mfma3<E>(acc[par], a[u], b);
+                }
             }
         }
     }
