@@ -445,6 +445,28 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
     const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
     const double dm = static_cast<double>(m);
+    // KIND 1: the epilogue's inputs that do not depend on the products (H
+    // coefficients, l(l+1)/a^2, U0 + c1 Nprev) of the thread's first EPI items
+    // (degree, output column) are requested before anything else
+    constexpr int EPI = 2;
+    double pre_hA[EPI], pre_hB[EPI], pre_nk[EPI], pre_ob[EPI];
+    auto epi_inputs = [&](int it, double& hA, double& hB, double& nk, double& ob) {
+        const int i = it / 6, k = it - i * 6;
+        hA = A.rec[base + i].hA;
+        hB = A.rec[base + i].hB;
+        nk = A.noa2[m + i];
+        const size_t e2 = (static_cast<size_t>(k >> 1) * A.modes + base + i) * 2 + (k & 1);
+        ob = A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0;
+        if (A.Nprev) ob = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], ob);
+    };
+    if constexpr (KIND == 1) {
+#pragma unroll
+        for (int q = 0; q < EPI; ++q) {
+            const int it = threadIdx.x + q * static_cast<int>(blockDim.x);
+            pre_hA[q] = pre_hB[q] = pre_nk[q] = pre_ob[q] = 0.0;
+            if (it < Lm * 6) epi_inputs(it, pre_hA[q], pre_hB[q], pre_nk[q], pre_ob[q]);
+        }
+    }
     // staging item it = (latitude j, input field q): that field's columns for
     // both folds (zero for padding latitudes and absent fields), handed to
     // emit(column, S-fold value, D-fold value)
@@ -583,31 +605,37 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     if constexpr (KIND == 1) {
         __syncthreads();
         // one thread per (degree, output column)
-        for (int it = threadIdx.x; it < Lm * 6; it += blockDim.x) {
+        auto finish = [&](int it, double hA, double hB, double nk, double ob) {
             const int i = it / 6, k = it - i * 6;
             const float* zrow = zs + ((i & 1) * A.kmax + (i >> 1)) * 16;
             const float* zup = zs + (((i + 1) & 1) * A.kmax + ((i + 1) >> 1)) * 16;   // degree l+1 (<= L+1)
-            const LegCoef rc = A.rec[base + i];
             // undo the column scales (1 unless FP16)
             const double uP = SCALED ? 1.0 / static_cast<double>(sc[k]) : 1.0;
             const double uH = SCALED ? 1.0 / static_cast<double>(sc[8 + k]) : 1.0;
             double v = static_cast<double>(zrow[k]) * uP;
-            double hsum = rc.hA * static_cast<double>(zup[8 + k]);
+            double hsum = hA * static_cast<double>(zup[8 + k]);
             if (i >= 1) {
                 const float* zdn = zs + (((i - 1) & 1) * A.kmax + ((i - 1) >> 1)) * 16;
-                hsum = __builtin_fma(rc.hB, static_cast<double>(zdn[8 + k]), hsum);
+                hsum = __builtin_fma(hB, static_cast<double>(zdn[8 + k]), hsum);
             }
             v = __builtin_fma(hsum, uH, v);
             if (k >= 4) {
                 const double uK = SCALED ? 1.0 / static_cast<double>(sc[k + 2]) : 1.0;
-                v = __builtin_fma(A.noa2[m + i] * uK, static_cast<double>(zrow[k + 2]), v);
+                v = __builtin_fma(nk * uK, static_cast<double>(zrow[k + 2]), v);
             }
-            const int f = k >> 1, part = k & 1;
-            const size_t e2 = (static_cast<size_t>(f) * A.modes + base + i) * 2 + part;
-            double o = __builtin_fma(A.c0, v, A.U0 ? reinterpret_cast<const double*>(A.U0)[e2] : 0.0);
-            if (A.Nprev) o = __builtin_fma(A.c1, reinterpret_cast<const double*>(A.Nprev)[e2], o);
+            const size_t e2 = (static_cast<size_t>(k >> 1) * A.modes + base + i) * 2 + (k & 1);
             if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
-            reinterpret_cast<double*>(A.out)[e2] = o;
+            reinterpret_cast<double*>(A.out)[e2] = __builtin_fma(A.c0, v, ob);
+        };
+#pragma unroll
+        for (int q = 0; q < EPI; ++q) {
+            const int it = threadIdx.x + q * static_cast<int>(blockDim.x);
+            if (it < Lm * 6) finish(it, pre_hA[q], pre_hB[q], pre_nk[q], pre_ob[q]);
+        }
+        for (int it = threadIdx.x + EPI * static_cast<int>(blockDim.x); it < Lm * 6; it += blockDim.x) {
+            double hA, hB, nk, ob;
+            epi_inputs(it, hA, hB, nk, ob);
+            finish(it, hA, hB, nk, ob);
         }
     }
 }
