@@ -121,15 +121,8 @@ __device__ __forceinline__ RowRec32 round_rec(const RowRec& r) {
     return q;
 }
 
-__device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
-                                               RowRec* __restrict__ rec, RowRec32* __restrict__ rec32, int L,
-                                               int modes, double dt, double H, int m, int j) {
-    const int base = m * (2 * L + 3 - m) / 2;
-    const int idx = base + j;
-    const int Lm = L - m + 1;
-    const ModeCoef cf = coef[idx];
-    const double2 rh = U0[idx], rz = U0[modes + idx], rd = U0[2 * modes + idx];
-    const int cd = j & 1;                                   // chain in which row j is a delta row
+// The delta row (coupled to h) and the zeta row of degree k = m + j.
+__device__ __forceinline__ RowRec delta_row(const ModeCoef& cf, double2 rh, double2 rd, double dt, double H) {
     RowRec d;
     d.a = -dt * cf.cm;
     d.c = -dt * cf.cp;
@@ -145,8 +138,10 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
     d.cf = static_cast<float>(d.c);
     d.rfx = static_cast<float>(rd.x);
     d.rfy = static_cast<float>(rd.y);
-    rec[2 * base + cd * Lm + j] = d;
-    rec32[2 * base + cd * Lm + j] = round_rec(d);
+    return d;
+}
+
+__device__ __forceinline__ RowRec zeta_row(const ModeCoef& cf, double2 rz, double dt) {
     RowRec z;
     z.a = dt * cf.cm;
     z.c = dt * cf.cp;
@@ -160,6 +155,21 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
     z.cf = static_cast<float>(z.c);
     z.rfx = static_cast<float>(rz.x);
     z.rfy = static_cast<float>(rz.y);
+    return z;
+}
+
+__device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, const ModeCoef* __restrict__ coef,
+                                               RowRec* __restrict__ rec, RowRec32* __restrict__ rec32, int L,
+                                               int modes, double dt, double H, int m, int j) {
+    const int base = m * (2 * L + 3 - m) / 2;
+    const int idx = base + j;
+    const int Lm = L - m + 1;
+    const ModeCoef cf = coef[idx];
+    const int cd = j & 1;                                   // chain in which row j is a delta row
+    const RowRec d = delta_row(cf, U0[idx], U0[2 * modes + idx], dt, H);
+    rec[2 * base + cd * Lm + j] = d;
+    rec32[2 * base + cd * Lm + j] = round_rec(d);
+    const RowRec z = zeta_row(cf, U0[modes + idx], dt);
     rec[2 * base + (1 - cd) * Lm + j] = z;
     rec32[2 * base + (1 - cd) * Lm + j] = round_rec(z);
 }
@@ -202,6 +212,10 @@ struct SolveArgs {
     int L, modes, N, npb, npad;         // npb: workgroups per chain; npad: N rounded up to 64 P
     int nck_max, rec_bytes;             // per-wave checkpoints; LDS bytes of the records
     double dtH;
+    // the fused schedule builds its chain's row records itself from these
+    const double2* __restrict__ U0;     // [3][modes] state
+    const ModeCoef* __restrict__ coef;  // [modes]
+    double dt, H;
 };
 
 struct Lane {
@@ -403,9 +417,20 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     const int nseg = (Lm + S - 1) / S;
     constexpr int CKW = ckpt_words<SCHED>();
 
-    // the chain's row records, shared by all waves of the block
+    // the chain's row records, shared by all waves of the block: built here from
+    // the state and the mode coefficients (fused schedule; row j of chain C is
+    // a delta row when j and C have the same parity), else copied from the
+    // records the factorization was built from
     RecT<T>* rc = reinterpret_cast<RecT<T>*>(smem);
-    {
+    if constexpr (SCHED == FUSED) {
+        for (int j = threadIdx.x; j < Lm; j += blockDim.x) {
+            const int idx = base + j;
+            const ModeCoef cf = A.coef[idx];
+            const RowRec r = ((j & 1) == C) ? delta_row(cf, A.U0[idx], A.U0[2 * A.modes + idx], A.dt, A.H)
+                                            : zeta_row(cf, A.U0[A.modes + idx], A.dt);
+            if constexpr (std::is_same<T, float>::value) rc[j] = round_rec(r); else rc[j] = r;
+        }
+    } else {
         static_assert(sizeof(RecT<T>) % sizeof(uint4) == 0, "records are copied in 16-byte units");
         const uint4* src = reinterpret_cast<const uint4*>(chain_records<T>(A, 2 * base + C * Lm));
         uint4* dst = reinterpret_cast<uint4*>(rc);
@@ -846,7 +871,7 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
         plan.max_L = max_L;
     }
     swe_ctx* c0 = mem[0].ctx;
-    {
+    if (SCHED != FUSED) {
         hipLaunchKernelGGL(rexi_rows_batched_kernel, dim3(plan.max_L + 1, count), dim3(256), 0, stream,
                            reinterpret_cast<const RowsArgs*>(plan.d_rows));
         REXI_HIP(hipGetLastError());
@@ -922,7 +947,7 @@ int launch_shape(swe_ctx* ctx, const SolveArgs& A, const Tuning& t, hipStream_t 
 
 // Shape-independent arguments of one member's solve; allocates the row records
 // and (for more than one pole wave) the partial sums.
-int base_args(swe_ctx* ctx, int N, double dt, const double* U1, int P, SolveArgs& A, int& nparts) {
+int base_args(swe_ctx* ctx, int N, double dt, const double* U0, const double* U1, int P, SolveArgs& A, int& nparts) {
     if (!ctx->d_rows) {
         if (hipMalloc(&ctx->d_rows, sizeof(RowRec) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess ||
             hipMalloc(&ctx->d_rows32, sizeof(RowRec32) * 2 * static_cast<size_t>(ctx->modes)) != hipSuccess)
@@ -938,6 +963,10 @@ int base_args(swe_ctx* ctx, int N, double dt, const double* U1, int P, SolveArgs
     A.npad = (N + 2 * WAVE - 1) / (2 * WAVE) * (2 * WAVE);
     nparts = (N + WAVE * P - 1) / (WAVE * P);          // pole waves that produce partial sums
     A.dtH = dt * ctx->H;
+    A.U0 = reinterpret_cast<const double2*>(U0);
+    A.coef = ctx->d_coef;
+    A.dt = dt;
+    A.H = ctx->H;
     A.fact = nullptr;
     A.ckpt = nullptr;
     A.npb = A.nck_max = A.rec_bytes = 0;
@@ -964,9 +993,10 @@ int base_args(swe_ctx* ctx, int N, double dt, const double* U1, int P, SolveArgs
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
     SolveArgs A;
     int nparts = 0;
-    int rc = base_args(ctx, N, dt, U1, ctx->tune.poles_per_lane, A, nparts);
+    int rc = base_args(ctx, N, dt, U0, U1, ctx->tune.poles_per_lane, A, nparts);
     if (rc != REXI_OK) return rc;
-    {
+    if (ctx->tune.solver == REXI_SOLVER_STREAM || ctx->tune.solver == REXI_SOLVER_HYBRID) {
+        // the streaming schedules read (and factorize) records built in HBM
         hipLaunchKernelGGL(rexi_rows_kernel, dim3(ctx->L + 1), dim3(256), 0, stream,
                            reinterpret_cast<const double2*>(U0), ctx->d_coef, reinterpret_cast<RowRec*>(ctx->d_rows),
                            reinterpret_cast<RowRec32*>(ctx->d_rows32), ctx->L, ctx->modes, dt, ctx->H);
@@ -1091,7 +1121,7 @@ int launch_rexi_batched(const BatchMember* mem, int count, hipStream_t stream) {
     std::vector<SolveArgs> A(count);
     for (int i = 0; i < count; ++i) {
         int nparts = 0;
-        const int rc = base_args(mem[i].ctx, mem[i].N, mem[i].dt, mem[i].U1, t.poles_per_lane, A[i], nparts);
+        const int rc = base_args(mem[i].ctx, mem[i].N, mem[i].dt, mem[i].U0, mem[i].U1, t.poles_per_lane, A[i], nparts);
         if (rc != REXI_OK) return rc;
     }
     if (!c0->batch) c0->batch = new BatchPlan();
