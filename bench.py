@@ -42,15 +42,17 @@ FLOPS_ZETA_ROW = 39
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each
-# scaled by the same counter on a copy of known size (profiles/rexi_chain_kernel_T255_N800.md).
+# scaled by the same counter on a copy of known size (the chain-kernel summary under profiles/).
 # Valid only for the kernel source (sha256) and launch shape they were taken with.
 MEASURED_TRAFFIC = {
     # the FP32 solve at T255, N = 800 (the same launch in both workloads: only the
-    # Legendre stage around it differs): 112.2 MB read + 128.8 MB written
-    ("T255-fp32", "069957af133a6802ce52c4f92991c7745c86f833244d2c336adfd766916d124b",
-     (1, 8, 4, 2)): 112.2e6 + 128.8e6,
-    ("T255-fp32-bf16", "069957af133a6802ce52c4f92991c7745c86f833244d2c336adfd766916d124b",
-     (1, 8, 4, 2)): 112.2e6 + 128.8e6,
+    # Legendre stage around it differs): 116.6 MB read + 128.8 MB written
+    ("T255-fp32", "56297a0b9efac0cfa2b8e91182925f4507b60bee36a79f5ebe2e52ae432d9d03",
+     (1, 8, 4, 2)): 116.6e6 + 128.8e6,
+    ("T255-fp32-bf16", "56297a0b9efac0cfa2b8e91182925f4507b60bee36a79f5ebe2e52ae432d9d03",
+     (1, 8, 4, 2)): 116.6e6 + 128.8e6,
+    ("T255-fp32-fp16", "56297a0b9efac0cfa2b8e91182925f4507b60bee36a79f5ebe2e52ae432d9d03",
+     (1, 8, 4, 2)): 116.6e6 + 128.8e6,
 }
 
 

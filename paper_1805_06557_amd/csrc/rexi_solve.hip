@@ -77,10 +77,10 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-// Uniform data of one chain row, in chain order (record 2 base(m) + c Lm + j),
-// rebuilt for every call by rexi_rows_kernel from the state, dt and the
-// per-mode coefficients, so that the solve reads one contiguous record per row
-// (two scalar loads) and does no wave-uniform arithmetic.
+// Uniform data of one chain row, formed for every call from the state, dt and
+// the per-mode coefficients (by the fused solve itself, in LDS, or by
+// rexi_rows_kernel in HBM in chain order, record 2 base(m) + c Lm + j), so that
+// the sweeps read one record per row and do no wave-uniform arithmetic.
 struct RowRec {
     double a, c;       // couplings to rows j-1 and j+1, signed for the row type, times dt
     double dts;        // dt m q_k
