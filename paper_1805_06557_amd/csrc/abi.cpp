@@ -355,13 +355,15 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     ctx->nlat = nlat;
     ctx->nlon = nlon;
     ctx->prec = prec;
-    // measured defaults at T255 / N = 800 (the autotuner refines them per problem):
-    // FP32 two poles per lane, 8-row segments, 4 waves; FP64 one pole, 16 rows, 2 waves
-    const bool fp32 = (prec & REXI_PREC_FP32_SOLVE) != 0;
+    // measured defaults (the autotuner refines them per problem): two poles per
+    // lane, 8-row segments, 4 waves per workgroup in both precisions.  At T511
+    // (512-row chains, N = 2000) the FP64 solve takes 1.98 ms with these against
+    // 3.24 ms with one pole per lane, 16 rows and 2 waves: a long chain's records
+    // leave LDS room for few workgroups per CU, so waves per workgroup count.
     ctx->tune.solver = REXI_SOLVER_FUSED;
-    ctx->tune.poles_per_lane = fp32 ? 2 : 1;
-    ctx->tune.seg_rows = fp32 ? 8 : 16;
-    ctx->tune.waves = fp32 ? 4 : 2;
+    ctx->tune.poles_per_lane = 2;
+    ctx->tune.seg_rows = 8;
+    ctx->tune.waves = 4;
     ctx->a = a;
     ctx->g = g;
     ctx->H = H;
