@@ -309,11 +309,13 @@ __device__ __forceinline__ void forward_rhs(const RecT<T>& R, const Lane& ln, Cx
 }
 
 // Sums the 6 staged slots over the 64 lanes of the wave and writes them.
-// red: [6][64] double2.  Slot s < 4: chain row 4g + s; slots 4, 5: h of the two
-// delta rows of the group.
-template <int C>
-__device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, int lane, int pw, int base,
-                                             int j0g, int Lm) {
+// red: [6][64] double2.  Slot s < 4: chain row 4g + s; slots 4, 5: sum of
+// (w/z) delta of the two delta rows of the group, from which
+// h = sum_n (w_n/z_n) (t - dt H delta_n) = t swz - dt H sum_n (w_n/z_n) delta_n
+// with swz the wave's sum of w/z and t the row's h right-hand side.
+template <typename T, int C>
+__device__ __forceinline__ void reduce_group(const SolveArgs& A, const RecT<T>* rc, double2 swz, double2* red,
+                                             int lane, int pw, int base, int j0g, int Lm) {
     wave_sync();
     const int slot = lane >> 3, part = lane & 7;
     double sx = 0.0, sy = 0.0;
@@ -340,18 +342,27 @@ __device__ __forceinline__ void reduce_group(const SolveArgs& A, double2* red, i
             field = 0;
         }
         const int j = j0g + q;
-        if (j < Lm) A.out[(pw * 3 + field) * A.modes + base + j] = make_double2(sx, sy);
+        if (j < Lm) {
+            if (slot >= 4) {
+                const double tx = static_cast<double>(rc[j].hx), ty = static_cast<double>(rc[j].hy);
+                const double ax = __builtin_fma(tx, swz.x, -(ty * swz.y));
+                const double ay = __builtin_fma(tx, swz.y, ty * swz.x);
+                sx = __builtin_fma(-A.dtH, sx, ax);
+                sy = __builtin_fma(-A.dtH, sy, ay);
+            }
+            A.out[(pw * 3 + field) * A.modes + base + j] = make_double2(sx, sy);
+        }
     }
     wave_sync();
 }
 
-// Back-substitution through one segment whose pivots ps and d' values ds are in
-// registers: x_j = d'_j - c_j p_j x_{j+1}; the weighted outputs of the lane's
-// P poles are added in pole order, then summed over the wave.
+// Back-substitution through one segment whose c'_j = c_j p_j and d'_j values cs
+// and ds are in registers: x_j = d'_j - c'_j x_{j+1}; the weighted outputs of
+// the lane's P poles are added in pole order, then summed over the wave.
 template <typename T, int S, int C, int P>
 __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln, const RecT<T>* rc, int j0, int Lm,
-                                             int base, int pw, int lane, const Cx<T> (*ps)[S],
-                                             const Cx<T> (*ds)[S], Cx<T>* vnext, double2* red) {
+                                             int base, int pw, int lane, const Cx<T> (*cs)[S],
+                                             const Cx<T> (*ds)[S], Cx<T>* vnext, double2 swz, double2* red) {
     static_for<0, S / 4>([&](auto G) {
         constexpr int g = S / 4 - 1 - decltype(G)::value;
         static_for<0, 4>([&](auto Qi) {
@@ -365,10 +376,9 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
             for (int k = 0; k < P; ++k) {
                 Cx<T> v{T(0), T(0)};
                 if (live) {
-                    const T tc = coupling_c<T>(rc[j]);
-                    const Cx<T> cpj{tc * ps[k][jj].x, tc * ps[k][jj].y};
-                    v.x = ds[k][jj].x - fmaT(cpj.x, vnext[k].x, -(cpj.y * vnext[k].y));
-                    v.y = ds[k][jj].y - fmaT(cpj.x, vnext[k].y, cpj.y * vnext[k].x);
+                    const Cx<T> cpj = cs[k][jj];
+                    v.x = fmaT(-cpj.x, vnext[k].x, fmaT(cpj.y, vnext[k].y, ds[k][jj].x));
+                    v.y = fmaT(-cpj.x, vnext[k].y, fmaT(-cpj.y, vnext[k].x, ds[k][jj].y));
                     vnext[k] = v;
                 }
                 const double vx = static_cast<double>(v.x), vy = static_cast<double>(v.y);
@@ -377,20 +387,17 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
                 sx = k ? sx + ox : ox;
                 sy = k ? sy + oy : oy;
                 if constexpr (DELTA) {
-                    if (live) {
-                        const double tx = __builtin_fma(-A.dtH, vx, static_cast<double>(rc[j].hx));
-                        const double ty = __builtin_fma(-A.dtH, vy, static_cast<double>(rc[j].hy));
-                        const double gx = __builtin_fma(ln[k].wzr, tx, -(ln[k].wzi * ty));
-                        const double gy = __builtin_fma(ln[k].wzr, ty, ln[k].wzi * tx);
-                        hx = k ? hx + gx : gx;
-                        hy = k ? hy + gy : gy;
-                    }
+                    // (w/z) delta; v = 0 past the chain's end
+                    const double gx = __builtin_fma(ln[k].wzr, vx, -(ln[k].wzi * vy));
+                    const double gy = __builtin_fma(ln[k].wzr, vy, ln[k].wzi * vx);
+                    hx = k ? hx + gx : gx;
+                    hy = k ? hy + gy : gy;
                 }
             }
             red[q * WAVE + lane] = make_double2(sx, sy);
             if constexpr (DELTA) red[(4 + (q >> 1)) * WAVE + lane] = make_double2(hx, hy);
         });
-        reduce_group<C>(A, red, lane, pw, base, j0 + 4 * g, Lm);
+        reduce_group<T, C>(A, rc, swz, red, lane, pw, base, j0 + 4 * g, Lm);
     });
 }
 
@@ -454,6 +461,20 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
         ln[k].zirf = static_cast<float>(ln[k].p.zir);
         ln[k].ziif = static_cast<float>(ln[k].p.zii);
     }
+    // sum of w/z over the wave's poles (lane-local in pole order, then an xor
+    // butterfly: every lane ends with the same bits, as each step adds the same
+    // two values)
+    double2 swz = make_double2(ln[0].wzr, ln[0].wzi);
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+        swz.x += ln[k].wzr;
+        swz.y += ln[k].wzi;
+    }
+#pragma unroll
+    for (int msk = 1; msk < WAVE; msk <<= 1) {
+        swz.x += __shfl_xor(swz.x, msk);
+        swz.y += __shfl_xor(swz.y, msk);
+    }
 
     double2* red = reinterpret_cast<double2*>(smem + static_cast<size_t>(A.rec_bytes) +
                                               static_cast<size_t>(wv) * sizeof(double2) * 6 * WAVE);
@@ -467,6 +488,8 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     Cx<T> cp[P], dp[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) cp[k] = dp[k] = Cx<T>{T(0), T(0)};
+    // per segment row: the pivot p_j, replaced by c'_j = c_j p_j once the row's
+    // d'_j is formed (the back-substitution needs only c'_j and d'_j)
     Cx<T> ps[P][S], ds[P][S];
     // forward sweep over the full segments, keeping the state entering each later one
     for (int seg = 0; seg < nseg - 1; ++seg) {
@@ -525,16 +548,21 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
             if (j0 + jj < Lm) {
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    if constexpr (SCHED == STREAM)
-                        ps[k][jj] = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
-                    else
-                        ps[k][jj] = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], cp[k]);
-                    forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], dp[k]);
+                    if constexpr (SCHED == STREAM) {
+                        const Cx<T> p = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
+                        forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, dp[k]);
+                        const T tc = coupling_c<T>(rc[j0 + jj]);
+                        ps[k][jj] = Cx<T>{tc * p.x, tc * p.y};
+                    } else {
+                        const Cx<T> p = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], cp[k]);
+                        forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, dp[k]);
+                        ps[k][jj] = cp[k];   // c'_j, formed by pivot_row as c_j p_j
+                    }
                     ds[k][jj] = dp[k];
                 }
             }
         });
-        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, red);
+        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, swz, red);
     }
     // earlier segments: rebuild pivots and d' from the checkpoint, then back-substitute
     for (int seg = nseg - 2; seg >= 0; --seg) {
@@ -562,12 +590,19 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
             constexpr bool DELTA = ((jj + C) & 1) == 0;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                if constexpr (SCHED != STREAM) ps[k][jj] = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], c[k]);
-                forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], d[k]);
+                if constexpr (SCHED == STREAM) {
+                    forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], d[k]);
+                    const T tc = coupling_c<T>(rc[j0 + jj]);
+                    ps[k][jj] = Cx<T>{tc * ps[k][jj].x, tc * ps[k][jj].y};
+                } else {
+                    const Cx<T> p = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], c[k]);
+                    forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, d[k]);
+                    ps[k][jj] = c[k];   // c'_j
+                }
                 ds[k][jj] = d[k];
             }
         });
-        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, red);
+        back_segment<T, S, C, P>(A, ln, rc, j0, Lm, base, pw, lane, ps, ds, vnext, swz, red);
     }
 }
 
