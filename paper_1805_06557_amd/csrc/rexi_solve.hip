@@ -58,6 +58,14 @@ __device__ __forceinline__ double rcp_refined(double n) {
 // carries a relative error of a few u_32, within the FP32 sweep's own rounding.
 __device__ __forceinline__ float rcp_refined(float n) { return __builtin_amdgcn_rcpf(n); }
 
+// Lane 0's value of v, held in scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(u & 0xffffffffu)));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(u >> 32)));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -475,6 +483,7 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
         swz.x += __shfl_xor(swz.x, msk);
         swz.y += __shfl_xor(swz.y, msk);
     }
+    swz = make_double2(wave_uniform(swz.x), wave_uniform(swz.y));   // scalar registers
 
     double2* red = reinterpret_cast<double2*>(smem + static_cast<size_t>(A.rec_bytes) +
                                               static_cast<size_t>(wv) * sizeof(double2) * 6 * WAVE);
