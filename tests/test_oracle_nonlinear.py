@@ -8,7 +8,9 @@
   h = -(a Omega u0 + u0^2 / 2) mu^2 / g + const) is a steady state of the whole
   system: (L + N) U = 0 -- this ties the Coriolis operator, gravity and N together;
 * Heun is second order; Strang version 1 (N^{dt/2} o REXI^{dt} o N^{dt/2}) is second
-  order against a small-step RK4 solution of the whole system.
+  order against a small-step RK4 solution of the whole system;
+* RK4 itself: on a linear right-hand side one step is the degree-4 Taylor
+  polynomial of the exponential.
 """
 import numpy as np
 import pytest
@@ -230,3 +232,29 @@ def test_grid_coriolis_matches_spectral_operator():
     assert np.abs(lc[0]).max() == 0.0
     assert np.abs(lc[1] - (-div_f)).max() <= 1e-12 * scale
     assert np.abs(lc[2] - curl_f).max() <= 1e-12 * scale
+
+
+def test_rk4_on_a_linear_system_is_the_taylor_polynomial(monkeypatch):
+    """For u' = A u one classical RK4 step equals sum_{k <= 4} (h A)^k u / k!
+    (the four order conditions of the method's weights on linear problems);
+    the oracle's RK4 is run with its right-hand side replaced by the linear
+    operator alone, and compared with that polynomial built from repeated
+    operator applications."""
+    L = 8
+    g = _grid(L)
+    U = random_state(L, 21)
+    monkeypatch.setattr(nonlinear, "full_tendency", lambda grid, V: apply(V, grid.L, grid.p))
+    h = 900.0
+    got = nonlinear.rk4(g, U, h, 1)
+    term = U.copy()
+    ref = U.copy()
+    for k in range(1, 5):
+        term = apply(term, L, g.p) * (h / k)
+        ref = ref + term
+    for f in range(3):
+        assert np.abs(got[f] - ref[f]).max() <= 1e-13 * np.abs(ref[f]).max(), f
+    # the fifth Taylor term, which the step must not contain, is far above the
+    # tolerance in every field (a method of higher order would fail the check)
+    fifth = apply(term, L, g.p) * (h / 5)
+    for f in range(3):
+        assert np.abs(fifth[f]).max() > 1e-8 * np.abs(ref[f]).max(), f
