@@ -53,6 +53,12 @@ MEASURED_TRAFFIC = {
      (1, 8, 4, 2)): 117.0e6 + 128.8e6,
     ("T255-fp32-fp16", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
      (1, 8, 4, 2)): 117.0e6 + 128.8e6,
+    # the FP64 solve at T255, N = 800: 222.9 MB read + 235.6 MB written
+    ("T255-fp64", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
+     (1, 8, 4, 2)): 222.9e6 + 235.6e6,
+    # the FP64 solve at T511, N = 2000: 2132.7 MB read + 2253.8 MB written
+    ("T511-fp64", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
+     (1, 8, 4, 2)): 2132.7e6 + 2253.8e6,
 }
 
 
