@@ -141,6 +141,26 @@ int rexi_lg_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, d
                  const double* U0, double* U1, hipStream_t stream);
 
 /*
+ * rexi_lg_step_noalloc -- rexi_lg_step for callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same kernels and the same result bits as
+ * rexi_lg_step; the pole table and the per-degree sums live in a static
+ * device array of the library (229 408 bytes per device, held until the
+ * process ends) instead of context allocations, so the call allocates
+ * nothing on the device.  Limits: N <= 4096 (and L <= 1023, as for every
+ * context).  The array keeps the last call's contents: a call whose
+ * (alpha, beta, N, dt) differ from the previous call's on that device uploads
+ * the new pole table on `stream` and waits for the stream; a call with the
+ * same set only enqueues the two kernels.  Every call on one device shares the
+ * array, so calls that may overlap on one device (several streams or host
+ * threads) race; the caller orders them.
+ * Errors: REXI_EINVAL (as rexi_lg_step, and N > 4096), REXI_ENUMERIC,
+ * REXI_ENOTSUP, REXI_EDEVICE.
+ */
+int rexi_lg_step_noalloc(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                         const double* U0, double* U1, hipStream_t stream);
+
+/*
  * rexi_linear_step_batched -- the REXI linear stage (Section 4.2, Eq. rexi)
  * of an ensemble of independent problems, each with its own context (own
  * truncation), coefficients, pole count and dt, in one row-record launch, one

@@ -27,6 +27,7 @@ SIGNATURES = {
     "swe_destroy": (_c_int, [_vp]),
     "rexi_linear_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "rexi_lg_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
+    "rexi_lg_step_noalloc": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "sh_synthesis": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
     "sh_analysis": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
     "swe_nonlinear_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),

@@ -147,6 +147,14 @@ class SWE:
                                       _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
                                       _stream_handle(stream)), "rexi_lg_step")
 
+    def rexi_lg_step_noalloc(self, alpha, beta, dt: float, U0, U1, stream=None) -> None:
+        """rexi_lg_step without device allocation (scratch in the library's static array)."""
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        _check(self._lib.rexi_lg_step_noalloc(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt),
+                                              _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                              _stream_handle(stream)), "rexi_lg_step_noalloc")
+
     def sh_synthesis(self, spec, grid, nf: int, stream=None) -> None:
         _check(self._lib.sh_synthesis(self._h, _state_ptr(spec, self.L, nf, "spec"),
                                       _grid_ptr(grid, self.nlat, self.nlon, nf, "grid"), nf,

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librexi_swe.so")
 
-SOURCES = ["abi.cpp", "host_numerics.cpp", "tables.cpp", "rexi_solve.hip", "sht.hip", "sht_mfma.hip"]
+SOURCES = ["abi.cpp", "host_numerics.cpp", "tables.cpp", "rexi_solve.hip", "sht.hip", "sht_mfma.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

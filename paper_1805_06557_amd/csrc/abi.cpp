@@ -40,6 +40,42 @@ uint64_t fnv1a(const void* data, size_t bytes, uint64_t h) {
     return h;
 }
 
+}  // namespace
+
+uint64_t pole_key(const double* alpha, const double* beta, int N, double dt) {
+    uint64_t key = 1469598103934665603ULL;
+    key = fnv1a(alpha, sizeof(double) * 2 * static_cast<size_t>(N), key);
+    key = fnv1a(beta, sizeof(double) * 2 * static_cast<size_t>(N), key);
+    key = fnv1a(&N, sizeof(N), key);
+    key = fnv1a(&dt, sizeof(dt), key);
+    return key;
+}
+
+int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, const char* who) {
+    for (int n = 0; n < N; ++n) {
+        const PoleData& q = pd[n];
+        if (!std::isfinite(q.zr) || !std::isfinite(q.zi) || !std::isfinite(q.wr) || !std::isfinite(q.wi))
+            return fail(REXI_EINVAL, std::string(who) + ": non-finite alpha or beta");
+    }
+    const double rho = dt * (std::sqrt(ctx->g * ctx->H * ctx->L * (ctx->L + 1.0)) / ctx->a + 2.0 * ctx->Omega);
+    const double probes[5] = {-rho, -0.5 * rho, 0.0, 0.5 * rho, rho};
+    for (double w : probes) {
+        const int wn = winding_number(pd, N, 0.0, w);
+        if (wn != 1 && wn != -1) {
+            char buf[200];
+            std::snprintf(buf, sizeof buf,
+                          "%s: the poles do not enclose the spectrum of dt L "
+                          "(winding %d around %.6g i; rho = %.6g)", who, wn, w, rho);
+            return fail(REXI_ENUMERIC, buf);
+        }
+    }
+    if (!(min_distance_to_segment(pd, N, rho) > 1e-6 * (1.0 + rho)))
+        return fail(REXI_ENUMERIC, std::string(who) + ": a pole lies on the spectrum of dt L");
+    return REXI_OK;
+}
+
+namespace {
+
 // RAII guard that makes the context's device current for the duration of a call.
 struct DeviceGuard {
     int prev = -1;
@@ -101,37 +137,15 @@ PoleSet* pole_slot(swe_ctx* ctx, uint64_t key, int N, bool& hit) {
 // poles enclose the spectrum of dt L.
 int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
                   hipStream_t stream) {
-    uint64_t key = 1469598103934665603ULL;
-    key = fnv1a(alpha, sizeof(double) * 2 * N, key);
-    key = fnv1a(beta, sizeof(double) * 2 * N, key);
-    key = fnv1a(&N, sizeof(N), key);
-    key = fnv1a(&dt, sizeof(dt), key);
+    const uint64_t key = pole_key(alpha, beta, N, dt);
     bool hit = false;
     PoleSet* slot = pole_slot(ctx, key, N, hit);
     if (hit) return REXI_OK;
 
     std::vector<PoleData> pd(N);
     build_pole_data(alpha, beta, N, pd.data());
-    for (int n = 0; n < N; ++n) {
-        const PoleData& q = pd[n];
-        if (!std::isfinite(q.zr) || !std::isfinite(q.zi) || !std::isfinite(q.wr) || !std::isfinite(q.wi))
-            return fail(REXI_EINVAL, "rexi_linear_step: non-finite alpha or beta");
-    }
-    const double rho = dt * (std::sqrt(ctx->g * ctx->H * ctx->L * (ctx->L + 1.0)) / ctx->a + 2.0 * ctx->Omega);
-    const double probes[5] = {-rho, -0.5 * rho, 0.0, 0.5 * rho, rho};
-    for (double w : probes) {
-        const int wn = winding_number(pd.data(), N, 0.0, w);
-        if (wn != 1 && wn != -1) {
-            char buf[200];
-            std::snprintf(buf, sizeof buf,
-                          "rexi_linear_step: the poles do not enclose the spectrum of dt L "
-                          "(winding %d around %.6g i; rho = %.6g)", wn, w, rho);
-            return fail(REXI_ENUMERIC, buf);
-        }
-    }
-    if (!(min_distance_to_segment(pd.data(), N, rho) > 1e-6 * (1.0 + rho)))
-        return fail(REXI_ENUMERIC, "rexi_linear_step: a pole lies on the spectrum of dt L");
-
+    const int rc = check_poles(ctx, pd.data(), N, dt, "rexi_linear_step");
+    if (rc != REXI_OK) return rc;
     return activate_poles(ctx, slot, pd.data(), N, key, stream);
 }
 
@@ -374,6 +388,9 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
         delete ctx;
         return hip_fail(e, "swe_create: hipGetDevice");
     }
+    // the allocation-free entry point's scratch address on this device (a failure
+    // here only disables that entry point, which retries and reports it)
+    (void)noalloc_init_device(ctx->device);
     std::vector<ModeCoef> coef(ctx->modes);
     build_mode_coef(L, a, g, Omega, coef.data());
     e = hipMalloc(&ctx->d_coef, sizeof(ModeCoef) * ctx->modes);

@@ -245,6 +245,21 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
 // l a 2x2 system in (h, delta), zeta multiplied by S(0); the sums over poles are
 // formed once per degree.
 int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream);
+// The same two launches on caller-provided buffers: poles [N] and the per-degree
+// sums [L+2][2] complex (lg_sums_bytes(L) bytes); no allocation, no profiling.
+inline size_t lg_sums_bytes(int L) { return sizeof(double) * 4 * static_cast<size_t>(L + 2); }
+int launch_rexi_lg_on(swe_ctx* ctx, const PoleData* poles, void* sums, int N, double dt, const double* U0,
+                      double* U1, hipStream_t stream);
+// Host checks of a coefficient set before any launch: finite values, the
+// poles wind once around the spectrum segment i[-rho, rho] of dt L and keep a
+// distance from it.  `who` names the entry point in the error text.
+int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, const char* who);
+// Cache key of a coefficient set (alpha, beta: 2N doubles each) and dt.
+uint64_t pole_key(const double* alpha, const double* beta, int N, double dt);
+// Allocation-free entry point support: resolves the device address of the
+// library's static scratch array on `device` (once per device; call with the
+// device current).
+int noalloc_init_device(int device);
 // out = x + a y over n doubles (out may equal x or y).
 int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
 // Radix sequence of the longitude FFT of M = nlon/2 complex points.

@@ -1141,22 +1141,28 @@ __global__ __launch_bounds__(256) void lg_apply_kernel(const double2* U0, double
 
 }  // namespace
 
-int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
-    if (!ctx->d_lgsum) {
-        if (hipMalloc(&ctx->d_lgsum, sizeof(double2) * 2 * static_cast<size_t>(ctx->L + 2)) != hipSuccess)
-            return fail(REXI_ENOMEM, "rexi_lg_step: cannot allocate the per-degree sums");
-    }
+int launch_rexi_lg_on(swe_ctx* ctx, const PoleData* poles, void* sums, int N, double dt, const double* U0,
+                      double* U1, hipStream_t stream) {
     const double c1 = dt * dt * ctx->H * ctx->g / (ctx->a * ctx->a);
-    const int slot = prof_begin(ctx, REXI_KERNEL_SOLVE, stream);
-    hipLaunchKernelGGL(lg_sums_kernel, dim3(ctx->L + 2), dim3(256), 0, stream, ctx->d_poles, N, ctx->L, c1,
-                       reinterpret_cast<double2*>(ctx->d_lgsum));
+    hipLaunchKernelGGL(lg_sums_kernel, dim3(ctx->L + 2), dim3(256), 0, stream, poles, N, ctx->L, c1,
+                       reinterpret_cast<double2*>(sums));
     REXI_HIP(hipGetLastError());
     hipLaunchKernelGGL(lg_apply_kernel, dim3(ctx->L + 1), dim3(256), 0, stream, reinterpret_cast<const double2*>(U0),
-                       reinterpret_cast<double2*>(U1), reinterpret_cast<const double2*>(ctx->d_lgsum), ctx->L,
+                       reinterpret_cast<double2*>(U1), reinterpret_cast<const double2*>(sums), ctx->L,
                        ctx->modes, dt * ctx->H, dt * ctx->g / (ctx->a * ctx->a));
     REXI_HIP(hipGetLastError());
-    prof_end(ctx, REXI_KERNEL_SOLVE, slot, stream);
     return REXI_OK;
+}
+
+int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    if (!ctx->d_lgsum) {
+        if (hipMalloc(&ctx->d_lgsum, lg_sums_bytes(ctx->L)) != hipSuccess)
+            return fail(REXI_ENOMEM, "rexi_lg_step: cannot allocate the per-degree sums");
+    }
+    const int slot = prof_begin(ctx, REXI_KERNEL_SOLVE, stream);
+    const int rc = launch_rexi_lg_on(ctx, ctx->d_poles, ctx->d_lgsum, N, dt, U0, U1, stream);
+    prof_end(ctx, REXI_KERNEL_SOLVE, slot, stream);
+    return rc;
 }
 
 int launch_rexi_batched(const BatchMember* mem, int count, hipStream_t stream) {
