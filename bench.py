@@ -12,7 +12,10 @@ FP64 beta sum.  Prints one JSON line (rank 0):
   roofline     achieved rate of the dominant kernel (the banded chain solve)
                against the chip's vector ALU peak, from HIP events recorded
                around every launch of that kernel in the timed region
-  cpu_baseline the FP64 oracle on a bounded sample of the same workload
+  cpu_baseline the FP64 oracle (plain CPU implementation) on the same step,
+               timed on the host's cores (the whole step at T255; a sample of
+               the REXI stage's orders where the whole step would take minutes);
+               its result is also the reference of step_error_vs_oracle
 """
 from __future__ import annotations
 
@@ -25,49 +28,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_VALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-PEAK_FP32_VALU = 78.6      # TFLOP/s: the same for unpacked FP32, the form this library is built for
+PEAK_FP64_VALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_VALU = 78.6      # TFLOP/s: the same count for FP32 without packed (2-per-lane) instructions, which this
+                           # library does not use
 PEAK_FP32_PACKED = 157.3   # TFLOP/s: published FP32 vector peak (packed FP32, 2 per lane), reported alongside
 PEAK_HBM = 8000.0          # GB/s
 
-# Algorithmic flops of the fused chain solve per (pole, chain row), counting a
-# real add/sub/mul as 1, an FMA as 2 and the reciprocal as 1:
-#   delta row: diagonal 5, right-hand side 10, pivot 4 + |w|^2 3 + 1/|w|^2 1 +
-#              conj/scale 2, c' 2, d' 4 + 6, back-substitution 8, weighted
-#              output 6 + sum 2, h recovery 4 + 6 + sum 2          = 65
-#   zeta row:  diagonal 1, pivot 4 + 3 + 1 + 2, c' 2, d' 10, back 8,
-#              weighted output 6 + sum 2                            = 39
-FLOPS_DELTA_ROW = 65
-FLOPS_ZETA_ROW = 39
+# Algorithmic work of the banded REXI solve per pole-unknown (one pole applied to
+# one chain unknown; two chain unknowns (delta, zeta) per mode, h eliminated),
+# the fixed count of the hot-path scope table, independent of the kernel's
+# instruction mix: diagonal 4, right-hand-side modification 10 (delta rows),
+# forward Thomas step ~19, back substitution 8, h recovery 10 (delta rows),
+# beta-weighted accumulation 8-16: about 60 flops.
+FLOPS_PER_POLE_UNKNOWN = 60
+# Bytes per pole-unknown of the factor-streaming schedule: the cached pivot
+# (complex FP32 / FP64) read by the forward sweep and again by the backward pass.
+STREAM_BYTES_PER_POLE_UNKNOWN = {True: 16, False: 32}
 
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each
 # scaled by the same counter on a copy of known size (the chain-kernel summary under profiles/).
 # Valid only for the kernel source (sha256) and launch shape they were taken with.
 MEASURED_TRAFFIC = {
-    # the FP32 solve at T255, N = 800 (the same launch in both workloads: only the
-    # Legendre stage around it differs): 117.0 MB read + 128.8 MB written
-    ("T255-fp32", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
-     (1, 8, 4, 2)): 117.0e6 + 128.8e6,
-    ("T255-fp32-bf16", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
-     (1, 8, 4, 2)): 117.0e6 + 128.8e6,
-    ("T255-fp32-fp16", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
-     (1, 8, 4, 2)): 117.0e6 + 128.8e6,
-    # the FP64 solve at T255, N = 800: 222.9 MB read + 235.6 MB written
-    ("T255-fp64", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
-     (1, 8, 4, 2)): 222.9e6 + 235.6e6,
-    # the FP64 solve at T511, N = 2000: 2132.7 MB read + 2253.8 MB written
-    ("T511-fp64", "7d11c9ecb1eccbfadd13441cf2f54d702755584f8517b3a876051d769879903c",
-     (1, 8, 4, 2)): 2132.7e6 + 2253.8e6,
 }
 
 
-def measured_traffic(workload, tuning):
+def kernel_source_digest():
     import hashlib
     src = os.path.join(ROOT, "paper_1805_06557_amd", "csrc", "rexi_solve.hip")
     with open(src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    key = (workload, digest, (tuning["solver"], tuning["seg_rows"], tuning["waves"], tuning["poles_per_lane"]))
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(workload, tuning):
+    key = (workload, kernel_source_digest(),
+           (tuning["solver"], tuning["seg_rows"], tuning["waves"], tuning["poles_per_lane"]))
     return MEASURED_TRAFFIC.get(key)
 
 
@@ -75,81 +70,112 @@ def n_modes(L):
     return (L + 1) * (L + 2) // 2
 
 
-def solve_flops(L, N):
+def pole_unknowns(L, N):
     # every (l, m) appears once as a delta row and once as a zeta row
-    return N * n_modes(L) * (FLOPS_DELTA_ROW + FLOPS_ZETA_ROW)
+    return 2 * N * n_modes(L)
 
 
-def cpu_baseline(w, seconds: float, full: bool):
-    """Time the oracle on a bounded sample of the workload.
+def solve_flops(L, N):
+    return FLOPS_PER_POLE_UNKNOWN * pole_unknowns(L, N)
 
-    REXI stage: the oracle's banded solves on a sample of zonal orders (taken
-    from the short end of the chain-length range), run over a process pool and
-    scaled by the fraction of pole-rows covered.  Non-linear stage (full steps
-    only): two Heun steps of the oracle timed whole, in-process."""
+
+def _blas_threads():
+    """BLAS thread counts numpy would use in this process (threadpoolctl)."""
+    try:
+        from threadpoolctl import threadpool_info
+        return sorted({int(i.get("num_threads", 0)) for i in threadpool_info() if i.get("user_api") == "blas"})
+    except Exception:                                   # noqa: BLE001 - report only
+        return None
+
+
+def _oracle_rexi_orders(args):
+    """Worker: the oracle's REXI stage on a list of zonal orders, one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        from oracle import linear
+        from oracle.operator import Params
+        U0, alpha, beta, dt, L, orders = args
+        return linear.rexi_linear_step(U0, alpha, beta, dt, L, Params(), orders=orders)
+
+
+def oracle_rexi(U0, alpha, beta, dt, L, orders=None, cores=None):
+    """The oracle's REXI stage over a process pool (orders dealt round-robin, the
+    longest chains first); returns (U1, seconds, processes)."""
     import concurrent.futures as cf
+    cores = cores or len(os.sched_getaffinity(0))
+    orders = list(range(L, -1, -1)) if orders is None else list(orders)
+    chunks = [c for c in (orders[i::cores] for i in range(cores)) if c]
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=len(chunks)) as ex:
+        parts = list(ex.map(_oracle_rexi_orders, [(U0, alpha, beta, dt, L, c) for c in chunks]))
+    return sum(parts), time.perf_counter() - t0, len(chunks)
 
+
+def oracle_step(w, U0, full_step: bool, seconds: float):
+    """The oracle (plain FP64 CPU implementation) on this workload, timed on the
+    host: the whole l_rexi_n_erk_ver1 step (Heun half step in-process with numpy's
+    BLAS threads, the REXI stage over a process pool with one BLAS thread per
+    process, Heun half step) when all orders fit the time budget, else the two
+    Heun half steps whole and the REXI stage on a sample of orders from the short
+    end of the chain-length range, scaled by the fraction of pole-rows covered.
+    Returns (the oracle's result or None when sampled, cpu_baseline dict)."""
     from oracle import rexi
-    from paper_1805_06557_amd.inputs import jet_state
-
+    cores = len(os.sched_getaffinity(0))
     alpha, beta, _, _ = rexi.coefficients(rexi.FN_EXP, w.N, w.p0, w.y)
-    U0 = jet_state(w.L, w.seed)
-    cores = min(len(os.sched_getaffinity(0)), 16)
-    t_nl = 0.0
-    if full:
+    t_nl, A, g = 0.0, U0, None
+    if full_step:
         from oracle import nonlinear
         from oracle.operator import Params
         from oracle.sht import Grid
         g = Grid(w.L, w.nlat, w.nlon, Params())
         nonlinear.tendency(g, U0)                 # builds the Legendre tables (not timed)
         t0 = time.perf_counter()
-        U = nonlinear.heun(g, U0, 0.5 * w.dt)
-        nonlinear.heun(g, U, 0.5 * w.dt)
+        A = nonlinear.heun(g, U0, 0.5 * w.dt)
         t_nl = time.perf_counter() - t0
-    # calibrate on one middle order, model the cost of order m as ~ (L - m + 1)^2
-    # (the oracle assembles dense matrices), take orders from the short end
+    # full REXI stage if a calibrated estimate fits the budget (order m costs ~ (L - m + 1)^2)
     mc = w.L // 2
     t0 = time.perf_counter()
-    _oracle_chunk((U0, alpha, beta, w.dt, w.L, [mc]))
+    _oracle_rexi_orders((A, alpha, beta, w.dt, w.L, [mc]))
     tc = time.perf_counter() - t0
-    orders, est = [], 0.0
-    for m in range(w.L, -1, -1):
-        if m == mc:
-            continue
-        est += tc * ((w.L - m + 1) / (w.L - mc + 1)) ** 2
-        orders.append(m)
-        if est > seconds * cores:
-            break
-    t0 = time.perf_counter()
-    chunks = [orders[i::cores] for i in range(cores)]
-    with cf.ProcessPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(_oracle_chunk, [(U0, alpha, beta, w.dt, w.L, c) for c in chunks if c]))
-    elapsed = time.perf_counter() - t0
-    rows = sum(w.L - m + 1 for m in orders)
-    frac = rows / n_modes(w.L)
-    t_rexi = elapsed / frac
-    sample = (f"REXI stage: zonal orders {min(orders)}..{max(orders)} ({len(orders)} of {w.L + 1}, "
-              f"{100 * frac:.1f}% of the pole-rows) in {elapsed:.1f} s over {cores} processes, "
-              f"scaled to {t_rexi:.1f} s per stage")
-    if full:
-        sample += f"; non-linear stage: two oracle Heun steps timed whole, {t_nl:.2f} s"
-    return {
-        "value": w.N / (t_rexi + t_nl),
+    cost = [tc * ((w.L - m + 1) / (w.L - mc + 1)) ** 2 for m in range(w.L + 1)]
+    if sum(cost) <= seconds * cores:
+        R, t_rexi, procs = oracle_rexi(A, alpha, beta, w.dt, w.L, cores=cores)
+        ref = R
+        if full_step:
+            t0 = time.perf_counter()
+            ref = nonlinear.heun(g, R, 0.5 * w.dt)
+            t_nl += time.perf_counter() - t0
+        what = ("the whole step: two Heun half steps in-process" if full_step else "the whole REXI stage") + \
+               f" ({t_nl:.2f} s) and the REXI stage over all {w.L + 1} orders ({t_rexi:.1f} s on {procs} processes)"
+        t_total = t_rexi + t_nl
+    else:
+        orders, est = [], 0.0
+        for m in range(w.L, -1, -1):
+            est += cost[m]
+            orders.append(m)
+            if est > seconds * cores:
+                break
+        _, elapsed, procs = oracle_rexi(A, alpha, beta, w.dt, w.L, orders=orders, cores=cores)
+        frac = sum(w.L - m + 1 for m in orders) / n_modes(w.L)
+        t_rexi = elapsed / frac
+        if full_step:
+            from oracle import nonlinear
+            t0 = time.perf_counter()
+            nonlinear.heun(g, A, 0.5 * w.dt)
+            t_nl += time.perf_counter() - t0
+        what = (f"REXI stage on zonal orders {min(orders)}..{max(orders)} ({len(orders)} of {w.L + 1}, "
+                f"{100 * frac:.1f}% of the pole-rows) in {elapsed:.1f} s over {procs} processes, scaled to "
+                f"{t_rexi:.1f} s per stage") + (f"; two Heun half steps timed whole, {t_nl:.2f} s" if full_step else "")
+        t_total = t_rexi + t_nl
+        ref = None
+    return ref, {
+        "value": w.N / t_total,
         "unit": "term-solves/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": sample,
+        "sample": what + f"; {t_total:.1f} s per step; BLAS threads in-process {_blas_threads()}, "
+                         "1 per pool process",
     }
-
-
-def _oracle_chunk(args):
-    import os as _os
-    _os.environ.setdefault("OMP_NUM_THREADS", "1")
-    from oracle import linear
-    from oracle.operator import Params
-    U0, alpha, beta, dt, L, orders = args
-    linear.rexi_linear_step(U0, alpha, beta, dt, L, Params(), orders=orders)
-    return len(orders)
 
 
 PEAK_BF16_MFMA = 2500.0    # TFLOP/s, dense bf16 matrix cores
@@ -177,26 +203,20 @@ def split_table_bytes(L, nlat):
     return rows * hpad * 2 * 2
 
 
-def step_error_vs_fp64(ctx, w, alpha, beta):
-    """Per-field error of one step of this workload against the same step in FP64
-    (FP64 solves and transforms; that path matches the FP64 oracle to 1e-12)."""
+def step_error_vs_oracle(ctx, w, alpha, beta, U0, ref, full):
+    """Per-field L-inf and L2 error of one step of this workload (the timed
+    path, from the workload's initial state) against the oracle's step."""
     import torch
-
-    from paper_1805_06557_amd import api
-    from paper_1805_06557_amd.inputs import jet_state
-
-    U0 = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
-    got = torch.empty_like(U0)
-    ctx.strang_step(alpha, beta, w.dt, U0, got)
-    ref_ctx = api.SWE(w.L, w.nlat, w.nlon, prec=0)
-    ref = torch.empty_like(U0)
-    ref_ctx.strang_step(alpha, beta, w.dt, U0, ref)
-    g, r = got.cpu().numpy(), ref.cpu().numpy()
-    ref_ctx.close()
-    out = {"state": _field_errors(g, r)}
-    u0 = U0.cpu().numpy()
-    out["increment"] = _field_errors(g - u0, r - u0)
-    return out
+    d0 = torch.from_numpy(U0).cuda()
+    got = torch.empty_like(d0)
+    if full:
+        ctx.strang_step(alpha, beta, w.dt, d0, got)
+    else:
+        ctx.rexi_linear_step(alpha, beta, w.dt, d0, got)
+    ctx.sync()
+    g = got.cpu().numpy()
+    return {"state": _field_errors(g, ref), "increment": _field_errors(g - U0, ref - U0),
+            "reference": "oracle (FP64 CPU), same initial state and contour"}
 
 
 def _timed(fn, reps, stream):
@@ -219,11 +239,12 @@ def _field_errors(got, ref):
     return {"linf_rel": dict(zip(("h", "zeta", "delta"), linf)), "l2_rel": dict(zip(("h", "zeta", "delta"), l2))}
 
 
-def equal_error_arm(reps):
+def equal_error_arm(reps, with_oracle=True):
     """FP32 against FP64 REXI stages at T255 (dt = 3600 s), each with the contour
     that meets the same target scalar error E with the fewest poles, timed on the
-    same jet state; the error of each is measured per field against the FP64
-    stage with a much tighter contour (N = 800, p0 = 12, predicted error 1.3e-11)."""
+    same jet state; the error of each is measured per field against the oracle's
+    REXI stage with a much tighter contour (N = 800, p0 = 12, predicted error
+    1.3e-11), run over a process pool on the host."""
     import torch
 
     from paper_1805_06557_amd import api, configs
@@ -231,14 +252,22 @@ def equal_error_arm(reps):
 
     stream = torch.cuda.current_stream()
     ref_w = configs.T255_FP64
-    U0 = torch.from_numpy(jet_state(255, ref_w.seed)).cuda()
-    cref = api.SWE(255, prec=0)
-    a, b, _, _ = api.rexi_coefficients(api.FN_EXP, ref_w.N, ref_w.p0, ref_w.y)
-    Uref = torch.empty_like(U0)
-    cref.rexi_linear_step(a, b, ref_w.dt, U0, Uref, stream)
-    ref = Uref.cpu().numpy()
-    cref.close()
-    out = {"E": configs.EQUAL_ERROR_E, "reference": "FP64 stage, N=800, p0=12"}
+    u0 = jet_state(255, ref_w.seed)
+    U0 = torch.from_numpy(u0).cuda()
+    if with_oracle:
+        from oracle import rexi
+        a, b, _, _ = rexi.coefficients(rexi.FN_EXP, ref_w.N, ref_w.p0, ref_w.y)
+        ref, t_ref, procs = oracle_rexi(u0, a, b, ref_w.dt, ref_w.L)
+        out = {"E": configs.EQUAL_ERROR_E,
+               "reference": f"oracle REXI stage, N=800, p0=12 ({t_ref:.1f} s on {procs} host processes)"}
+    else:
+        cref = api.SWE(255, prec=0)
+        a, b, _, _ = api.rexi_coefficients(api.FN_EXP, ref_w.N, ref_w.p0, ref_w.y)
+        Uref = torch.empty_like(U0)
+        cref.rexi_linear_step(a, b, ref_w.dt, U0, Uref, stream)
+        ref = Uref.cpu().numpy()
+        cref.close()
+        out = {"E": configs.EQUAL_ERROR_E, "reference": "FP64 GPU stage, N=800, p0=12"}
     for key, w in (("fp32", configs.T255_FP32_AT_E), ("fp64", configs.T255_FP64_AT_E)):
         ctx = api.SWE(w.L, prec=w.prec)
         a, b, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
@@ -356,6 +385,8 @@ def ensemble_arm(reps):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         api.rexi_linear_step_batched(members, stream=stream)
+        stream.synchronize()
+        fused = [m[5].clone() for m in members]
         eager = _timed(lambda: api.rexi_linear_step_batched(members, stream=stream), reps, stream)
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
@@ -366,13 +397,55 @@ def ensemble_arm(reps):
             for ctx, a, b, dt, U0, U1 in members:
                 ctx.rexi_linear_step(a, b, dt, U0, U1, stream)
         separate()
+        stream.synchronize()
+        same = all(bool(torch.equal(f, m[5])) for f, m in zip(fused, members))
         sep = _timed(separate, reps, stream)
     total_n = sum(m["N"] for m in plan)
     for m in members:
         m[0].close()
     return {"members": len(plan), "truncations": sorted({m["L"] for m in plan}), "total_poles": total_n,
             "ms_fused_eager": eager, "ms_fused_graph": graph, "ms_one_launch_per_member": sep,
+            "every_member_bit_identical_to_its_single_call": same,
             "term_solves_per_s_graph": total_n / (graph * 1e-3)}
+
+
+def stream_arm(w, reps):
+    """The factor-streaming schedule of the REXI solve (pivots cached per contour
+    and dt, read by both sweeps) on this workload's REXI problem, FP32 and FP64
+    solves: HIP events around every solve launch; algorithmic bytes 16 B (FP32)
+    or 32 B (FP64) per pole-unknown against the 8 TB/s HBM peak, with the
+    counter-measured traffic where the profiles hold it for this kernel source."""
+    import torch
+
+    from paper_1805_06557_amd import api
+    from paper_1805_06557_amd.inputs import jet_state
+
+    a, b, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
+    U0 = torch.from_numpy(jet_state(w.L, w.seed)).cuda()
+    U1 = torch.empty_like(U0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for key, prec in (("fp32", api.PREC_FP32_SOLVE), ("fp64", 0)):
+        ctx = api.SWE(w.L, prec=prec)
+        ctx.set_tuning(solver=api.SOLVER_STREAM)
+        ctx.rexi_linear_step(a, b, w.dt, U0, U1, stream)            # builds the cached pivots
+        ctx.sync()
+        ctx.profile_kernels([api.KERNEL_SOLVE])
+        for _ in range(reps):
+            ctx.rexi_linear_step(a, b, w.dt, U0, U1, stream)
+        ms, n = ctx.profile_read(api.KERNEL_SOLVE)
+        ctx.sync()
+        tuning = ctx.get_tuning()
+        ctx.close()
+        per = ms / max(n, 1)
+        nbytes = STREAM_BYTES_PER_POLE_UNKNOWN[key == "fp32"] * pole_unknowns(w.L, w.N)
+        gbs = nbytes / (per * 1e-3) / 1e9
+        out[key] = {"bound": "hbm", "kernel": "rexi_chain_kernel (streaming schedule)", "achieved": gbs,
+                    "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs / PEAK_HBM,
+                    "traffic": measured_traffic(f"{w.name}-stream-{key}", tuning),
+                    "algorithmic_bytes_per_launch": nbytes, "avg_kernel_ms": per, "launches": n,
+                    "tuning": tuning}
+    return out
 
 
 def main():
@@ -382,7 +455,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="T255-fp32-bf16")
     ap.add_argument("--stage", choices=["auto", "rexi"], default="auto")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solver", choices=["default", "fused", "stream", "hybrid"], default="default",
                     help="REXI chain-solve schedule")
@@ -483,8 +556,10 @@ def main():
                           "ms_per_launch": ms / max(n, 1)}
     solve_ms, solve_n = solve_ms_timed, solve_n_timed
     ctx.profile(False)
-    if not torch.isfinite(torch.view_as_real(U)).all():
-        print("bench.py: non-finite state after the timed steps", file=sys.stderr)
+    try:
+        ctx.sync()                     # the library's device-side status: non-finite outputs
+    except api.RexiError as e:
+        print(f"bench.py: {e}", file=sys.stderr)
         sys.exit(3)
 
     ms_per_step = ms_total / args.steps
@@ -530,15 +605,22 @@ def main():
             "avg_kernel_ms": avg_solve_ms,
             "launches": solve_n,
             "algorithmic_flops_per_launch": solve_flops(w.L, w.N),
-            "peak_note": "unpacked vector ALU peak (the published 157.3 TFLOP/s FP32 figure needs packed FP32)",
-            "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED if fp32 else None,
+            "flops_per_pole_unknown": FLOPS_PER_POLE_UNKNOWN,
+            "pole_unknowns_per_launch": pole_unknowns(w.L, w.N),
+            "peak_note": "vector ALU peak without packed FP32: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz",
+            "frac_of_published_fp32_peak": achieved / PEAK_FP32_PACKED if fp32 else None,
+            "published_fp32_peak": PEAK_FP32_PACKED if fp32 else None,
             "tuning": tuning,
         },
         "kernels": stage_ms,
         "setup": {"rexi_factor_kernel_ms": fact_ms / max(fact_n, 1), "launches": fact_n},
     }
-    if full and w.prec:
-        out["step_error_vs_fp64_path"] = step_error_vs_fp64(ctx, w, alpha, beta)
+    oracle_ref = None
+    if not args.no_cpu_baseline:
+        u0 = jet_state(w.L, w.seed)
+        oracle_ref, out["cpu_baseline"] = oracle_step(w, u0, full, args.cpu_seconds)
+        if oracle_ref is not None:
+            out["step_error_vs_oracle"] = step_error_vs_oracle(ctx, w, alpha, beta, u0, oracle_ref, full)
     if full and (w.prec & (api.PREC_BF16_SPLIT | api.PREC_FP16_SPLIT)):
         syn = stage_ms["legendre_synth_kernel"]["ms_per_launch"]
         ana = stage_ms["legendre_anal_kernel"]["ms_per_launch"]
@@ -557,11 +639,14 @@ def main():
     out["graph"] = graph_steps(ctx, full, alpha, beta, w, U, V, args.steps)
     ctx.close()
     if not args.no_arms:
-        out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2))
+        out["roofline_stream"] = stream_arm(w, max(3, args.steps // 2))
+        out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2),
+                                                             with_oracle=not args.no_cpu_baseline)
         out["ensemble"] = ensemble_arm(max(3, args.steps // 2))
         out["schemes"] = schemes_arm(max(3, args.steps // 4))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, full)
+    # the cpu_baseline dict goes last in the line
+    if "cpu_baseline" in out:
+        out["cpu_baseline"] = out.pop("cpu_baseline")
     print(json.dumps(out))
 
 

@@ -51,14 +51,21 @@ enum {
 enum { REXI_FN_EXP = 0, REXI_FN_PSI1 = 1, REXI_FN_PSI2 = 2 };
 
 /* Precision modes of a context (bit flags; 0 = everything in FP64).
- * REXI_PREC_FP32_SOLVE: the banded REXI solves run in complex FP32; the row
- *   data are formed in FP64 and rounded once, the beta-weighted sum
- *   accumulates in FP64.
+ * REXI_PREC_FP32_SOLVE: the banded REXI solves run in complex FP32.  The
+ *   pole-independent row data (couplings, dt terms, right-hand sides) are
+ *   formed in FP64 and rounded once to FP32; the pole-dependent diagonal
+ *   z + dt^2 g H l(l+1)/(a^2 z) - i dt m q_l and right-hand-side term t/z are
+ *   formed in FP32 from z and 1/z rounded to FP32, and the pivot reciprocal is
+ *   the hardware's FP32 reciprocal without refinement (a backward error of a
+ *   few FP32 units relative to the diagonal, the size the FP32 sweep makes
+ *   anyway).  Solutions are widened to FP64 for the beta-weighted sum, which
+ *   accumulates in FP64 (Section 4.2.2: the sum cancels; its terms are up to
+ *   kappa = sum |beta_n| / |x + alpha_n| times larger than the result).
  * REXI_PREC_BF16_SPLIT, REXI_PREC_FP16_SPLIT (exclusive): the Legendre
  *   contractions of the transforms (Section 3.2) run on the matrix cores with
  *   every operand split into two 16-bit values (hi + lo) and three products
  *   accumulated in FP32: relative error per product about 2^-16 (BF16) or
- *   2^-21 (FP16; data columns scaled by exact powers of two into FP16's
+ *   2^-22 (FP16; data columns scaled by exact powers of two into FP16's
  *   range), plus FP32 accumulation over the latitudes or degrees.  FFTs,
  *   products and the time stepping stay FP64. */
 enum {
@@ -90,6 +97,67 @@ int rexi_coefficients(int fn, int N, double p0, double y,
                       double* alpha, double* beta, double* r, double* mu);
 
 /*
+ * rexi_check_contour -- the host checks that rexi_linear_step applies to a
+ * coefficient set before it enqueues anything, without a context or device:
+ * alpha, beta finite; the polygon of the poles z_n = -alpha_n winds once
+ * around the segment i[-rho, rho], rho = dt (sqrt(g H L(L+1))/a + 2 Omega),
+ * which holds the spectrum of dt L (Section 4.2.1: the contour must enclose
+ * the spectrum); and every row of every chain system of the banded solve
+ * (z_n I - dt L_m with h eliminated) is strictly diagonally dominant, the
+ * condition under which its unpivoted elimination is stable.  Per degree l
+ * the orders m <= l shift the diagonal by dt m q_l, q_l = 2 Omega/(l(l+1)),
+ * within i[0, dt 2 Omega/(l+1)]: the zeta-row diagonal z - i dt m q_l is at
+ * least the distance of z from that segment and the delta-row diagonal
+ * z + dt^2 g H l(l+1)/(a^2 z) - i dt m q_l at least the distance of
+ * z + dt^2 g H l(l+1)/(a^2 z) from it, while the row's off-diagonals (the
+ * Coriolis couplings to degrees l -+ 1) sum to at most dt max_m (|c^-| + |c^+|).
+ * margin (may be NULL) receives the smallest ratio of the two over poles and
+ * degrees (> 1 passes).  alpha, beta: host arrays of 2N doubles.
+ * Host only.
+ * Errors: REXI_EINVAL (bad sizes or constants, NULL arrays, non-finite
+ * coefficients), REXI_ENUMERIC (a check fails; *margin is still written when
+ * the winding check passed).
+ */
+int rexi_check_contour(int L, double a, double g, double H, double Omega, double dt,
+                       const double* alpha, const double* beta, int N, double* margin);
+
+/*
+ * rexi_spectral_radius -- rho = dt (sqrt(g H L(L+1))/a + 2 Omega), a bound on
+ * |lambda| over the spectrum of dt L (L = L_g + L_c; gravity-wave frequencies
+ * plus the Coriolis term).  Host only.  Errors: REXI_EINVAL.
+ */
+int rexi_spectral_radius(int L, double dt, double a, double g, double H, double Omega, double* rho);
+
+/*
+ * rexi_contour_error -- the accuracy of a coefficient set (alpha, beta: host,
+ * 2N doubles) on the spectrum segment i[-rho, rho] (Section 4.2.2):
+ *   *approx = max_w |S(i w) - e^{i w}|,  *kappa = max_w sum_n |beta_n| / |i w + alpha_n|,
+ * over npts (>= 2) equally spaced w in [-rho, rho], S(x) = sum_n beta_n / (x + alpha_n)
+ * summed in FP64 in pole order.  kappa is the cancellation factor of the sum:
+ * a solve with unit roundoff u carries an error of about u kappa.  Host only.
+ * Errors: REXI_EINVAL.
+ */
+int rexi_contour_error(const double* alpha, const double* beta, int N, double rho, int npts,
+                       double* approx, double* kappa);
+
+/*
+ * rexi_choose_contour -- a contour for a target accuracy on i[-rho, rho]
+ * (the contour must enclose the spectrum, Section 4.2.1; the shift trades the
+ * trapezoidal rule's error against the cancellation of the sum, Section
+ * 4.2.2): y = sqrt(2) 1.05 rho, and p0 from p0_grid (n_p0 values; NULL: 2, 3,
+ * 4, 5, 6, 8, 10, 12, 14, 16, 20, 24, 28, 32).  The predicted error of a
+ * contour is approx + u kappa (rexi_contour_error with 1601 points for approx
+ * and 401 for kappa; u = 2^-53 for prec 0, 2^-24 with REXI_PREC_FP32_SOLVE).
+ * N_fixed == 0: the contour with the fewest even N <= n_max whose prediction
+ * is <= target (ties: the first p0 of the grid).  N_fixed > 0 (even): the p0 of
+ * the grid with the smallest prediction at that N (target and n_max unused).
+ * Outputs (host): *p0, *y, *N, *predicted.  Host only.
+ * Errors: REXI_EINVAL; REXI_ENUMERIC when no p0 of the grid meets the target.
+ */
+int rexi_choose_contour(double rho, double target, int prec, int N_fixed, const double* p0_grid, int n_p0,
+                        int n_max, double* p0, double* y, int* N, double* predicted);
+
+/*
  * swe_create -- context for truncation L on an nlat x nlon Gauss grid with
  * planet radius a [m], gravity g [m/s^2], mean depth H [m], rotation rate
  * Omega [1/s] and precision flags prec (REXI_PREC_*).
@@ -119,9 +187,10 @@ int swe_destroy(swe_ctx* ctx);
  * rebuilds it, so a later call on another stream must be ordered after that
  * call by the caller.  U0, U1: device states [3][modes] complex128; they must
  * not overlap.
- * Before enqueueing, the host checks that the polygon of the poles -alpha_n
- * winds once around the segment i[-rho, rho], rho = dt (sqrt(g H L(L+1))/a +
- * 2 Omega), which bounds the spectrum of dt L; otherwise REXI_ENUMERIC.
+ * Before enqueueing, the host applies the checks of rexi_check_contour (the
+ * poles enclose the spectrum; the chain systems are diagonally dominant, so
+ * the unpivoted elimination is stable); otherwise REXI_ENUMERIC.
+ * Non-finite outputs are reported by swe_sync.
  * Errors: REXI_EINVAL (N odd or < 2, dt <= 0, NULL pointers), REXI_ENUMERIC,
  * REXI_ENOMEM, REXI_EDEVICE.
  */
@@ -134,8 +203,8 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta,
  * L_g couples h and delta of one degree, zeta is left alone):
  *   U1 = sum_n beta_n (dt L_g + alpha_n)^-1 U0,
  * computed per degree from two sums over the poles and applied per mode
- * (no banded solve).  U1 may equal U0.  Same contour check and errors as
- * rexi_linear_step.
+ * (no banded solve).  U1 may equal U0.  Same contour checks and errors as
+ * rexi_linear_step, without the dominance check (there is no chain solve).
  */
 int rexi_lg_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
                  const double* U0, double* U1, hipStream_t stream);
@@ -227,8 +296,12 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta,
                     int N, double dt, const double* U0, double* U1,
                     hipStream_t stream);
 
-/* swe_sync -- waits for all work the context enqueued; returns REXI_EDEVICE
- * if the device reported an error. */
+/* swe_sync -- waits for all work on the context's device; returns REXI_EDEVICE
+ * if the device reported an error, and REXI_ENUMERIC if any kernel of this
+ * context wrote a non-finite value (NaN or infinity) into an output since the
+ * last swe_sync: the REXI/linear stage outputs, the non-linear step outputs
+ * and the transform outputs set a device-side flag word (the error text names
+ * which); the flag is cleared by the call that reports it. */
 int swe_sync(swe_ctx* ctx);
 
 /* rexi_last_error -- thread-local text of the last error ("" if none).  The

@@ -22,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from .operator import Params, energy_scale, gather_m, operator_matrix, scatter_m
+from .operator import Params, energy_scale, gather_m, mode_index, operator_matrix, scatter_m
 
 KL = KU = 4
 
@@ -83,6 +83,32 @@ def rexi_step_m(u: np.ndarray, A: np.ndarray, alpha: np.ndarray, beta: np.ndarra
         y = scipy.linalg.solve_banded((KL, KU), _band(M), du)
         acc.add(b * y)
     return acc.value() / d
+
+
+def rexi_term_magnitudes(U0: np.ndarray, alpha: np.ndarray, beta: np.ndarray, dt: float,
+                         L: int, p: Params = Params(), orders=None) -> np.ndarray:
+    """Per output entry, the sum over the poles of the magnitudes of the terms of
+    Eq. (rexi): sum_n |beta_n| |((dt L + alpha_n)^{-1} U0)_j| (real array [3, modes]).
+
+    Section 4.2.2: the terms of the sum are far larger than the result, so any
+    evaluation with unit roundoff u carries an error of about u times this sum
+    (the per-entry form of kappa; for U0 = h_00 alone it is kappa(0) |h_00|)."""
+    M = np.zeros(U0.shape, dtype=np.float64)
+    for m in (range(L + 1) if orders is None else orders):
+        A = operator_matrix(m, L, p)
+        d = energy_scale(m, L, p)
+        n = A.shape[0]
+        dB = dt * (d[:, None] * A / d[None, :])
+        du = d * gather_m(U0, m, L)
+        acc = np.zeros(n)
+        for a, b in zip(alpha, beta):
+            y = scipy.linalg.solve_banded((KL, KU), _band(dB + a * np.eye(n)), du)
+            acc += np.abs(b) * np.abs(y)
+        tmp = np.zeros(U0.shape, dtype=np.complex128)
+        scatter_m(tmp, acc / d, m, L)
+        s = mode_index(L, m, m)
+        M[:, s:s + L - m + 1] = tmp[:, s:s + L - m + 1].real
+    return M
 
 
 def rexi_linear_step(U0: np.ndarray, alpha: np.ndarray, beta: np.ndarray, dt: float,

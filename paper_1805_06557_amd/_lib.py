@@ -22,6 +22,12 @@ class RexiMember(ctypes.Structure):
 # name -> (restype, argtypes); the stream argument is a hipStream_t (void*).
 SIGNATURES = {
     "rexi_coefficients": (_c_int, [_c_int, _c_int, _c_double, _c_double, _dp, _dp, _dp, _dp]),
+    "rexi_check_contour": (_c_int, [_c_int, _c_double, _c_double, _c_double, _c_double, _c_double, _dp, _dp,
+                                    _c_int, _dp]),
+    "rexi_spectral_radius": (_c_int, [_c_int, _c_double, _c_double, _c_double, _c_double, _c_double, _dp]),
+    "rexi_contour_error": (_c_int, [_dp, _dp, _c_int, _c_double, _c_int, _dp, _dp]),
+    "rexi_choose_contour": (_c_int, [_c_double, _c_double, _c_int, _c_int, _dp, _c_int, _c_int, _dp, _dp, _ip,
+                                     _dp]),
     "swe_create": (_c_int, [_c_int, _c_int, _c_int, _c_double, _c_double, _c_double, _c_double, _c_int,
                             ctypes.POINTER(_vp)]),
     "swe_destroy": (_c_int, [_vp]),

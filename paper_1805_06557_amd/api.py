@@ -51,6 +51,54 @@ def rexi_coefficients(fn: int, N: int, p0: float, y: float):
     return alpha.view(np.complex128), beta.view(np.complex128), r.value, mu.value
 
 
+def spectral_radius(L: int, dt: float, a: float = EARTH["a"], g: float = EARTH["g"], H: float = EARTH["H"],
+                    Omega: float = EARTH["Omega"]) -> float:
+    """rho bounding the spectrum of dt L -- see rexi_spectral_radius()."""
+    rho = ctypes.c_double()
+    _check(_lib.load().rexi_spectral_radius(L, float(dt), a, g, H, Omega, ctypes.byref(rho)), "rexi_spectral_radius")
+    return rho.value
+
+
+def check_contour(L: int, dt: float, alpha, beta, a: float = EARTH["a"], g: float = EARTH["g"],
+                  H: float = EARTH["H"], Omega: float = EARTH["Omega"]) -> float:
+    """The host checks of a coefficient set (rexi_check_contour); returns the
+    dominance margin, raises RexiError when a check fails."""
+    al = _host_coeffs(alpha)
+    be = _host_coeffs(beta)
+    if al.size != be.size:
+        raise ValueError("alpha and beta differ in length")
+    margin = ctypes.c_double(float("nan"))
+    _check(_lib.load().rexi_check_contour(L, a, g, H, Omega, float(dt), _dptr(al), _dptr(be), al.size // 2,
+                                          ctypes.byref(margin)), "rexi_check_contour")
+    return margin.value
+
+
+def contour_error(alpha, beta, rho: float, npts: int = 1601):
+    """(approx, kappa) of a coefficient set on i[-rho, rho] -- see rexi_contour_error()."""
+    al = _host_coeffs(alpha)
+    be = _host_coeffs(beta)
+    if al.size != be.size:
+        raise ValueError("alpha and beta differ in length")
+    e = ctypes.c_double()
+    k = ctypes.c_double()
+    _check(_lib.load().rexi_contour_error(_dptr(al), _dptr(be), al.size // 2, float(rho), int(npts), ctypes.byref(e),
+                                          ctypes.byref(k)), "rexi_contour_error")
+    return e.value, k.value
+
+
+def choose_contour(rho: float, target: float = 0.0, prec: int = PREC_FP64, N_fixed: int = 0, p0_grid=None,
+                   n_max: int = 4096):
+    """dict(p0, y, N, predicted) -- see rexi_choose_contour()."""
+    grid = None if p0_grid is None else np.ascontiguousarray(np.asarray(p0_grid, dtype=np.float64))
+    p0, y, pred = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    N = ctypes.c_int()
+    _check(_lib.load().rexi_choose_contour(float(rho), float(target), int(prec), int(N_fixed),
+                                           None if grid is None else _dptr(grid), 0 if grid is None else grid.size,
+                                           int(n_max), ctypes.byref(p0), ctypes.byref(y), ctypes.byref(N),
+                                           ctypes.byref(pred)), "rexi_choose_contour")
+    return dict(p0=p0.value, y=y.value, N=N.value, predicted=pred.value)
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:

@@ -3,10 +3,11 @@
 Contour parameters: the T31 case uses the paper's own choice (p0 = 10,
 p_{+-1} = +-30i, N = 128; Section 5).  For the others y = sqrt(2) 1.05 rho with
 rho = dt (sqrt(g H L(L+1)) / a + 2 Omega) the spectral-radius bound of dt L,
-and p0 is the shift that minimises the scalar error max_{|w|<=rho}
-|S(i w) - e^{i w}| at the stated N for the solve precision (p0 trades the
-geometric error of the trapezoidal rule against the cancellation of the sum,
-Section 4.2.2).
+and p0 is the shift that minimises the predicted error (scalar error
+max_{|w|<=rho} |S(i w) - e^{i w}| plus unit roundoff times the sum's
+cancellation factor) at the stated N for the solve precision, as the
+library's rexi_choose_contour evaluates it (p0 trades the geometric error of
+the trapezoidal rule against the cancellation of the sum, Section 4.2.2).
 """
 from __future__ import annotations
 
@@ -71,7 +72,7 @@ T511_FP64 = Workload(
     extra={"max_steps": 1})
 
 # T511 with the split-FP16 Legendre stage; the solves stay FP64 (at dt = 7200 s
-# no FP32 contour reaches a useful error: contour.choose finds none).
+# no FP32 contour reaches a useful error: rexi_choose_contour finds none).
 T511_FP64_FP16 = Workload(
     "T511-fp64-fp16", L=511, nlat=768, nlon=1536, dt=7200.0, N=2000, p0=24.0, y=270.3467676176863,
     steps=1, prec=4, seed=4,
@@ -87,7 +88,7 @@ ALL = {w.name: w for w in [T31_LINEAR, T127_NONLINEAR, T255_FP64, T255_FP32, T25
 # (dt = 3600 s) at a target scalar error E = 1e-4 on |w| <= rho.  Each
 # precision gets its own contour, the fewest poles whose predicted error
 # (approximation error + unit roundoff x kappa) meets E over the p0 grid of
-# contour.choose: FP32 needs a small shift (its rounding floor u_32 kappa grows
+# rexi_choose_contour: FP32 needs a small shift (its rounding floor u_32 kappa grows
 # like e^{p0}) and therefore many poles, FP64 reaches E with a large shift and
 # few poles.
 EQUAL_ERROR_E = 1e-4
@@ -110,14 +111,15 @@ ALL.update({w.name: w for w in [T255_FP32_AT_E, T255_FP64_AT_E, ENSEMBLE]})
 
 
 def ensemble_plan(count: int = 64, seed: int = 3, prec: int = 1, dt: float = 3600.0):
-    """Members of the ensemble: list of dicts with L, N, p0, y, dt and the input seed."""
-    from . import contour
+    """Members of the ensemble: list of dicts with L, N, p0, y, dt and the input seed
+    (each member's shift from the library's rexi_choose_contour at its N)."""
+    from . import api
     from .inputs import ensemble_members
     cache = {}
     out = []
     for L, N, s in ensemble_members(count, seed):
         if (L, N) not in cache:
-            cache[(L, N)] = contour.best_p0(L, dt, N, prec)
+            cache[(L, N)] = api.choose_contour(api.spectral_radius(L, dt), prec=prec, N_fixed=N)
         c = cache[(L, N)]
-        out.append(dict(L=L, N=N, p0=c.p0, y=c.y, dt=dt, seed=s))
+        out.append(dict(L=L, N=N, p0=c["p0"], y=c["y"], dt=dt, seed=s))
     return out

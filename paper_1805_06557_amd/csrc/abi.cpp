@@ -51,27 +51,9 @@ uint64_t pole_key(const double* alpha, const double* beta, int N, double dt) {
     return key;
 }
 
-int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, const char* who) {
-    for (int n = 0; n < N; ++n) {
-        const PoleData& q = pd[n];
-        if (!std::isfinite(q.zr) || !std::isfinite(q.zi) || !std::isfinite(q.wr) || !std::isfinite(q.wi))
-            return fail(REXI_EINVAL, std::string(who) + ": non-finite alpha or beta");
-    }
-    const double rho = dt * (std::sqrt(ctx->g * ctx->H * ctx->L * (ctx->L + 1.0)) / ctx->a + 2.0 * ctx->Omega);
-    const double probes[5] = {-rho, -0.5 * rho, 0.0, 0.5 * rho, rho};
-    for (double w : probes) {
-        const int wn = winding_number(pd, N, 0.0, w);
-        if (wn != 1 && wn != -1) {
-            char buf[200];
-            std::snprintf(buf, sizeof buf,
-                          "%s: the poles do not enclose the spectrum of dt L "
-                          "(winding %d around %.6g i; rho = %.6g)", who, wn, w, rho);
-            return fail(REXI_ENUMERIC, buf);
-        }
-    }
-    if (!(min_distance_to_segment(pd, N, rho) > 1e-6 * (1.0 + rho)))
-        return fail(REXI_ENUMERIC, std::string(who) + ": a pole lies on the spectrum of dt L");
-    return REXI_OK;
+int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, bool chain, const char* who) {
+    const OperatorBounds op{ctx->L, ctx->a, ctx->g, ctx->H, ctx->Omega, ctx->coup_max.data()};
+    return check_poles(op, pd, N, dt, chain, who, nullptr);
 }
 
 namespace {
@@ -134,19 +116,26 @@ PoleSet* pole_slot(swe_ctx* ctx, uint64_t key, int N, bool& hit) {
 }
 
 // Uploads (alpha, beta) if they differ from the cached set and checks that the
-// poles enclose the spectrum of dt L.
-int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
-                  hipStream_t stream) {
+// poles enclose the spectrum of dt L (and, when `chain`, that the chain
+// systems of the banded solve are diagonally dominant).
+int prepare_poles(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt, bool chain,
+                  const char* who, hipStream_t stream) {
     const uint64_t key = pole_key(alpha, beta, N, dt);
     bool hit = false;
     PoleSet* slot = pole_slot(ctx, key, N, hit);
-    if (hit) return REXI_OK;
+    if (hit && (!chain || slot->chain_ok)) return REXI_OK;
 
     std::vector<PoleData> pd(N);
     build_pole_data(alpha, beta, N, pd.data());
-    const int rc = check_poles(ctx, pd.data(), N, dt, "rexi_linear_step");
+    int rc = check_poles(ctx, pd.data(), N, dt, chain, who);
     if (rc != REXI_OK) return rc;
-    return activate_poles(ctx, slot, pd.data(), N, key, stream);
+    if (hit) {
+        slot->chain_ok = true;
+        return REXI_OK;
+    }
+    if ((rc = activate_poles(ctx, slot, pd.data(), N, key, stream)) != REXI_OK) return rc;
+    slot->chain_ok = chain;
+    return REXI_OK;
 }
 
 template <typename T>
@@ -277,6 +266,17 @@ int tendency_eval(swe_ctx* ctx, const double* U, double* Nout, hipStream_t strea
 // Crank-Nicolson over tau: (I - tau/2 L)^-1 (I + tau/2 L) U0 = -U0 + 4 (2 - tau L)^-1 U0,
 // one real shift z = 2 with weight 4 on the chain solve.  U0 and U1 must differ.
 int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream) {
+    // the shift z = 2 lies 2 away from the spectrum segment: every chain diagonal
+    // is at least 2 in modulus (see check_poles), the off-diagonals of a row sum
+    // to at most tau coup_max[k]
+    const double off = tau * *std::max_element(ctx->coup_max.begin(), ctx->coup_max.end());
+    if (!(2.0 > off)) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "swe_cn_step: dt = %.6g is too long for the unpivoted chain elimination (off-diagonal "
+                      "sum %.4g >= diagonal bound 2)", tau, off);
+        return fail(REXI_ENUMERIC, buf);
+    }
     uint64_t key = 0x43726e6b4e69636fULL;            // a tag no coefficient hash is expected to hit
     key = fnv1a(&tau, sizeof(tau), key);
     bool hit = false;
@@ -293,7 +293,7 @@ int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
         if ((rc = activate_poles(ctx, slot, &pd, 1, key, stream)) != REXI_OK) return rc;
     }
     if ((rc = launch_rexi_solve(ctx, 1, tau, U0, U1, stream)) != REXI_OK) return rc;
-    return launch_axpy(U1, U1, -1.0, U0, 6 * ctx->modes, stream);
+    return launch_axpy(U1, U1, -1.0, U0, 6 * ctx->modes, ctx->d_status, STATUS_REXI, stream);
 }
 
 int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream, double two_omega = 0.0) {
@@ -332,6 +332,11 @@ void prof_end(swe_ctx* ctx, int kernel, int slot, hipStream_t stream) {
     if (hipEventRecord(ctx->prof.stop[kernel][slot], stream) == hipSuccess) ctx->prof.count[kernel] = slot + 1;
 }
 
+bool valid_constants(double a, double g, double H, double Omega) {
+    return a > 0 && g > 0 && H > 0 && Omega >= 0 && std::isfinite(a) && std::isfinite(g) && std::isfinite(H) &&
+           std::isfinite(Omega);
+}
+
 }  // namespace rexi
 
 using namespace rexi;
@@ -345,13 +350,63 @@ int rexi_coefficients(int fn, int N, double p0, double y, double* alpha, double*
     return rexi::coefficients(fn, N, p0, y, alpha, beta, r, mu);
 }
 
+int rexi_check_contour(int L, double a, double g, double H, double Omega, double dt, const double* alpha,
+                       const double* beta, int N, double* margin) {
+    if (L < 1 || L > 1023) return fail(REXI_EINVAL, "rexi_check_contour: L must be in [1, 1023]");
+    if (!valid_constants(a, g, H, Omega))
+        return fail(REXI_EINVAL, "rexi_check_contour: a, g, H must be positive and Omega non-negative");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "rexi_check_contour: dt must be positive");
+    if (!alpha || !beta) return fail(REXI_EINVAL, "rexi_check_contour: NULL alpha or beta");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "rexi_check_contour: N must be even and in [2, 2^20]");
+    std::vector<PoleData> pd(N);
+    build_pole_data(alpha, beta, N, pd.data());
+    std::vector<double> off;
+    coupling_row_max(L, Omega, off);
+    const OperatorBounds op{L, a, g, H, Omega, off.data()};
+    return check_poles(op, pd.data(), N, dt, true, "rexi_check_contour", margin);
+}
+
+int rexi_spectral_radius(int L, double dt, double a, double g, double H, double Omega, double* rho) {
+    if (!rho || L < 0 || !(dt > 0) || !std::isfinite(dt) || !valid_constants(a, g, H, Omega))
+        return fail(REXI_EINVAL, "rexi_spectral_radius: bad argument");
+    *rho = spectral_radius(L, dt, a, g, H, Omega);
+    return REXI_OK;
+}
+
+int rexi_contour_error(const double* alpha, const double* beta, int N, double rho, int npts, double* approx,
+                       double* kappa) {
+    if (!alpha || !beta || !approx || !kappa) return fail(REXI_EINVAL, "rexi_contour_error: NULL argument");
+    if (N < 1 || N > (1 << 20) || npts < 2 || npts > (1 << 20) || !(rho >= 0) || !std::isfinite(rho))
+        return fail(REXI_EINVAL, "rexi_contour_error: bad N, npts or rho");
+    contour_error(alpha, beta, N, rho, npts, approx, kappa);
+    return REXI_OK;
+}
+
+int rexi_choose_contour(double rho, double target, int prec, int N_fixed, const double* p0_grid, int n_p0,
+                        int n_max, double* p0, double* y, int* N, double* predicted) {
+    if (!p0 || !y || !N || !predicted) return fail(REXI_EINVAL, "rexi_choose_contour: NULL output");
+    if (!(rho > 0) || !std::isfinite(rho)) return fail(REXI_EINVAL, "rexi_choose_contour: rho must be positive");
+    if (prec & ~(REXI_PREC_FP32_SOLVE | REXI_PREC_BF16_SPLIT | REXI_PREC_FP16_SPLIT))
+        return fail(REXI_EINVAL, "rexi_choose_contour: unknown precision flags");
+    if (p0_grid && (n_p0 < 1 || n_p0 > 1024)) return fail(REXI_EINVAL, "rexi_choose_contour: bad grid size");
+    for (int i = 0; p0_grid && i < n_p0; ++i)
+        if (!(p0_grid[i] > 0) || !std::isfinite(p0_grid[i]))
+            return fail(REXI_EINVAL, "rexi_choose_contour: grid shifts must be positive");
+    if (N_fixed < 0 || (N_fixed & 1) || N_fixed > (1 << 16))
+        return fail(REXI_EINVAL, "rexi_choose_contour: N_fixed must be 0 or even and at most 65536");
+    if (N_fixed == 0) {
+        if (!(target > 0) || !std::isfinite(target)) return fail(REXI_EINVAL, "rexi_choose_contour: target must be positive");
+        if (n_max < 2 || n_max > (1 << 16)) return fail(REXI_EINVAL, "rexi_choose_contour: n_max must be in [2, 65536]");
+    }
+    return choose_contour(rho, target, prec, N_fixed, p0_grid, n_p0, n_max, p0, y, N, predicted);
+}
+
 int swe_create(int L, int nlat, int nlon, double a, double g, double H, double Omega, int prec,
                swe_ctx** out) {
     if (!out) return fail(REXI_EINVAL, "swe_create: NULL output pointer");
     *out = nullptr;
     if (L < 1 || L > 1023) return fail(REXI_EINVAL, "swe_create: L must be in [1, 1023]");
-    if (!(a > 0) || !(g > 0) || !(H > 0) || !(Omega >= 0) || !std::isfinite(a) || !std::isfinite(g) ||
-        !std::isfinite(H) || !std::isfinite(Omega))
+    if (!valid_constants(a, g, H, Omega))
         return fail(REXI_EINVAL, "swe_create: a, g, H must be positive and Omega non-negative");
     const bool linear_only = nlat == 0 && nlon == 0;
     if (!linear_only) {
@@ -383,6 +438,7 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     ctx->H = H;
     ctx->Omega = Omega;
     ctx->modes = n_modes(L);
+    coupling_row_max(L, Omega, ctx->coup_max);
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) {
         delete ctx;
@@ -396,6 +452,8 @@ int swe_create(int L, int nlat, int nlon, double a, double g, double H, double O
     e = hipMalloc(&ctx->d_coef, sizeof(ModeCoef) * ctx->modes);
     if (e == hipSuccess)
         e = hipMemcpy(ctx->d_coef, coef.data(), sizeof(ModeCoef) * ctx->modes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&ctx->d_status, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(ctx->d_status, 0, sizeof(unsigned));
     if (e != hipSuccess) {
         swe_destroy(ctx);
         return hip_fail(e, "swe_create: uploading operator tables");
@@ -417,6 +475,7 @@ int swe_destroy(swe_ctx* ctx) {
     DeviceGuard guard(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->d_coef) (void)hipFree(ctx->d_coef);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
     for (PoleSet& ps : ctx->pole_sets)
         if (ps.d) (void)hipFree(ps.d);
     if (ctx->d_partial) (void)hipFree(ctx->d_partial);
@@ -474,7 +533,7 @@ int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int 
     if (a0 < a1 + bytes && a1 < a0 + bytes) return fail(REXI_EINVAL, "rexi_linear_step: U0 and U1 overlap");
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(REXI_EDEVICE, "rexi_linear_step: cannot select the context's device");
-    int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
+    int rc = prepare_poles(ctx, alpha, beta, N, dt, true, "rexi_linear_step", stream);
     if (rc != REXI_OK) return rc;
     return launch_rexi_solve(ctx, N, dt, U0, U1, stream);
 }
@@ -487,7 +546,7 @@ int rexi_lg_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, d
     if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "rexi_lg_step: dt must be positive");
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(REXI_EDEVICE, "rexi_lg_step: cannot select the context's device");
-    int rc = prepare_poles(ctx, alpha, beta, N, dt, stream);
+    int rc = prepare_poles(ctx, alpha, beta, N, dt, false, "rexi_lg_step", stream);
     if (rc != REXI_OK) return rc;
     return launch_rexi_lg(ctx, N, dt, U0, U1, stream);
 }
@@ -519,7 +578,7 @@ int rexi_linear_step_batched(const rexi_member* members, int count, hipStream_t 
     if (!guard.ok) return fail(REXI_EDEVICE, "rexi_linear_step_batched: cannot select the device");
     for (int i = 0; i < count; ++i) {
         const int rc = prepare_poles(members[i].ctx, members[i].alpha, members[i].beta, members[i].N,
-                                     members[i].dt, stream);
+                                     members[i].dt, true, "rexi_linear_step_batched", stream);
         if (rc != REXI_OK) return rc;
     }
     return launch_rexi_batched(mem.data(), count, stream);
@@ -635,7 +694,7 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N
     if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_strang_step: dt must be positive");
     DeviceGuard guard(ctx->device);
     int rc;
-    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, true, "swe_strang_step", stream)) != REXI_OK) return rc;
     if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
     return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
@@ -674,7 +733,7 @@ int swe_split_step(swe_ctx* ctx, int scheme, const double* alpha, const double* 
     int rc;
     auto linear = [&](const double* in, double* out) -> int {
         if (!rexi) return cn_linear(ctx, tl, in, out, stream);
-        int r = prepare_poles(ctx, alpha, beta, N, tl, stream);
+        int r = prepare_poles(ctx, alpha, beta, N, tl, !lg, "swe_split_step", stream);
         if (r != REXI_OK) return r;
         return lg ? launch_rexi_lg(ctx, N, tl, in, out, stream) : launch_rexi_solve(ctx, N, tl, in, out, stream);
     };
@@ -708,18 +767,21 @@ int swe_etdrk2_step(swe_ctx* ctx, const double* alpha, const double* beta0, cons
     // N0 = N(U0)
     if ((rc = tendency_eval(ctx, U0, ctx->d_n0, stream)) != REXI_OK) return rc;
     // A = psi_0(dt L) U0 + dt psi_1(dt L) N0
-    if ((rc = prepare_poles(ctx, alpha, beta0, N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = prepare_poles(ctx, alpha, beta0, N, dt, true, "swe_etdrk2_step", stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
-    if ((rc = prepare_poles(ctx, alpha, b1.data(), N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = prepare_poles(ctx, alpha, b1.data(), N, dt, true, "swe_etdrk2_step", stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_n0, ctx->d_tmpB, stream)) != REXI_OK) return rc;
-    if ((rc = launch_axpy(ctx->d_tmpA, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, stream)) != REXI_OK) return rc;
+    if ((rc = launch_axpy(ctx->d_tmpA, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, ctx->d_status, STATUS_REXI, stream)) != REXI_OK)
+        return rc;
     // D = N(A) - N0
     if ((rc = tendency_eval(ctx, ctx->d_tmpA, ctx->d_ustar, stream)) != REXI_OK) return rc;
-    if ((rc = launch_axpy(ctx->d_ustar, ctx->d_ustar, -1.0, ctx->d_n0, n, stream)) != REXI_OK) return rc;
+    if ((rc = launch_axpy(ctx->d_ustar, ctx->d_ustar, -1.0, ctx->d_n0, n, ctx->d_status, STATUS_NONLINEAR, stream)) !=
+        REXI_OK)
+        return rc;
     // U1 = A + dt psi_2(dt L) D
-    if ((rc = prepare_poles(ctx, alpha, b2.data(), N, dt, stream)) != REXI_OK) return rc;
+    if ((rc = prepare_poles(ctx, alpha, b2.data(), N, dt, true, "swe_etdrk2_step", stream)) != REXI_OK) return rc;
     if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_ustar, ctx->d_tmpB, stream)) != REXI_OK) return rc;
-    return launch_axpy(U1, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, stream);
+    return launch_axpy(U1, ctx->d_tmpA, 1.0, ctx->d_tmpB, n, ctx->d_status, STATUS_NONLINEAR, stream);
 }
 
 int swe_profile(swe_ctx* ctx, int enable) {
@@ -756,6 +818,17 @@ int swe_sync(swe_ctx* ctx) {
     if (!ctx) return fail(REXI_EINVAL, "swe_sync: NULL context");
     DeviceGuard guard(ctx->device);
     REXI_HIP(hipDeviceSynchronize());
+    unsigned flags = 0;
+    REXI_HIP(hipMemcpy(&flags, ctx->d_status, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags) {
+        REXI_HIP(hipMemset(ctx->d_status, 0, sizeof flags));
+        REXI_HIP(hipDeviceSynchronize());
+        std::string what;
+        if (flags & STATUS_REXI) what += " REXI/linear stage output;";
+        if (flags & STATUS_NONLINEAR) what += " non-linear step output;";
+        if (flags & STATUS_TRANSFORM) what += " transform output;";
+        return fail(REXI_ENUMERIC, "swe_sync: non-finite values were written since the last swe_sync:" + what);
+    }
     return REXI_OK;
 }
 

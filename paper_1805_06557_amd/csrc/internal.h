@@ -55,6 +55,43 @@ int winding_number(const PoleData* pd, int N, double x, double y);
 // Smallest distance between a pole z_n and the segment i[-rho, rho].
 double min_distance_to_segment(const PoleData* pd, int N, double rho);
 
+// rho = dt (sqrt(g H L(L+1))/a + 2 Omega): bound on the spectrum of dt L.
+double spectral_radius(int L, double dt, double a, double g, double H, double Omega);
+// max_w |S(i w) - e^{i w}| (approx) and max_w sum |beta|/|i w + alpha| (kappa)
+// over npts points of [-rho, rho]; either output may be NULL.
+void contour_error(const double* alpha, const double* beta, int N, double rho, int npts, double* approx,
+                   double* kappa);
+// See rexi_choose_contour in rexi_swe.h.
+int choose_contour(double rho, double target, int prec, int N_fixed, const double* grid, int n_grid, int n_max,
+                   double* p0, double* y, int* N, double* predicted);
+
+// Largest off-diagonal row sum of the chain form per unit dt for each degree:
+// out[k] = max over the orders m <= k of |cm| + |cp| (see ModeCoef), k = 0..L.
+void coupling_row_max(int L, double Omega, std::vector<double>& out);
+
+// The operator a coefficient set is checked against.
+struct OperatorBounds {
+    int L;
+    double a, g, H, Omega;
+    const double* off;   // [L+1] coupling_row_max
+};
+
+// Host checks of a coefficient set before any launch: finite values; the
+// poles wind once around the segment i[-rho, rho] that holds the spectrum of
+// dt L (rho = dt (sqrt(g H L(L+1))/a + 2 Omega)) and keep a distance from it;
+// with `chain`, every row of every chain system is strictly diagonally
+// dominant (the condition under which the unpivoted elimination is stable).
+// For degree k the orders m <= k give diagonal shifts dt m q_k in
+// [0, dt 2 Omega/(k+1)], so a zeta-row diagonal z - i dt m q_k is at least the
+// distance of z from the segment i[0, dt 2 Omega/(k+1)], and a delta-row
+// diagonal z + dt^2 H gN_k / z - i dt m q_k at least the distance of
+// z + dt^2 H gN_k / z from it; the row's off-diagonals sum to at most
+// dt off[k].  *margin (may be NULL) receives the smallest ratio over poles and
+// degrees (> 1 when every row is dominant).  `who` names the entry point in
+// the error text.
+int check_poles(const OperatorBounds& op, const PoleData* pd, int N, double dt, bool chain, const char* who,
+                double* margin);
+
 // Extended-precision REXI coefficients (see rexi_coefficients in rexi_swe.h).
 int coefficients(int fn, int N, double p0, double y, double* alpha, double* beta,
                  double* r, double* mu);
@@ -110,6 +147,7 @@ struct PoleSet {
     int cap = 0, n = 0;
     uint64_t key = 0;              // hash of alpha, beta, N and dt
     bool valid = false;
+    bool chain_ok = false;         // the chain systems' dominance was checked for this set
     unsigned long long used = 0;   // last use, for replacement
 };
 
@@ -125,6 +163,10 @@ struct Tuning {
 struct swe_ctx {
     int L = 0, nlat = 0, nlon = 0, prec = 0, device = 0, modes = 0;
     double a = 0, g = 0, H = 0, Omega = 0;
+    std::vector<double> coup_max;      // [L+1] rexi::coupling_row_max(L, Omega)
+    // non-finite results written by the context's kernels since the last
+    // swe_sync (bit flags rexi::STATUS_*), set with vector atomics
+    unsigned* d_status = nullptr;
     rexi::Tuning tune;
     rexi::Profiler prof;
 
@@ -206,6 +248,14 @@ struct swe_ctx {
 
 namespace rexi {
 
+// Flags of ctx->d_status: which kind of output turned non-finite.
+enum : unsigned { STATUS_REXI = 1u, STATUS_NONLINEAR = 2u, STATUS_TRANSFORM = 4u };
+
+// Sets `bit` in *status when v is not finite (a rare path: one vector atomic).
+__device__ __forceinline__ void note_nonfinite(unsigned* status, double v, unsigned bit) {
+    if (!__builtin_isfinite(v)) atomicOr(status, bit);
+}
+
 // Launches the chain solve + reduction for one REXI stage on `stream`.
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
                       hipStream_t stream);
@@ -250,18 +300,18 @@ int launch_rexi_lg(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
 inline size_t lg_sums_bytes(int L) { return sizeof(double) * 4 * static_cast<size_t>(L + 2); }
 int launch_rexi_lg_on(swe_ctx* ctx, const PoleData* poles, void* sums, int N, double dt, const double* U0,
                       double* U1, hipStream_t stream);
-// Host checks of a coefficient set before any launch: finite values, the
-// poles wind once around the spectrum segment i[-rho, rho] of dt L and keep a
-// distance from it.  `who` names the entry point in the error text.
-int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, const char* who);
+// check_poles with the context's operator.
+int check_poles(const swe_ctx* ctx, const PoleData* pd, int N, double dt, bool chain, const char* who);
 // Cache key of a coefficient set (alpha, beta: 2N doubles each) and dt.
 uint64_t pole_key(const double* alpha, const double* beta, int N, double dt);
 // Allocation-free entry point support: resolves the device address of the
 // library's static scratch array on `device` (once per device; call with the
 // device current).
 int noalloc_init_device(int device);
-// out = x + a y over n doubles (out may equal x or y).
-int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream);
+// out = x + a y over n doubles (out may equal x or y); non-finite outputs set
+// `bit` in *status.
+int launch_axpy(double* out, const double* x, double a, const double* y, int n, unsigned* status, unsigned bit,
+                hipStream_t stream);
 // Radix sequence of the longitude FFT of M = nlon/2 complex points.
 int ring_plan(int M, std::vector<int>& radix);
 // Twiddles of every pass of that plan, pass-major ([M] complex).

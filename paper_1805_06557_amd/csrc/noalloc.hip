@@ -98,7 +98,7 @@ extern "C" int rexi_lg_step_noalloc(swe_ctx* ctx, const double* alpha, const dou
     const uint64_t key = pole_key(alpha, beta, N, dt);
     if (!dev.poles_valid || dev.poles_key != key) {
         build_pole_data(alpha, beta, N, dev.host);
-        const int rc = check_poles(ctx, dev.host, N, dt, "rexi_lg_step_noalloc");
+        const int rc = check_poles(ctx, dev.host, N, dt, false, "rexi_lg_step_noalloc");
         if (rc != REXI_OK) return rc;
         // ordered after earlier work on `stream`; the wait lets the next call
         // rebuild the host table

@@ -224,6 +224,7 @@ struct SolveArgs {
     const double2* __restrict__ U0;     // [3][modes] state
     const ModeCoef* __restrict__ coef;  // [modes]
     double dt, H;
+    unsigned* status;                   // non-finite outputs set STATUS_REXI
 };
 
 struct Lane {
@@ -358,6 +359,7 @@ __device__ __forceinline__ void reduce_group(const SolveArgs& A, const RecT<T>* 
                 sx = __builtin_fma(-A.dtH, sx, ax);
                 sy = __builtin_fma(-A.dtH, sy, ay);
             }
+            note_nonfinite(A.status, sx + sy, STATUS_REXI);
             A.out[(pw * 3 + field) * A.modes + base + j] = make_double2(sx, sy);
         }
     }
@@ -695,10 +697,13 @@ __device__ __forceinline__ double2 sum_parts(const double2* __restrict__ part, i
 }
 
 __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part,
-                                                           double2* __restrict__ U1, int count, int nparts) {
+                                                           double2* __restrict__ U1, int count, int nparts,
+                                                           unsigned* status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    U1[i] = sum_parts(part, count, nparts, i);
+    const double2 v = sum_parts(part, count, nparts, i);
+    note_nonfinite(status, v.x + v.y, STATUS_REXI);
+    U1[i] = v;
 }
 
 // Ensemble form: member blockIdx.y (count = 0: the member has one pole wave
@@ -707,13 +712,16 @@ struct SumArgs {
     const double2* part;
     double2* U1;
     int count, nparts;
+    unsigned* status;
 };
 
 __global__ __launch_bounds__(256) void sum_partials_batched_kernel(const SumArgs* __restrict__ args) {
     const SumArgs a = args[blockIdx.y];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.count) return;
-    a.U1[i] = sum_parts(a.part, a.count, a.nparts, i);
+    const double2 v = sum_parts(a.part, a.count, a.nparts, i);
+    note_nonfinite(a.status, v.x + v.y, STATUS_REXI);
+    a.U1[i] = v;
 }
 
 // The factorization cache of a context: reserve_factors sizes it (dropping a
@@ -877,7 +885,7 @@ int launch_batched_typed(const BatchMember* mem, int count, const Tuning& t, hip
                                c->modes, mem[i].dt, c->H};
             const int nparts = (mem[i].N + WAVE * P - 1) / (WAVE * P);
             sums[i] = SumArgs{reinterpret_cast<const double2*>(c->d_partial), reinterpret_cast<double2*>(mem[i].U1),
-                              nparts > 1 ? 3 * c->modes : 0, nparts};
+                              nparts > 1 ? 3 * c->modes : 0, nparts, c->d_status};
             max_modes = std::max(max_modes, c->modes);
             max_L = std::max(max_L, c->L);
         }
@@ -1014,6 +1022,7 @@ int base_args(swe_ctx* ctx, int N, double dt, const double* U0, const double* U1
     A.fact = nullptr;
     A.ckpt = nullptr;
     A.npb = A.nck_max = A.rec_bytes = 0;
+    A.status = ctx->d_status;
     const size_t count = static_cast<size_t>(3) * ctx->modes;
     if (nparts == 1) {
         A.out = reinterpret_cast<double2*>(const_cast<double*>(U1));
@@ -1056,7 +1065,7 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
         const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
         hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks), dim3(threads), 0, stream,
                            reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1), count,
-                           nparts);
+                           nparts, ctx->d_status);
         REXI_HIP(hipGetLastError());
         prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
     }
@@ -1117,7 +1126,7 @@ __global__ __launch_bounds__(256) void lg_sums_kernel(const PoleData* __restrict
 
 // U1 = (sum over poles) U0 per mode; one workgroup per order m.  U1 may equal U0.
 __global__ __launch_bounds__(256) void lg_apply_kernel(const double2* U0, double2* U1, const double2* __restrict__ AB,
-                                                       int L, int modes, double dtH, double dtg_a2) {
+                                                       int L, int modes, double dtH, double dtg_a2, unsigned* status) {
     const int m = blockIdx.x;
     const int base = m * (2 * L + 3 - m) / 2;
     const double2 S0 = AB[2 * (L + 1)];
@@ -1133,6 +1142,7 @@ __global__ __launch_bounds__(256) void lg_apply_kernel(const double2* U0, double
         const double2 d1 = make_double2(__builtin_fma(db.x, h.x, -(db.y * h.y)) + __builtin_fma(A.x, d.x, -(A.y * d.y)),
                                         __builtin_fma(db.x, h.y, db.y * h.x) + __builtin_fma(A.x, d.y, A.y * d.x));
         const double2 z1 = make_double2(__builtin_fma(S0.x, z.x, -(S0.y * z.y)), __builtin_fma(S0.x, z.y, S0.y * z.x));
+        note_nonfinite(status, (h1.x + h1.y) + (z1.x + z1.y) + (d1.x + d1.y), STATUS_REXI);
         U1[idx] = h1;
         U1[modes + idx] = z1;
         U1[2 * modes + idx] = d1;
@@ -1149,7 +1159,7 @@ int launch_rexi_lg_on(swe_ctx* ctx, const PoleData* poles, void* sums, int N, do
     REXI_HIP(hipGetLastError());
     hipLaunchKernelGGL(lg_apply_kernel, dim3(ctx->L + 1), dim3(256), 0, stream, reinterpret_cast<const double2*>(U0),
                        reinterpret_cast<double2*>(U1), reinterpret_cast<const double2*>(sums), ctx->L,
-                       ctx->modes, dt * ctx->H, dt * ctx->g / (ctx->a * ctx->a));
+                       ctx->modes, dt * ctx->H, dt * ctx->g / (ctx->a * ctx->a), ctx->d_status);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }

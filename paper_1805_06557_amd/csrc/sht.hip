@@ -63,6 +63,7 @@ struct LegArgs {
     const int* __restrict__ seed_e;     // [nseg][half]
     int L, nlat, half, modes, nseg;
     double a;
+    unsigned* status;                   // non-finite outputs set a STATUS_* flag
 };
 
 // Recurrence state of one latitude: Pbar_{l-1}, Pbar_l in units of 2^e.
@@ -410,6 +411,7 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
                 const size_t idx = static_cast<size_t>(base) + i0 + d;
                 if constexpr (KIND == 0) {
                     double* dst = reinterpret_cast<double*>(P.spec + static_cast<size_t>(blockIdx.y) * A.modes + idx);
+                    note_nonfinite(A.status, s, STATUS_TRANSFORM);
                     dst[k] = s;
                 } else {
                     const int f = k >> 1, part = k & 1;
@@ -417,6 +419,7 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
                     double v = __builtin_fma(P.c0, s, P.U0 ? reinterpret_cast<const double*>(P.U0)[e2] : 0.0);
                     if (P.Nprev) v = __builtin_fma(P.c1, reinterpret_cast<const double*>(P.Nprev)[e2], v);
                     if (P.Nsave) reinterpret_cast<double*>(P.Nsave)[e2] = s;
+                    note_nonfinite(A.status, v, STATUS_NONLINEAR);
                     reinterpret_cast<double*>(P.out)[e2] = v;
                 }
             }
@@ -443,6 +446,7 @@ struct RingArgs {
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
     int nf;
+    unsigned* status;                  // non-finite grid outputs set STATUS_TRANSFORM
     double two_omega;                  // mode 2: 2 Omega adds f = 2 Omega mu to zeta (absolute vorticity)
 };
 
@@ -762,7 +766,11 @@ __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
             wave_pack_inverse<MC>(A, x, twr, lane);
             wave_fft<MC, true>(x, A, tw, lane);
             double2* g = reinterpret_cast<double2*>(A.gout + (static_cast<size_t>(f) * A.nlat + j) * A.nlon);
-            for (int k = lane; k < M; k += WAVE) g[k] = x[pad8(k)];
+            for (int k = lane; k < M; k += WAVE) {
+                const double2 v = x[pad8(k)];
+                note_nonfinite(A.status, v.x + v.y, STATUS_TRANSFORM);
+                g[k] = v;
+            }
             wave_sync();
         }
     } else if constexpr (MODE == 1) {
@@ -816,14 +824,20 @@ __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
 
 namespace {
 // out = x + a y over n doubles (spectral-state combinations of the time steppers).
-__global__ __launch_bounds__(256) void axpy_kernel(double* out, const double* x, double a, const double* y, int n) {
+__global__ __launch_bounds__(256) void axpy_kernel(double* out, const double* x, double a, const double* y, int n,
+                                                   unsigned* status, unsigned bit) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = __builtin_fma(a, y[i], x[i]);
+    if (i < n) {
+        const double v = __builtin_fma(a, y[i], x[i]);
+        note_nonfinite(status, v, bit);
+        out[i] = v;
+    }
 }
 }  // namespace
 
-int launch_axpy(double* out, const double* x, double a, const double* y, int n, hipStream_t stream) {
-    hipLaunchKernelGGL(axpy_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, out, x, a, y, n);
+int launch_axpy(double* out, const double* x, double a, const double* y, int n, unsigned* status, unsigned bit,
+                hipStream_t stream) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, out, x, a, y, n, status, bit);
     REXI_HIP(hipGetLastError());
     return REXI_OK;
 }
@@ -849,6 +863,7 @@ static LegArgs leg_args(const swe_ctx* ctx) {
     g.half = ctx->nlat / 2;
     g.modes = ctx->modes;
     g.a = ctx->a;
+    g.status = ctx->d_status;
     return g;
 }
 
@@ -864,6 +879,7 @@ static RingArgs ring_args(const swe_ctx* ctx) {
     r.nlat = ctx->nlat;
     r.nlon = ctx->nlon;
     r.half = ctx->nlat / 2;
+    r.status = ctx->d_status;
     return r;
 }
 

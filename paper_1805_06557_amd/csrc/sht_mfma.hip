@@ -21,7 +21,7 @@
 // value x is stored as x_hi = t(x), x_lo = t(x - x_hi) for the 16-bit type t,
 // interleaved in groups of four (hi[4], lo[4]); a product is accumulated in
 // FP32 as a_hi b_hi + a_hi b_lo + a_lo b_hi with v_mfma_f32_16x16x16_bf16 or
-// _f16 (relative error about 2^-16 per product for BF16, 2^-21 for FP16, plus
+// _f16 (relative error about 2^-16 per product for BF16, 2^-22 for FP16, plus
 // FP32 accumulation).  FP16's exponent range is narrow, so in FP16 mode every
 // column of the data operand is scaled by a power of two that brings its
 // largest magnitude into [1/2, 1) (exact; undone on the FP32 sums), and the
@@ -235,6 +235,7 @@ struct MfmaArgs {
     double2* __restrict__ Nsave;
     double2* __restrict__ out;
     double c0, c1;
+    unsigned* status;                     // non-finite outputs set a STATUS_* flag
 };
 
 // ---------------------------------------------------------------- synthesis --
@@ -595,8 +596,9 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             if constexpr (KIND == 0) {
                 const int f = f0 + (c >> 1);
                 if (i >= Lm || f >= A.nf) continue;
-                reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + base + i)[c & 1] =
-                    static_cast<double>(acc[t]) / (SCALED ? static_cast<double>(sc[c]) : 1.0);
+                const double v = static_cast<double>(acc[t]) / (SCALED ? static_cast<double>(sc[c]) : 1.0);
+                note_nonfinite(A.status, v, STATUS_TRANSFORM);
+                reinterpret_cast<double*>(A.spec_out + static_cast<size_t>(f) * A.modes + base + i)[c & 1] = v;
             } else {
                 zs[(par * A.kmax + r) * 16 + c] = acc[t];
             }
@@ -625,7 +627,9 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             }
             const size_t e2 = (static_cast<size_t>(k >> 1) * A.modes + base + i) * 2 + (k & 1);
             if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
-            reinterpret_cast<double*>(A.out)[e2] = __builtin_fma(A.c0, v, ob);
+            const double o = __builtin_fma(A.c0, v, ob);
+            note_nonfinite(A.status, o, STATUS_NONLINEAR);
+            reinterpret_cast<double*>(A.out)[e2] = o;
         };
 #pragma unroll
         for (int q = 0; q < EPI; ++q) {
@@ -658,6 +662,7 @@ MfmaArgs mfma_args(const swe_ctx* ctx) {
     A.kmax = ctx->tab_kmax;
     A.modes = ctx->modes;
     A.a = ctx->a;
+    A.status = ctx->d_status;
     return A;
 }
 

@@ -1,18 +1,32 @@
-"""The host-side contour chooser (Section 4.2 coefficients, Section 4.2.2
-cancellation) against the oracle: its error estimate is the oracle's brute-force
-REXI sum on the same grid, and the stored equal-error contours of the T255
-FP32-against-FP64 comparison are what the chooser returns, minimal in N."""
+"""The library's host-only contour calls against the oracle (no GPU needed):
+rexi_spectral_radius, rexi_contour_error (Section 4.2 sum, Section 4.2.2
+cancellation factor), rexi_choose_contour (the contour for a target error)
+and rexi_check_contour (the poles enclose the spectrum of dt L, Section
+4.2.1, and the chain systems of the banded solve are diagonally dominant,
+the condition for the unpivoted elimination).  The reference values come from
+the oracle's brute-force REXI sums and from the oracle's own operator
+matrices, never from the library."""
 import numpy as np
 import pytest
 
 from oracle import rexi as orexi
-from oracle.operator import Params, spectral_radius_bound
-from paper_1805_06557_amd import configs, contour
+from oracle.operator import Params, operator_matrix, spectral_radius_bound
+from paper_1805_06557_amd import api, configs
+
+U = {0: 2.0 ** -53, 1: 2.0 ** -24}
+
+
+def _oracle_predicted(a, b, rho, prec):
+    """approx (1601 points) + u kappa (401 points), evaluated by the oracle."""
+    w = np.linspace(-rho, rho, 1601)
+    approx = np.abs(orexi.rexi_sum(a, b, 1j * w) - np.exp(1j * w)).max()
+    kap = orexi.kappa(a, b, 1j * np.linspace(-rho, rho, 401)).max()
+    return approx + U[prec & 1] * kap
 
 
 def test_radius_matches_oracle_bound():
     for L, dt in [(31, 3600.0), (255, 3600.0), (511, 7200.0)]:
-        assert abs(contour.spectral_radius(L, dt) - spectral_radius_bound(L, dt, Params())) < 1e-12
+        assert abs(api.spectral_radius(L, dt) - spectral_radius_bound(L, dt, Params())) <= 1e-14 * L
 
 
 def test_scalar_error_and_kappa_match_oracle_brute_force():
@@ -21,36 +35,114 @@ def test_scalar_error_and_kappa_match_oracle_brute_force():
     a, b, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, y)
     w = np.linspace(-rho, rho, 1601)
     ref = np.abs(orexi.rexi_sum(a, b, 1j * w) - np.exp(1j * w)).max()
-    la, lb, _, _ = contour.api.rexi_coefficients(contour.api.FN_EXP, N, p0, y)
-    got = contour.scalar_error(la, lb, rho)
-    kref = orexi.kappa(a, b, 1j * np.linspace(-rho, rho, 401)).max()
+    kref = orexi.kappa(a, b, 1j * w).max()
+    la, lb, _, _ = api.rexi_coefficients(api.FN_EXP, N, p0, y)
+    got, kap = api.contour_error(la, lb, rho, 1601)
     # the two evaluations differ only by rounding (order of the sum, last bits of the coefficients)
     assert abs(got - ref) <= 1e-3 * ref + 8 * 2.0 ** -53 * kref
-    assert abs(contour.kappa(la, lb, rho) - kref) <= 1e-12 * kref
+    assert abs(kap - kref) <= 1e-12 * kref
     # far from the rounding floor they agree closely
     a, b, _, _ = orexi.coefficients(orexi.FN_EXP, 64, p0, y)
-    la, lb, _, _ = contour.api.rexi_coefficients(contour.api.FN_EXP, 64, p0, y)
+    la, lb, _, _ = api.rexi_coefficients(api.FN_EXP, 64, p0, y)
     ref = np.abs(orexi.rexi_sum(a, b, 1j * w) - np.exp(1j * w)).max()
-    assert abs(contour.scalar_error(la, lb, rho) - ref) <= 1e-9 * ref
+    assert abs(api.contour_error(la, lb, rho, 1601)[0] - ref) <= 1e-9 * ref
 
 
 @pytest.mark.parametrize("w", [configs.T255_FP32_AT_E, configs.T255_FP64_AT_E], ids=lambda w: w.name)
 def test_equal_error_contours(w):
     E = configs.EQUAL_ERROR_E
-    c = contour.choose(w.L, w.dt, E, w.prec)
-    assert (c.p0, c.N) == (w.p0, w.N)
-    assert abs(c.y - w.y) < 1e-9
-    rho = contour.spectral_radius(w.L, w.dt)
-    # minimal: two poles fewer misses the target at the same shift
+    rho = api.spectral_radius(w.L, w.dt)
+    c = api.choose_contour(rho, E, w.prec)
+    assert (c["p0"], c["N"]) == (w.p0, w.N)
+    assert abs(c["y"] - w.y) < 1e-9
+    # minimal: two poles fewer misses the target at the same shift (oracle evaluation)
     a, b, _, _ = orexi.coefficients(orexi.FN_EXP, w.N - 2, w.p0, w.y)
-    assert contour.predicted_error(a, b, rho, w.prec) > E
+    assert _oracle_predicted(a, b, rho, w.prec) > E
     # the oracle's own coefficients meet the target at the chosen N
     a, b, _, _ = orexi.coefficients(orexi.FN_EXP, w.N, w.p0, w.y)
-    assert contour.predicted_error(a, b, rho, w.prec) <= E
+    assert _oracle_predicted(a, b, rho, w.prec) <= E
 
 
 def test_fp32_floor_needs_more_poles():
     """At E = 1e-4 the FP32 rounding floor u_32 kappa forces a small shift and
-    about four times the poles of FP64 (T255, dt = 3600 s)."""
+    about four times the poles of FP64 (T255, dt = 3600 s); 1e-6 is out of FP32's
+    reach on the shift grid."""
     assert configs.T255_FP32_AT_E.N > 3 * configs.T255_FP64_AT_E.N
-    assert contour.choose(255, 3600.0, 1e-6, 1) is None
+    with pytest.raises(api.RexiError) as ei:
+        api.choose_contour(api.spectral_radius(255, 3600.0), 1e-6, 1)
+    assert ei.value.code == api.REXI_ENUMERIC
+
+
+def test_best_shift_at_fixed_pole_count():
+    """N_fixed: the grid shift whose (oracle-evaluated) predicted error is smallest."""
+    L, dt, N, prec = 127, 3600.0, 300, 1
+    rho = api.spectral_radius(L, dt)
+    c = api.choose_contour(rho, prec=prec, N_fixed=N, p0_grid=[4.0, 6.0, 8.0, 10.0])
+    assert c["N"] == N
+    preds = {}
+    for p0 in (4.0, 6.0, 8.0, 10.0):
+        a, b, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, c["y"])
+        preds[p0] = _oracle_predicted(a, b, rho, prec)
+    assert preds[c["p0"]] <= min(preds.values()) * (1 + 1e-6)
+
+
+def _true_dominance_ratio(L, dt, a_coef, p):
+    """min over poles and chain rows of |diagonal| / (off-diagonal row sum) of the
+    chain systems, built from the oracle's dense operator matrices: eliminating
+    h_k (coupled only to delta_k) from (z I - dt A_m) leaves the delta-row
+    diagonal z - dt A[dd] - dt^2 A[dh] A[hd] / z and the zeta-row diagonal
+    z - dt A[zz]; the off-diagonals are dt times the zeta-delta couplings."""
+    z = -a_coef
+    worst = np.inf
+    for m in range(L + 1):
+        A = operator_matrix(m, L, p)
+        n = L - m + 1
+        for i in range(n):
+            h, ze, de = 3 * i, 3 * i + 1, 3 * i + 2
+            off_d = dt * sum(abs(A[de, 3 * j + 1]) for j in (i - 1, i + 1) if 0 <= j < n)
+            off_z = dt * sum(abs(A[ze, 3 * j + 2]) for j in (i - 1, i + 1) if 0 <= j < n)
+            bd = z - dt * A[de, de] - dt * dt * A[de, h] * A[h, de] / z
+            bz = z - dt * A[ze, ze]
+            if off_d > 0:
+                worst = min(worst, float(np.min(np.abs(bd))) / off_d)
+            if off_z > 0:
+                worst = min(worst, float(np.min(np.abs(bz))) / off_z)
+    return worst
+
+
+@pytest.mark.parametrize("L,dt,N,p0,y", [(31, 3600.0, 128, 10.0, 30.0), (12, 7200.0, 96, 6.0, None)],
+                         ids=["T31-paper", "T12-dt7200"])
+def test_check_contour_accepts_and_bounds_the_true_dominance(L, dt, N, p0, y):
+    p = Params()
+    rho = spectral_radius_bound(L, dt, p)
+    y = y or np.sqrt(2) * 1.05 * rho
+    a, b, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, y)
+    margin = api.check_contour(L, dt, a, b)
+    assert margin > 1.0
+    # the library's margin is a lower bound of the dominance the rows really have
+    assert _true_dominance_ratio(L, dt, a, p) >= margin * (1 - 1e-12)
+
+
+def test_check_contour_rejects_poles_next_to_the_spectrum():
+    """A long step (dt = 6 h at T8: Coriolis couplings dt 2 Omega ~ 3) on a circle
+    through +-1.02 i rho: rows near the ends of the spectrum segment are not
+    diagonally dominant (checked on the oracle's matrices too), so the check
+    refuses the set."""
+    L, dt, N, p0 = 8, 21600.0, 64, 2.0
+    p = Params()
+    rho = spectral_radius_bound(L, dt, p)
+    a, b, _, _ = orexi.coefficients(orexi.FN_EXP, N, p0, 1.02 * rho)
+    assert _true_dominance_ratio(L, dt, a, p) < 1.0
+    with pytest.raises(api.RexiError) as ei:
+        api.check_contour(L, dt, a, b)
+    assert ei.value.code == api.REXI_ENUMERIC
+    assert "diagonally dominant" in str(ei.value)
+
+
+def test_check_contour_rejects_a_contour_missing_the_spectrum():
+    L, dt = 31, 3600.0
+    a, b, _, _ = orexi.coefficients(orexi.FN_EXP, 128, 1.0, 2.0)      # circle through +-2i, rho = 6.1
+    with pytest.raises(api.RexiError) as ei:
+        api.check_contour(L, dt, a, b)
+    assert ei.value.code == api.REXI_ENUMERIC
+    assert "enclose" in str(ei.value)

@@ -167,3 +167,35 @@ def test_psi_sums_against_augmented_expm(fn, k):
     assert err <= 1.01 * worst + floor, (err, worst, floor)
     # and psi_k is not exp: the two differ by O(1)
     assert np.sqrt(_energy(got - linear.expm_step(U0, dt, L, p), L, p) / _energy(U0, L, p)) > 1e-2
+
+
+def test_term_magnitudes_closed_forms():
+    """The per-entry sum of the term magnitudes of Eq. (rexi) (the rounding floor
+    of Section 4.2.2).  Without rotation a mode (l, m) couples h and delta only:
+    (dt A + alpha) restricted to (h, delta) is [[alpha, -dt H], [dt g N / a^2, alpha]]
+    (N = l(l+1)), so an input h0 alone gives the terms beta (alpha, -dt g N/a^2) h0 /
+    (alpha^2 + dt^2 g H N / a^2); h_00 alone gives kappa(0) |h_00|.  And the sum of
+    magnitudes bounds the magnitude of the sum."""
+    L, dt = 6, 1800.0
+    p = Params(Omega=0.0)
+    alpha, beta, _, _ = rexi.coefficients(rexi.FN_EXP, 64, 6.0, 14.0)
+    U0 = np.zeros((3, op.n_modes(L)), dtype=np.complex128)
+    l, m, h0 = 4, 2, 3.0 - 2.0j
+    idx = op.mode_index(L, l, m)
+    U0[0, idx] = h0
+    U0[0, 0] = 7.5
+    M = linear.rexi_term_magnitudes(U0, alpha, beta, dt, L, p)
+    c = dt * dt * p.g * p.H * l * (l + 1) / p.a ** 2
+    den = np.abs(alpha ** 2 + c)
+    want_h = np.sum(np.abs(beta) * np.abs(alpha) / den) * abs(h0)
+    want_d = np.sum(np.abs(beta) / den) * dt * p.g * l * (l + 1) / p.a ** 2 * abs(h0)
+    assert abs(M[0, idx] - want_h) <= 1e-12 * want_h
+    assert abs(M[2, idx] - want_d) <= 1e-12 * want_d
+    assert M[1, idx] == 0.0
+    assert abs(M[0, 0] - rexi.kappa(alpha, beta, 0.0)[0] * 7.5) <= 1e-12 * M[0, 0]
+    # rotation on, a random state: |sum| <= sum |.| entry by entry
+    U1 = random_state(L, 3)
+    q = Params()
+    got = linear.rexi_linear_step(U1, alpha, beta, dt, L, q)
+    M1 = linear.rexi_term_magnitudes(U1, alpha, beta, dt, L, q)
+    assert np.all(np.abs(got) <= M1 * (1 + 1e-12) + 1e-300)

@@ -6,7 +6,12 @@
   f(x) - t^N f(x) + O(t^{2N}) + O(r^N / N!) for entire f, so the REXI error at a
   point is a known closed form -- a wrong sign, offset or factor in alpha or beta
   breaks it;
-* conjugate symmetry and the rounding floor of the FP64-rounded coefficients.
+* conjugate symmetry and the rounding floor of the FP64-rounded coefficients;
+* the cancellation factor kappa(x) = sum |beta_n| / |x + alpha_n| (Section
+  4.2.2) at the centre of the circle, where every |x + alpha_n| = r and the
+  sum is the trapezoidal rule of e^{mu + r cos theta}: e^{mu} I_0(r) = e^{p0}
+  i0e(r) up to the rule's aliasing terms 2 I_N(r) e^{mu}, and elsewhere an
+  mpmath evaluation at 40 digits from the unrounded coefficients.
 """
 import json
 import os
@@ -14,6 +19,7 @@ import os
 import mpmath
 import numpy as np
 import pytest
+import scipy.special
 
 from oracle import rexi
 
@@ -72,3 +78,24 @@ def test_fp64_coefficients_on_imaginary_interval():
     floor = 8 * np.finfo(float).eps * rexi.kappa(alpha, beta, 1j * w)
     assert np.all(err <= 1.05 * geo + floor)
     assert err.max() < 3e-12
+
+
+@pytest.mark.parametrize("N,p0,y", [(128, 10.0, 30.0), (256, 8.0, 67.9), (800, 8.0, 67.91071976436587)])
+def test_kappa_at_the_centre_closed_form(N, p0, y):
+    """kappa(mu) = (1/N) sum_n e^{mu + r cos theta_n} = e^{p0} i0e(r) (I_0 scaled by
+    e^{-r}; mu + r = p0), with aliasing terms below 2 I_N(r)/I_0(r) ~ 1e-30 here."""
+    alpha, beta, r, mu = rexi.coefficients(rexi.FN_EXP, N, p0, y)
+    got = rexi.kappa(alpha, beta, mu)[0]
+    ref = np.exp(p0) * scipy.special.i0e(r)
+    assert abs(got - ref) <= 1e-13 * ref * np.sqrt(N), (got, ref)
+
+
+@pytest.mark.parametrize("x", [0.0, 3.1j, -5.7j, 2.0 + 1.0j])
+def test_kappa_matches_mpmath(x):
+    """kappa against a 40-digit evaluation on the unrounded coefficients."""
+    a_mp, b_mp, _, _ = rexi.coefficients_mp(rexi.FN_EXP, 128, 10.0, 30.0)
+    with mpmath.workdps(40):
+        X = mpmath.mpc(x)
+        ref = float(sum(abs(b) / abs(X + a) for a, b in zip(a_mp, b_mp)))
+    alpha, beta, _, _ = rexi.coefficients(rexi.FN_EXP, 128, 10.0, 30.0)
+    assert abs(rexi.kappa(alpha, beta, x)[0] - ref) <= 1e-13 * ref
