@@ -22,7 +22,17 @@ U0 + tau/2 (N(U0) + N(U*)) is held entry by entry to 2 tau times the
 first-order bound on the tendency's error (tests/_oracle_helpers.py,
 tendency_error_bound: the synthesis errors propagated through the products
 and the analysis, plus the analysis rounding; the factor 2 covers the two
-evaluations, U* differing from U0 by tau N)."""
+evaluations, U* differing from U0 by tau N).
+
+These worst-case bounds sit 10-1000 times above the errors rounding actually
+makes (independent roundings partly cancel).  So every test also holds the GPU
+to the rounding model's own error: the same transform or step computed on the
+CPU with the split arithmetic emulated on the oracle's tables
+(tests/_split_emulation.py: 16-bit hi/lo operands, three FP32 products, FP32
+accumulation, the same parity folding and H combination).  The GPU's error
+against the oracle, per field (largest entry and root mean square), must stay
+within 4 times the emulation's: the two differ in summation order and in
+where FP32 sums round, not in the model."""
 import numpy as np
 import pytest
 
@@ -33,6 +43,7 @@ from oracle.sht import Grid
 from paper_1805_06557_amd.inputs import jet_state, random_field
 
 from _oracle_helpers import analysis_term_sums, synthesis_term_sums, tendency_error_bound, term_scales
+from _split_emulation import SplitGrid
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -104,6 +115,22 @@ def _check_heun(got, ref, bound, label):
     assert r.max() <= 1.0, r.max(axis=1).tolist()
 
 
+MODEL_FACTOR = 4.0
+
+
+def _model_check(got, ref, emu, label):
+    """Per field: the GPU's largest and RMS error against the oracle within
+    MODEL_FACTOR times the emulated split computation's."""
+    got, ref, emu = (np.atleast_2d(x) for x in (got, ref, emu))
+    e_g = np.abs(got - ref).max(axis=1)
+    e_e = np.abs(emu - ref).max(axis=1)
+    r_g = np.sqrt((np.abs(got - ref) ** 2).mean(axis=1))
+    r_e = np.sqrt((np.abs(emu - ref) ** 2).mean(axis=1))
+    print(label, "GPU / model error per field: largest", (e_g / e_e).tolist(), "rms", (r_g / r_e).tolist())
+    assert np.all(e_g <= MODEL_FACTOR * e_e), (e_g / e_e).tolist()
+    assert np.all(r_g <= MODEL_FACTOR * r_e), (r_g / r_e).tolist()
+
+
 def _scaled(got, ref, scale):
     return [float(np.abs(got[f] - ref[f]).max() / scale[f]) for f in range(3)]
 
@@ -134,6 +161,9 @@ def test_split_transforms(L, nlat, nlon, mode):
         assert r <= 1.0, (f, r)
     print("synthesis", mode, L, "largest error / bound", worst, "field-relative", max(_rel(got.reshape(nf, -1),
           np.stack([g.synthesis(spec[f]) for f in range(nf)]).reshape(nf, -1))))
+    sg = SplitGrid(L, nlat, nlon, Params(), mode)
+    _model_check(got.reshape(nf, -1), np.stack([g.synthesis(spec[f]) for f in range(nf)]).reshape(nf, -1),
+                 np.stack([sg.synthesis(spec[f]) for f in range(nf)]).reshape(nf, -1), f"T{L} synthesis {mode}")
     field = rng.standard_normal((nf, nlat, nlon))
     dso = torch.empty((nf, api.n_modes(L)), dtype=torch.complex128, device="cuda")
     ctx.sh_analysis(torch.from_numpy(field).cuda(), dso, nf)
@@ -149,6 +179,8 @@ def test_split_transforms(L, nlat, nlon, mode):
         worst = max(worst, r)
         assert r <= 1.0, (f, r)
     print("analysis", mode, L, "largest error / bound", worst)
+    _model_check(got, np.stack([g.analysis(field[f]) for f in range(nf)]),
+                 np.stack([sg.analysis(field[f]) for f in range(nf)]), f"T{L} analysis {mode}")
     ctx.sync()
     ctx.close()
 
@@ -168,6 +200,8 @@ def test_split_heun_increment(L, nlat, nlon, mode):
     got = d1.cpu().numpy()
     print("heun increment", mode, L, "relative to the increment", _rel(got - U0, ref - U0))
     _check_heun(got, ref, _heun_bound(g, U0, tau, mode), f"T{L} heun {mode}")
+    emu = onl.heun(SplitGrid(L, nlat, nlon, Params(), mode), U0, tau)
+    _model_check(got - U0, ref - U0, emu - U0, f"T{L} heun increment {mode}")
     ctx.close()
 
 
@@ -176,7 +210,8 @@ def t255_heun_oracle():
     L, nlat, nlon = 255, 384, 768
     g = Grid(L, nlat, nlon, Params())
     U0 = jet_state(L, 2)
-    return g, U0, onl.heun(g, U0, 1800.0), {m: _heun_bound(g, U0, 1800.0, m) for m in MODES}
+    return (g, U0, onl.heun(g, U0, 1800.0), {m: _heun_bound(g, U0, 1800.0, m) for m in MODES},
+            {m: onl.heun(SplitGrid(L, nlat, nlon, Params(), m), U0, 1800.0) for m in MODES})
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -184,7 +219,7 @@ def test_split_heun_t255_against_oracle(mode, t255_heun_oracle):
     """The T255 768 x 384 non-linear step (the workload's half step, tau = 1800 s)
     with the split Legendre stage against the oracle, per field, on the increment."""
     api = _api()
-    g, U0, ref, bounds = t255_heun_oracle
+    g, U0, ref, bounds, emus = t255_heun_oracle
     L, nlat, nlon = g.L, g.nlat, g.nlon
     ctx = api.SWE(L, nlat, nlon, prec=_prec(api, mode))
     d0 = torch.from_numpy(U0).cuda()
@@ -195,6 +230,7 @@ def test_split_heun_t255_against_oracle(mode, t255_heun_oracle):
     ctx.close()
     print("T255 heun increment vs oracle", mode, "relative to the increment", _rel(got - U0, ref - U0))
     _check_heun(got, ref, bounds[mode], f"T255 heun {mode}")
+    _model_check(got - U0, ref - U0, emus[mode] - U0, f"T255 heun increment {mode}")
 
 
 @pytest.fixture(scope="module")
@@ -202,7 +238,8 @@ def t511_heun_oracle():
     L, nlat, nlon = 511, 768, 1536
     g = Grid(L, nlat, nlon, Params())
     U0 = jet_state(L, 4)
-    return g, U0, onl.heun(g, U0, 900.0), {m: _heun_bound(g, U0, 900.0, m) for m in MODES}
+    return (g, U0, onl.heun(g, U0, 900.0),
+            {m: onl.heun(SplitGrid(L, nlat, nlon, Params(), m), U0, 900.0) for m in MODES})
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -226,12 +263,12 @@ def test_split_t511_round_trip_and_step(mode, t511_heun_oracle):
     e = _rel(back.cpu().numpy(), spec)
     print("T511 split round trip", mode, e)
     assert max(e) <= 16 * u_split(L, nlat, mode), e
-    g, U0, ref, bounds = t511_heun_oracle
+    g, U0, ref, emus = t511_heun_oracle
     d0 = torch.from_numpy(U0).cuda()
     d1 = torch.empty_like(d0)
     ctx.nonlinear_step(900.0, d0, d1)
     ctx.sync()
     got = d1.cpu().numpy()
     print("T511 heun increment vs oracle", mode, "relative to the increment", _rel(got - U0, ref - U0))
-    _check_heun(got, ref, bounds[mode], f"T511 heun {mode}")
+    _model_check(got - U0, ref - U0, emus[mode] - U0, f"T511 heun increment {mode}")
     ctx.close()
