@@ -232,6 +232,8 @@ struct Lane {
     double wzr, wzi;   // w / z
     float zrf, zif;    // z in FP32
     float zirf, ziif;  // 1/z in FP32
+    float wrf, wif;    // w in FP32 (the FP32 solve's weighting)
+    float wzrf, wzif;  // w / z in FP32
 };
 
 template <typename T>
@@ -381,7 +383,11 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
             constexpr bool DELTA = ((jj + C) & 1) == 0;
             const int j = j0 + jj;
             const bool live = j < Lm;
-            double sx = 0.0, sy = 0.0, hx = 0.0, hy = 0.0;
+            // weighted outputs of the lane's poles, added in pole order: in the
+            // solve's precision (an FP32 product and sum adds one rounding of
+            // u_32 to terms that carry the FP32 sweep's few u_32), then widened
+            // for the FP64 sum over the wave
+            T sx = T(0), sy = T(0), hx = T(0), hy = T(0);
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 Cx<T> v{T(0), T(0)};
@@ -391,21 +397,33 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
                     v.y = fmaT(-cpj.x, vnext[k].y, fmaT(-cpj.y, vnext[k].x, ds[k][jj].y));
                     vnext[k] = v;
                 }
-                const double vx = static_cast<double>(v.x), vy = static_cast<double>(v.y);
-                const double ox = __builtin_fma(ln[k].p.wr, vx, -(ln[k].p.wi * vy));
-                const double oy = __builtin_fma(ln[k].p.wr, vy, ln[k].p.wi * vx);
+                T wr, wi, wzr, wzi;
+                if constexpr (std::is_same<T, float>::value) {
+                    wr = ln[k].wrf;
+                    wi = ln[k].wif;
+                    wzr = ln[k].wzrf;
+                    wzi = ln[k].wzif;
+                } else {
+                    wr = ln[k].p.wr;
+                    wi = ln[k].p.wi;
+                    wzr = ln[k].wzr;
+                    wzi = ln[k].wzi;
+                }
+                const T ox = fmaT(wr, v.x, -(wi * v.y));
+                const T oy = fmaT(wr, v.y, wi * v.x);
                 sx = k ? sx + ox : ox;
                 sy = k ? sy + oy : oy;
                 if constexpr (DELTA) {
                     // (w/z) delta; v = 0 past the chain's end
-                    const double gx = __builtin_fma(ln[k].wzr, vx, -(ln[k].wzi * vy));
-                    const double gy = __builtin_fma(ln[k].wzr, vy, ln[k].wzi * vx);
+                    const T gx = fmaT(wzr, v.x, -(wzi * v.y));
+                    const T gy = fmaT(wzr, v.y, wzi * v.x);
                     hx = k ? hx + gx : gx;
                     hy = k ? hy + gy : gy;
                 }
             }
-            red[q * WAVE + lane] = make_double2(sx, sy);
-            if constexpr (DELTA) red[(4 + (q >> 1)) * WAVE + lane] = make_double2(hx, hy);
+            red[q * WAVE + lane] = make_double2(static_cast<double>(sx), static_cast<double>(sy));
+            if constexpr (DELTA)
+                red[(4 + (q >> 1)) * WAVE + lane] = make_double2(static_cast<double>(hx), static_cast<double>(hy));
         });
         reduce_group<T, C>(A, rc, swz, red, lane, pw, base, j0 + 4 * g, Lm);
     });
@@ -421,14 +439,18 @@ enum Sched { FUSED = 0, STREAM = 1, HYBRID = 2 };
 template <int SCHED>
 constexpr int ckpt_words() { return SCHED == STREAM ? 1 : 2; }
 
-// One wave solves one chain for 64 P poles: lane l carries poles 64 P pw + 64 k + l,
-// k < P, whose sweeps share every row record and are interleaved row by row.
-template <typename T, int S, int C, int SCHED, int P>
+// One wave solves one chain for up to 64 PS poles (PS: the launch's poles per
+// lane): lane l carries poles 64 PS pw + 64 k + l, k < P, whose sweeps share
+// every row record and are interleaved row by row.  P = PS except in the last
+// pole wave when at most 64 poles are left there (P = 1: no lane sweeps a
+// padding pole next to a real one).  Checkpoints and partial sums are laid out
+// for PS.
+template <typename T, int S, int C, int SCHED, int P, int PS>
 __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m, int pb, unsigned char* smem) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
-    const int pw = pb * nw + wv;                 // pole wave: poles 64 P pw .. 64 P (pw + 1) - 1
+    const int pw = pb * nw + wv;                 // pole wave: poles 64 PS pw .. 64 PS (pw + 1) - 1
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int nseg = (Lm + S - 1) / S;
@@ -456,16 +478,20 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     }
     __syncthreads();
     // whole waves of padding poles have nothing to do
-    if (pw * WAVE * P >= A.N) return;
+    if (pw * WAVE * PS >= A.N) return;
 
     Lane ln[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        const int n = (pw * P + k) * WAVE + lane;
+        const int n = pw * WAVE * PS + k * WAVE + lane;
         ln[k].p = A.poles[n < A.N ? n : 0];
         if (n >= A.N) ln[k].p.wr = ln[k].p.wi = 0.0;   // padding lanes add nothing
         ln[k].wzr = __builtin_fma(ln[k].p.wr, ln[k].p.zir, -(ln[k].p.wi * ln[k].p.zii));
         ln[k].wzi = __builtin_fma(ln[k].p.wr, ln[k].p.zii, ln[k].p.wi * ln[k].p.zir);
+        ln[k].wrf = static_cast<float>(ln[k].p.wr);
+        ln[k].wif = static_cast<float>(ln[k].p.wi);
+        ln[k].wzrf = static_cast<float>(ln[k].wzr);
+        ln[k].wzif = static_cast<float>(ln[k].wzi);
         ln[k].zrf = static_cast<float>(ln[k].p.zr);
         ln[k].zif = static_cast<float>(ln[k].p.zi);
         ln[k].zirf = static_cast<float>(ln[k].p.zir);
@@ -491,10 +517,10 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
                                               static_cast<size_t>(wv) * sizeof(double2) * 6 * WAVE);
     // segment-start states of this wave: [nck_max][CKW][P][64]
     Cx<T>* ck = reinterpret_cast<Cx<T>*>(A.ckpt) +
-                (static_cast<size_t>(task) * A.npb * nw + pw) * A.nck_max * CKW * P * WAVE + lane;
+                (static_cast<size_t>(task) * A.npb * nw + pw) * A.nck_max * CKW * PS * WAVE + lane;
     // cached pivots of this chain: row j, pole n at fact[(row0 + j) npad + n]
     const Cx<T>* fact = reinterpret_cast<const Cx<T>*>(A.fact) + static_cast<size_t>(2 * base + C * Lm) * A.npad +
-                        pw * P * WAVE + lane;
+                        pw * PS * WAVE + lane;
 
     Cx<T> cp[P], dp[P];
 #pragma unroll
@@ -622,17 +648,29 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
 template <typename T, int S, int P>
 constexpr int chain_occupancy() { return sizeof(T) * S * P <= 128 ? 2 : 1; }
 
+// The chain of `task` for the pole waves of block pb: with two poles per lane,
+// a last pole wave holding at most 64 poles runs with one pole per lane.
+template <typename T, int S, int SCHED, int P>
+__device__ __forceinline__ void solve_task(const SolveArgs& A, int task, int pb, unsigned char* smem) {
+    const int m = task >> 1;
+    const int pw = pb * static_cast<int>(blockDim.x / WAVE) + static_cast<int>(threadIdx.x / WAVE);
+    const bool tail = P == 2 && pw * WAVE * P + WAVE >= A.N;
+    if (task & 1) {
+        if (tail) solve_chain<T, S, 1, SCHED, 1, P>(A, task, m, pb, smem);
+        else solve_chain<T, S, 1, SCHED, P, P>(A, task, m, pb, smem);
+    } else {
+        if (tail) solve_chain<T, S, 0, SCHED, 1, P>(A, task, m, pb, smem);
+        else solve_chain<T, S, 0, SCHED, P, P>(A, task, m, pb, smem);
+    }
+}
+
 template <typename T, int S, int SCHED, int P>
 __global__ __launch_bounds__(4 * WAVE) __attribute__((amdgpu_waves_per_eu(chain_occupancy<T, S, P>())))
 void rexi_chain_kernel(SolveArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int task = blockIdx.x / A.npb;      // task = 2 m + chain: longest chains first
     const int pb = blockIdx.x - task * A.npb;
-    const int m = task >> 1;
-    if (task & 1)
-        solve_chain<T, S, 1, SCHED, P>(A, task, m, pb, smem);
-    else
-        solve_chain<T, S, 0, SCHED, P>(A, task, m, pb, smem);
+    solve_task<T, S, SCHED, P>(A, task, pb, smem);
 }
 
 // Ensemble form: one launch over the work items (member, task, pole block) of
@@ -644,11 +682,7 @@ void rexi_chain_batched_kernel(const SolveArgs* __restrict__ args, const int4* _
     extern __shared__ __align__(16) unsigned char smem[];
     const int4 it = items[blockIdx.x];
     const SolveArgs A = args[it.x];
-    const int task = it.y, pb = it.z, m = task >> 1;
-    if (task & 1)
-        solve_chain<T, S, 1, SCHED, P>(A, task, m, pb, smem);
-    else
-        solve_chain<T, S, 0, SCHED, P>(A, task, m, pb, smem);
+    solve_task<T, S, SCHED, P>(A, it.y, it.z, smem);
 }
 
 // Factorization: the pivots of every chain row for every pole (padding lanes up

@@ -115,9 +115,11 @@ def test_schedule_and_shape_do_not_change_bits(prec):
     """Every schedule (pivots recomputed, streamed from the cached factorization,
     or both), segment length and workgroup size performs the same operations in
     the same order on each (pole, row), and the pole sum is grouped the same
-    way, so all give bit-identical results; repeated calls are bit-identical."""
+    way, so all give bit-identical results; repeated calls are bit-identical.
+    N = 180 leaves 52 poles for the second wave of two poles per lane, which then
+    runs with one pole per lane."""
     api = _api()
-    L, N, dt = 57, 200, 3600.0
+    L, N, dt = 57, 180, 3600.0
     alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, N, 8.0, 16.0)
     U0 = random_state(L, 8)
     refs = []
@@ -131,9 +133,14 @@ def test_schedule_and_shape_do_not_change_bits(prec):
                                    poles_per_lane=P)
                     assert np.array_equal(got, ref), (P, solver, S, W)
         refs.append(ref)
-    # interleaving two poles per lane only regroups the FP64 pole sum
+    # two poles per lane regroup the pole sum: each lane adds its poles' weighted
+    # outputs in the solve's precision before the FP64 sum over the wave
     scale = np.abs(refs[0]).max(axis=1, keepdims=True)
-    assert np.all(np.abs(refs[1] - refs[0]) <= 1e-13 * scale)
+    if prec == 0:
+        tol = 1e-13
+    else:
+        tol = 3 * U32 * _kappa_max(alpha, beta, spectral_radius_bound(L, dt, Params()))
+    assert np.all(np.abs(refs[1] - refs[0]) <= tol * scale)
 
 
 @pytest.mark.parametrize("solver", [2, 3])
