@@ -459,6 +459,71 @@ def stream_arm(w, reps):
     return out
 
 
+def split_mfma_flops_batch(L, nlat, nf):
+    """Matrix-core flops of one scalar-field split Legendre launch over nf fields
+    (8 fields = 16 real columns per 16-column product; three bf16 products per
+    16x16x16 tile and K step, padding rows and latitudes included)."""
+    hpad, rows = _split_blocks(L, nlat)
+    groups = (nf + 7) // 8
+    return groups * 3 * (hpad // 16) * (rows // 16) * 2 * 16 * 16 * 16
+
+
+def legendre_batch_arm(reps, nf=64):
+    """The Legendre stage of the transforms of many fields on one grid (T255 on
+    768 x 384, nf scalar fields): synthesis and analysis with the split-BF16
+    matrix-core kernels and with the FP64 kernels, HIP events around the
+    Legendre launches only.  Reports the matrix-core rate against the 2.5 PFLOP/s
+    dense bf16 peak and the algorithmic bytes (table once per 8-field group,
+    spectra in or out, Fourier coefficients out or in, complex128)."""
+    import numpy as np
+    import torch
+
+    from paper_1805_06557_amd import api
+    from paper_1805_06557_amd.inputs import random_field
+
+    L, nlat, nlon = 255, 384, 768
+    rng = np.random.default_rng(77)
+    spec = torch.from_numpy(np.stack([random_field(L, rng, 1.0) for _ in range(nf)])).cuda()
+    grid = torch.empty((nf, nlat, nlon), dtype=torch.float64, device="cuda")
+    back = torch.empty_like(spec)
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"T{L} on {nlon}x{nlat}, {nf} scalar fields per call"}
+    four_bytes = nf * (L + 1) * nlat * 16
+    spec_bytes = nf * n_modes(L) * 16
+    for key, prec in (("bf16_split", api.PREC_BF16_SPLIT), ("fp64", 0)):
+        ctx = api.SWE(L, nlat, nlon, prec=prec)
+        ctx.sh_synthesis(spec, grid, nf, stream)
+        ctx.sh_analysis(grid, back, nf, stream)
+        ctx.sync()
+        ctx.profile_kernels([api.KERNEL_LEG_SYNTH, api.KERNEL_LEG_ANAL])
+        for _ in range(reps):
+            ctx.sh_synthesis(spec, grid, nf, stream)
+            ctx.sh_analysis(grid, back, nf, stream)
+        ms_s, n_s = ctx.profile_read(api.KERNEL_LEG_SYNTH)
+        ms_a, n_a = ctx.profile_read(api.KERNEL_LEG_ANAL)
+        ctx.sync()
+        ctx.close()
+        syn, ana = ms_s / max(n_s, 1), ms_a / max(n_a, 1)
+        entry = {"synth_ms": syn, "anal_ms": ana}
+        if prec:
+            fl = split_mfma_flops_batch(L, nlat, nf)
+            tb = split_table_bytes(L, nlat) * ((nf + 7) // 8)
+            entry.update({
+                "mfma_flops_per_launch": fl, "peak_TFLOP_s": PEAK_BF16_MFMA,
+                "synth_TFLOP_s": fl / (syn * 1e-3) / 1e12, "anal_TFLOP_s": fl / (ana * 1e-3) / 1e12,
+                "synth_frac": fl / (syn * 1e-3) / 1e12 / PEAK_BF16_MFMA,
+                "anal_frac": fl / (ana * 1e-3) / 1e12 / PEAK_BF16_MFMA,
+                "table_bytes_per_launch": tb,
+            })
+        else:
+            tb = 0
+        io = four_bytes + spec_bytes
+        entry.update({"algorithmic_bytes_per_launch": io + tb, "fourier_and_spectral_bytes": io,
+                      "synth_GB_s": (io + tb) / (syn * 1e-3) / 1e9, "anal_GB_s": (io + tb) / (ana * 1e-3) / 1e9})
+        out[key] = entry
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -479,6 +544,8 @@ def main():
                     help="autotune the REXI solve of the main workload (default: the library's launch shape)")
     ap.add_argument("--no-arms", action="store_true",
                     help="skip the FP32-vs-FP64 equal-error arm and the ensemble arm")
+    ap.add_argument("--only-legendre-batch", action="store_true",
+                    help="only run the batched Legendre arm (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is designed but not built "
@@ -500,6 +567,9 @@ def main():
     from paper_1805_06557_amd import api, configs
     from paper_1805_06557_amd.inputs import jet_state
 
+    if args.only_legendre_batch:
+        print(json.dumps({"legendre_batched": legendre_batch_arm(max(3, args.steps // 4))}))
+        return
     w = configs.ALL[args.workload]
     alpha, beta, _, _ = api.rexi_coefficients(api.FN_EXP, w.N, w.p0, w.y)
     full = args.stage == "auto" and w.nlat > 0
@@ -651,6 +721,7 @@ def main():
     ctx.close()
     if not args.no_arms:
         out["roofline_stream"] = stream_arm(w, max(3, args.steps // 2))
+        out["legendre_batched"] = legendre_batch_arm(max(3, args.steps // 4))
         out["fp32_vs_fp64_at_equal_error"] = equal_error_arm(max(3, args.steps // 2),
                                                              with_oracle=not args.no_cpu_baseline)
         out["ensemble"] = ensemble_arm(max(3, args.steps // 2))
