@@ -236,11 +236,39 @@ struct MfmaArgs {
     double2* __restrict__ out;
     double c0, c1;
     unsigned* status;                     // non-finite outputs set a STATUS_* flag
+    int ntg, ng;                          // KIND 0: latitude-tile groups, 8-field groups (split_item)
 };
 
+// The (order m, latitude-tile group, 8-field group) of a workgroup.  KIND 1:
+// (blockIdx.x, blockIdx.y, 0).  KIND 0: a one-dimensional grid in which the ng
+// field groups of one (order, tile group) pair p share an XCD (workgroup b runs
+// on XCD b mod 8) and are dispatched within a window of 8 ng workgroups, so the
+// table tiles they all read come from HBM once and then from that XCD's L2:
+// b = 8 (ng (p / 8) + g) + p mod 8, pairs ordered by order (longest first).
+// Returns false for the padding workgroups of the last window.
+template <int KIND>
+__device__ __forceinline__ bool split_item(const MfmaArgs& A, int& m, int& tg, int& g) {
+    if constexpr (KIND == 1) {
+        m = blockIdx.x;
+        tg = blockIdx.y;
+        g = 0;
+        return true;
+    } else {
+        const int b = blockIdx.x;
+        const int slot = b >> 3;
+        g = slot % A.ng;
+        const int p = 8 * (slot / A.ng) + (b & 7);
+        m = p / A.ntg;
+        tg = p - m * A.ntg;
+        return m <= A.L;
+    }
+}
+
+__host__ __device__ constexpr int split_grid_size(int pairs, int ng) { return (pairs + 7) / 8 * 8 * ng; }
+
 // ---------------------------------------------------------------- synthesis --
-// Workgroup: order m = blockIdx.x, 4 waves = 4 tiles of 16 northern latitudes
-// (tile 4 blockIdx.y + wave); KIND 0: fields 8 blockIdx.z .. 8 blockIdx.z + 7.
+// Workgroup (split_item): order m, 4 waves = 4 tiles of 16 northern latitudes
+// (tile 4 tg + wave); KIND 0: fields 8 g .. 8 g + 7.
 // LDS: the B operand X[parity][column][row] (rows in groups of four).
 // KIND 1 columns: h, zeta, U, V (real and imaginary parts), with
 //   U_l = -i m delta_l a/N_l + hA_{l-1} zeta_{l-1} a/N_{l-1} + hB_{l+1} zeta_{l+1} a/N_{l+1},
@@ -251,13 +279,14 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short xs[];
     constexpr bool SCALED = std::is_same<E, F16>::value;
     __shared__ float sred[4 * 16], sc[16];
-    const int m = blockIdx.x;
+    int m, tg, g;
+    if (!split_item<KIND>(A, m, tg, g)) return;
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int rowlen = lds_row(A.kmax);             // shorts per LDS column row
     unsigned short* xp = xs;                        // [2][16][rowlen]
-    const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
+    const int f0 = 8 * g;
     const double dm = static_cast<double>(m);
     // the 16 column values of staging row rp (parity, row), zero where there is
     // no degree or column
@@ -358,7 +387,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     }
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
-    const int tile = blockIdx.y * 4 + threadIdx.x / WAVE;
+    const int tile = tg * 4 + threadIdx.x / WAVE;
     if (tile * 16 >= A.hpad) return;
     const int kq = lane >> 4;                       // K quarter of this lane
     f32x4 acc[2];
@@ -416,12 +445,12 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 }
 
 // ----------------------------------------------------------------- analysis --
-// Workgroup: order m = blockIdx.x, ANA_WAVES waves taking the row tiles of 16
+// Workgroup (split_item, one tile group): order m, ANA_WAVES waves taking the row tiles of 16
 // degrees of one parity (even-parity tiles first) in turn.  LDS: the B operand
 // Y[fold][column][latitude] (latitudes in groups of four), fold 0 =
 // F(mu) + F(-mu), fold 1 = F(mu) - F(-mu), weighted; rows of a parity pair
 // with the fold of that parity.  KIND 0: O = sum_j w_j Pbar F (fields
-// 8 blockIdx.z ..), written from the accumulators.  KIND 1: the non-linear
+// 8 g ..), written from the accumulators.  KIND 1: the non-linear
 // tendency from the Fourier coefficients of hU, hV, zU, zV, KE:
 //   columns 0-7 (Pbar terms): m hU.y, -m hU.x, m zU.y, -m zU.x, -m zV.y, m zV.x, KE.x, KE.y
 //   columns 8-13 (H terms):   hV.x, hV.y, zV.x, zV.y, zU.x, zU.y
@@ -437,14 +466,15 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     extern __shared__ __align__(16) unsigned short ys[];
     constexpr bool SCALED = std::is_same<E, F16>::value;
     __shared__ float sred[ANA_WAVES * 16], sc[16];
-    const int m = blockIdx.x;
+    int m, tg, g;
+    if (!split_item<KIND>(A, m, tg, g)) return;
     const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int rowlen = lds_row(A.hpad);
     unsigned short* yp = ys;                                        // [2][16][rowlen]
     float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
-    const int f0 = KIND == 0 ? 8 * blockIdx.z : 0;
+    const int f0 = 8 * g;
     const double dm = static_cast<double>(m);
     // KIND 1: the epilogue's inputs that do not depend on the products (H
     // coefficients, l(l+1)/a^2, U0 + c1 Nprev) of the thread's first EPI items
@@ -715,7 +745,9 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.kmax));
     if (ctx->prec & REXI_PREC_FP16_SPLIT) lds += sizeof(float) * 16 * 2 * static_cast<size_t>(A.kmax);
     const int tiles = A.hpad / 16;
-    const dim3 grid(ctx->L + 1, (tiles + 3) / 4, kind == 0 ? (nf + 7) / 8 : 1);
+    A.ntg = (tiles + 3) / 4;
+    A.ng = (nf + 7) / 8;
+    const dim3 grid = kind == 0 ? dim3(split_grid_size((ctx->L + 1) * A.ntg, A.ng)) : dim3(ctx->L + 1, A.ntg, 1);
     const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
     const void* fn = kind == 0 ? (f16 ? reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, F16>)
                                       : reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, Bf16>))
@@ -749,7 +781,9 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     size_t zbytes = kind == 1 ? sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax) : 0;
     if (ctx->prec & REXI_PREC_FP16_SPLIT) zbytes = std::max(zbytes, sizeof(float) * 16 * 2 * static_cast<size_t>(A.hpad));
     lds += zbytes;
-    const dim3 grid(ctx->L + 1, 1, kind == 0 ? (nf + 7) / 8 : 1);
+    A.ntg = 1;
+    A.ng = (nf + 7) / 8;
+    const dim3 grid = kind == 0 ? dim3(split_grid_size(ctx->L + 1, A.ng)) : dim3(ctx->L + 1, 1, 1);
     const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
     const void* fn = kind == 0 ? (f16 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0, F16>)
                                       : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<0, Bf16>))
