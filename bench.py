@@ -49,18 +49,20 @@ STREAM_BYTES_PER_POLE_UNKNOWN = {True: 16, False: 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each
 # scaled by the same counter on a copy of known size (the chain-kernel summary under profiles/).
 # Valid only for the kernel source (sha256) and launch shape they were taken with.
-_D = "9f71a32914c9207d128579e9224d08fbb979255e00fa0c54394a1d153ad27fd8"
+_D = "10a5fdc7883d061b150f57c2c5ca05fa6001112812081432dc34c35d82cc23ae"
 MEASURED_TRAFFIC = {
     # FP32 fused solve at T255, N = 800 (the same launch in the FP32 workloads:
-    # only the Legendre stage around it differs): 117.1 MB read + 128.8 MB written
-    ("T255-fp32", _D, (1, 8, 4, 2)): 117.1e6 + 128.8e6,
-    ("T255-fp32-bf16", _D, (1, 8, 4, 2)): 117.1e6 + 128.8e6,
-    ("T255-fp32-fp16", _D, (1, 8, 4, 2)): 117.1e6 + 128.8e6,
-    # FP64 fused solve at T255, N = 800: 223.0 MB read + 235.6 MB written
-    ("T255-fp64", _D, (1, 8, 4, 2)): 223.0e6 + 235.6e6,
-    # streaming schedule at T255, N = 800: FP32 984.2 MB + 79.8 MB, FP64 1972.0 MB + 133.3 MB
-    ("T255-fp32-bf16-stream-fp32", _D, (2, 8, 4, 2)): 984.2e6 + 79.8e6,
-    ("T255-fp32-bf16-stream-fp64", _D, (2, 8, 4, 2)): 1972.0e6 + 133.3e6,
+    # only the Legendre stage around it differs): 110.0 MB read + 121.2 MB written
+    ("T255-fp32", _D, (1, 8, 4, 2)): 110.0e6 + 121.2e6,
+    ("T255-fp32-bf16", _D, (1, 8, 4, 2)): 110.0e6 + 121.2e6,
+    ("T255-fp32-fp16", _D, (1, 8, 4, 2)): 110.0e6 + 121.2e6,
+    # FP64 fused solve at T255, N = 800: 207.5 MB read + 220.3 MB written
+    ("T255-fp64", _D, (1, 8, 4, 2)): 207.5e6 + 220.3e6,
+    # FP64 fused solve at T511, N = 2000: 2132.7 MB read + 2253.9 MB written
+    ("T511-fp64", _D, (1, 8, 4, 2)): 2132.7e6 + 2253.9e6,
+    # streaming schedule at T255, N = 800: FP32 915.9 MB + 75.1 MB, FP64 1830.8 MB + 125.5 MB
+    ("T255-fp32-bf16-stream-fp32", _D, (2, 8, 4, 2)): 915.9e6 + 75.1e6,
+    ("T255-fp32-bf16-stream-fp64", _D, (2, 8, 4, 2)): 1830.8e6 + 125.5e6,
 }
 
 
