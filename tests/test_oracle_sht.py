@@ -145,3 +145,51 @@ def test_solid_body_velocity_closed_form():
     cos2 = (g.sint ** 2)[:, None]
     np.testing.assert_allclose(U, u0 * cos2 * np.ones((1, nlon)), atol=1e-12 * u0)
     np.testing.assert_allclose(V, 0.0, atol=1e-12 * u0)
+
+
+def _three_halves_grid(L):
+    """Smallest Gauss grid on which products of two fields of truncation L are
+    analysed without aliasing (Section 3.2): 2 nlat - 1 >= 3L in latitude,
+    nlon > 3L (even) in longitude."""
+    nlat = (3 * L + 2) // 2
+    nlon = 3 * L + 1
+    return nlat, nlon + nlon % 2
+
+
+@pytest.mark.parametrize("L", [10, 21, 31])
+def test_products_alias_free_on_three_halves_grid(L):
+    """The pseudo-spectral N(U) (products h V, zeta V and V.V/2 formed on the
+    grid, Section 3.2) on the 3/2-rule grid equals N(U) on a grid twice as fine
+    in both directions: the Gauss quadrature of the vector terms, weighted by
+    1/(1 - mu^2), is exact there as well.  The bar is rounding amplified by
+    l(l+1) in the kinetic-energy term.  One latitude or two longitudes fewer
+    must alias (the check can fail)."""
+    from oracle import nonlinear as onl
+    from paper_1805_06557_amd.inputs import random_state
+    p = Params()
+    nlat, nlon = _three_halves_grid(L)
+    U = random_state(L, 5)
+    fine = onl.tendency(Grid(L, 2 * nlat, 2 * nlon, p), U)
+
+    def rel(t):
+        return [float(np.abs(t[f] - fine[f]).max() / np.abs(fine[f]).max()) for f in range(3)]
+    bar = max(1e-14, 1e-15 * L * (L + 1))
+    assert max(rel(onl.tendency(Grid(L, nlat, nlon, p), U))) <= bar
+    assert min(rel(onl.tendency(Grid(L, nlat - 1, nlon, p), U))) > 1e3 * bar
+    assert min(rel(onl.tendency(Grid(L, nlat, nlon - 2, p), U))) > 1e3 * bar
+    rng = np.random.default_rng(L)
+    a, b = random_field(L, rng, 1.0), random_field(L, rng, 1.0)
+    g1, g2 = Grid(L, nlat, nlon, p), Grid(L, 2 * nlat, 2 * nlon, p)
+    s1 = g1.analysis(g1.synthesis(a) * g1.synthesis(b))
+    s2 = g2.analysis(g2.synthesis(a) * g2.synthesis(b))
+    assert np.abs(s1 - s2).max() <= 1e-14 * np.abs(s2).max()
+
+
+def test_workload_grids_meet_three_halves_rule():
+    from paper_1805_06557_amd import configs
+    grids = [w for w in configs.ALL.values() if getattr(w, "nlat", 0)]
+    assert grids
+    for w in grids:
+        if w.nlat:
+            nlat, nlon = _three_halves_grid(w.L)
+            assert w.nlat >= nlat and w.nlon >= nlon, w.name
