@@ -241,8 +241,9 @@ int to_fourier(swe_ctx* ctx, int kind, const double* spec, int nf, hipStream_t s
 // grid `gout`; mode 2: non-linear products into ctx->d_fout).
 int ring_from_part(swe_ctx* ctx, int mode, double* gout, int nf, hipStream_t stream, double two_omega = 0.0) {
     const bool split = split_legendre(ctx);
+    // the split synthesis of the state (kind 1, which mode 2 follows) is latitude-major
     return launch_ring(ctx, mode, ctx->d_part, split ? nullptr : ctx->d_segbase, split ? ctx->L + 1 : ctx->nseg,
-                       ctx->d_fout, nullptr, gout, nf, stream, two_omega);
+                       ctx->d_fout, nullptr, gout, nf, stream, two_omega, split && mode == 2);
 }
 
 // Fourier coefficients (ctx->d_fout) -> spectral fields or the Runge-Kutta update.

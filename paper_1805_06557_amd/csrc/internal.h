@@ -283,8 +283,10 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
                          const double* Nprev, double* Nsave, double* out, double c0, double c1,
                          hipStream_t stream);
 // Split-precision (bf16 hi/lo, matrix-core) Legendre stage: tables and the two
-// directions.  The synthesis writes the Fourier coefficients [nf][L+1][nlat]:
-// one partial row per order (the ring kernel reads them with segbase = nullptr).
+// directions.  The synthesis writes the Fourier coefficients of kind 0 (nf
+// fields) order-major [nf][L+1][nlat] and those of kind 1 (the state)
+// latitude-major [3][nlat][L+1] (the ring kernel reads a latitude's orders
+// contiguously); one partial per order either way (segbase = nullptr).
 int build_split_tables(swe_ctx* ctx, hipStream_t stream);
 int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, double* four, int nf,
                                 hipStream_t stream);
@@ -317,7 +319,10 @@ int ring_plan(int M, std::vector<int>& radix);
 // Twiddles of every pass of that plan, pass-major ([M] complex).
 int ring_twiddles(int M, const std::vector<int>& radix, std::vector<double>& tw);
 // mode 0: Fourier -> grid (nf fields); 1: grid -> Fourier; 2: non-linear products.
+// The partials are [nf][nseg][nlat] (segment-major), or with lat_major
+// [nf][nlat][L+1] (one per order, nseg = L+1, segbase = nullptr).
 int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
-                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega = 0.0);
+                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega = 0.0,
+                bool lat_major = false);
 
 }  // namespace rexi

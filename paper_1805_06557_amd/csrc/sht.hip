@@ -436,12 +436,15 @@ struct RingArgs {
     const double* __restrict__ mu;     // [half] sin(latitude), northern
     const int* __restrict__ radix;     // [npass]
     int npass, L, nlat, nlon, half;
-    // inverse input: synthesis partials [nf_in][nseg][nlat]; the Fourier
-    // coefficient F_m of a latitude is the sum over segments segbase[m] ..
-    // segbase[m + 1] - 1
+    // inverse input: synthesis partials, element (field f, segment g,
+    // latitude j) at f pfs + g pgs + j pjs ([nf_in][nseg][nlat], or
+    // [nf_in][nlat][L+1] latitude-major); the Fourier coefficient F_m of a
+    // latitude is the sum over segments segbase[m] .. segbase[m + 1] - 1
     const double2* __restrict__ part;
     const int* __restrict__ segbase;   // [L+2]; nullptr: one segment per order (segbase[m] = m)
     int nseg;
+    long long pfs;
+    int pgs, pjs;
     double2* __restrict__ fout;        // Fourier coefficients [nf_out][L+1][nlat] (order-major)
     const double* __restrict__ gin;    // grid input  [nf][nlat][nlon] (forward-only mode)
     double* __restrict__ gout;         // grid output [nf][nlat][nlon] (inverse-only mode)
@@ -555,36 +558,44 @@ __host__ __device__ constexpr int ring_radix(int rem) {
 }
 
 // One Stockham pass of radix R over the M complex values of the wave's LDS
-// array x (padded), in place: every lane first reads and transforms all its
-// butterflies, then writes them.  Ns = product of the radices already applied;
-// the pass's twiddles e^{-2 pi i t k / (Ns R)} are tw[Ns - 1 + (t - 1) Ns + k]
-// (consecutive k, so consecutive lanes read consecutive entries).  MC, NSC:
-// compile-time M and Ns (0: runtime).
+// array x (padded), in place: every lane first reads all its butterflies'
+// values and twiddles (lanes past the last butterfly read butterfly 0's and
+// discard the result), then transforms them, then writes them.  Ns = product
+// of the radices already applied; the pass's twiddles e^{-2 pi i t k / (Ns R)}
+// are tw[Ns - 1 + (t - 1) Ns + k] (consecutive k, so consecutive lanes read
+// consecutive entries).  MC, NSC: compile-time M and Ns (0: runtime).
 template <int R, bool INV, int MC, int NSC>
 __device__ __forceinline__ void wave_pass(double2* x, int Mr, int Nsr, const double2* tw, int lane) {
     const int M = MC > 0 ? MC : Mr;
     const int Ns = NSC > 0 ? NSC : Nsr;
     const int nb = M / R;
     constexpr int BPL = ((MC > 0 ? MC : RING_MMAX_RT) / R + WAVE - 1) / WAVE;   // butterflies per lane
+    constexpr bool TW = NSC != 1;                                              // the first pass has none
     lane = opaque_lane(lane);
-    double2 v[BPL][R];
+    double2 v[BPL][R], w[BPL][R];
 #pragma unroll
     for (int b = 0; b < BPL; ++b) {
-        const int jb = lane + b * WAVE;
-        if (jb < nb) {
-            const int k = jb % Ns;
+        const int jb0 = lane + b * WAVE;
+        const int jb = jb0 < nb ? jb0 : 0;
+        const int k = jb % Ns;
 #pragma unroll
-            for (int t = 0; t < R; ++t) {
-                double2 val = x[pad8(jb + t * nb)];
-                if (t > 0 && (NSC != 1)) {
-                    double2 w = tw[Ns - 1 + (t - 1) * Ns + k];
-                    if (INV) w.y = -w.y;
-                    val = cmul(val, w);
-                }
-                v[b][t] = val;
-            }
-            dft<R, INV>(v[b]);
+        for (int t = 0; t < R; ++t) {
+            v[b][t] = x[pad8(jb + t * nb)];
+            if (TW && t > 0) w[b][t] = tw[Ns - 1 + (t - 1) * Ns + k];
         }
+    }
+    __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of the arithmetic
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+        if (TW) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                double2 wt = w[b][t];
+                if (INV) wt.y = -wt.y;
+                v[b][t] = cmul(v[b][t], wt);
+            }
+        }
+        dft<R, INV>(v[b]);
     }
     wave_sync();
 #pragma unroll
@@ -638,25 +649,37 @@ __device__ __forceinline__ void wave_fft(double2* x, const RingArgs& A, const do
 // every order the lane holds is loaded before any is added).
 template <int MC>
 __device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j, double2* x, int lane) {
-    const double2* pf = A.part + static_cast<size_t>(f) * A.nseg * A.nlat + j;
+    const double2* pf = A.part + f * A.pfs + static_cast<long long>(j) * A.pjs;
     lane = opaque_lane(lane);
     if constexpr (MC > 0) {
         constexpr int MPL = (MC + WAVE - 1) / WAVE;   // orders per lane (L < M)
         double2 acc[MPL];
         int g0[MPL], g1[MPL];
+        if (A.segbase) {                              // segment ranges, all loads first
+#pragma unroll
+            for (int i = 0; i < MPL; ++i) {
+                const int m = min(lane + i * WAVE, A.L);
+                g0[i] = A.segbase[m];
+                g1[i] = A.segbase[m + 1];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MPL; ++i) {
+                const int m = lane + i * WAVE;
+                g0[i] = m;
+                g1[i] = m + 1;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < MPL; ++i) {
-            const int m = lane + i * WAVE;
-            const bool ok = m <= A.L;
-            g0[i] = !ok ? 0 : (A.segbase ? A.segbase[m] : m);
-            g1[i] = !ok ? 0 : (A.segbase ? A.segbase[m + 1] : m + 1);
+            if (lane + i * WAVE > A.L) g0[i] = g1[i] = 0;
         }
 #pragma unroll
         for (int i = 0; i < MPL; ++i)
-            acc[i] = g0[i] < g1[i] ? pf[static_cast<size_t>(g0[i]) * A.nlat] : make_double2(0.0, 0.0);
+            acc[i] = g0[i] < g1[i] ? pf[static_cast<long long>(g0[i]) * A.pgs] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int i = 0; i < MPL; ++i) {
-            for (int g = g0[i] + 1; g < g1[i]; ++g) acc[i] = cadd(acc[i], pf[static_cast<size_t>(g) * A.nlat]);
+            for (int g = g0[i] + 1; g < g1[i]; ++g) acc[i] = cadd(acc[i], pf[static_cast<long long>(g) * A.pgs]);
             const int m = lane + i * WAVE;
             if (m <= A.L) x[pad8(m)] = acc[i];
         }
@@ -664,7 +687,7 @@ __device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j
         for (int m = lane; m <= A.L; m += WAVE) {
             double2 acc = make_double2(0.0, 0.0);
             const int g1 = A.segbase ? A.segbase[m + 1] : m + 1;
-            for (int g = A.segbase ? A.segbase[m] : m; g < g1; ++g) acc = cadd(acc, pf[static_cast<size_t>(g) * A.nlat]);
+            for (int g = A.segbase ? A.segbase[m] : m; g < g1; ++g) acc = cadd(acc, pf[static_cast<long long>(g) * A.pgs]);
             x[pad8(m)] = acc;
         }
     }
@@ -680,23 +703,33 @@ __device__ __forceinline__ void wave_pack_inverse(const RingArgs& A, double2* x,
     const int M = MC > 0 ? MC : A.nlon / 2;
     constexpr int KPL = ((MC > 0 ? MC : RING_MMAX_RT) + WAVE - 1) / WAVE;
     lane = opaque_lane(lane);
+    // every read first, unconditionally (k and M - k stay inside the padded
+    // array; entries of orders above L are replaced by zero afterwards)
+    double2 xa[KPL], xb[KPL], tw[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k0 = lane + i * WAVE;
+        const int k = k0 < M ? k0 : 0;
+        xa[i] = x[pad8(k)];
+        xb[i] = x[pad8(M - k)];
+        tw[i] = twr[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of the arithmetic
     double2 z[KPL];
 #pragma unroll
     for (int i = 0; i < KPL; ++i) {
-        const int k = lane + i * WAVE;
-        if (k < M) {
-            double2 xk = make_double2(0.0, 0.0), xr = make_double2(0.0, 0.0);
-            if (k <= A.L) xk = x[pad8(k)];
-            const int kr = M - k;                      // 1..M
-            if (kr <= A.L && kr < M) xr = x[pad8(kr)];
-            if (k == 0) xk.y = 0.0;
-            const double2 xrc = conj2(xr);
-            const double2 sm = cadd(xk, xrc);
-            const double2 df = csub(xk, xrc);
-            const double2 tk = twr[k];
-            const double2 t = cmul(make_double2(tk.x, -tk.y), df);   // e^{+2 pi i k / nlon} d
-            z[i] = make_double2(sm.x - t.y, sm.y + t.x);             // s + i t
-        }
+        const int k0 = lane + i * WAVE;
+        const int k = k0 < M ? k0 : 0;
+        const int kr = M - k;                      // 1..M
+        double2 xk = k <= A.L ? xa[i] : make_double2(0.0, 0.0);
+        const double2 xr = (kr <= A.L && kr < M) ? xb[i] : make_double2(0.0, 0.0);
+        if (k == 0) xk.y = 0.0;
+        const double2 xrc = conj2(xr);
+        const double2 sm = cadd(xk, xrc);
+        const double2 df = csub(xk, xrc);
+        const double2 tk = tw[i];
+        const double2 t = cmul(make_double2(tk.x, -tk.y), df);   // e^{+2 pi i k / nlon} d
+        z[i] = make_double2(sm.x - t.y, sm.y + t.x);             // s + i t
     }
     wave_sync();
 #pragma unroll
@@ -711,19 +744,38 @@ __device__ __forceinline__ void wave_pack_inverse(const RingArgs& A, double2* x,
 // coefficients F_m = X_m / nlon, m <= L,
 //   X_m = (Z_m + conj Z_{M-m})/2 - (i/2) e^{-2 pi i m/nlon} (Z_m - conj Z_{M-m}),
 // written to frow[m nlat] (order-major buffer).
+template <int MC>
 __device__ __forceinline__ void wave_store_forward(const RingArgs& A, const double2* x, const double2* twr,
                                                    double2* frow, int lane) {
-    const int M = A.nlon / 2;
+    const int M = MC > 0 ? MC : A.nlon / 2;
+    constexpr int KPL = ((MC > 0 ? MC : RING_MMAX_RT) + WAVE - 1) / WAVE;
     const double inv = 1.0 / static_cast<double>(A.nlon);
     lane = opaque_lane(lane);
-    for (int k = lane; k <= A.L; k += WAVE) {
-        const double2 zk = x[pad8(k)];
-        const double2 zr = conj2(x[pad8(k == 0 ? 0 : M - k)]);
+    // every LDS read first (orders above L read order 0's entries, unused)
+    double2 za[KPL], zb[KPL], tw[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k0 = lane + i * WAVE;
+        const int k = k0 <= A.L ? k0 : 0;
+        za[i] = x[pad8(k)];
+        zb[i] = x[pad8(k == 0 ? 0 : M - k)];
+        tw[i] = twr[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);   // the reads stay ahead of the arithmetic
+    double2 X[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const double2 zk = za[i];
+        const double2 zr = conj2(zb[i]);
         const double2 sm = cadd(zk, zr);
         const double2 df = csub(zk, zr);
-        const double2 t = cmul(twr[k], df);
-        const double2 X = make_double2(0.5 * (sm.x + t.y), 0.5 * (sm.y - t.x));   // s/2 - i t/2
-        frow[static_cast<size_t>(k) * A.nlat] = scale2(X, inv);
+        const double2 t = cmul(tw[i], df);
+        X[i] = scale2(make_double2(0.5 * (sm.x + t.y), 0.5 * (sm.y - t.x)), inv);   // (s/2 - i t/2) / nlon
+    }
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int k = lane + i * WAVE;
+        if (k <= A.L) frow[static_cast<size_t>(k) * A.nlat] = X[i];
     }
 }
 
@@ -781,7 +833,7 @@ __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
             for (int k = lane; k < M; k += WAVE) x[pad8(k)] = g[k];
             wave_sync();
             wave_fft<MC, false>(x, A, tw, lane);
-            wave_store_forward(A, x, twr, A.fout + f * fstride + j, lane);
+            wave_store_forward<MC>(A, x, twr, A.fout + f * fstride + j, lane);
             wave_sync();
         }
     } else {
@@ -816,7 +868,7 @@ __global__ __launch_bounds__(RING_WAVES * WAVE) void ring_kernel(RingArgs A) {
         // output fields 0 hU, 1 hV, 2 zU, 3 zV, 4 KE: wave w transforms field w
         double2* xf = lds + (wv == 1 ? 2 : wv == 2 ? 1 : wv) * PL;
         wave_fft<MC, false>(xf, A, tw, lane);
-        wave_store_forward(A, xf, twr, A.fout + wv * fstride + j, lane);
+        wave_store_forward<MC>(A, xf, twr, A.fout + wv * fstride + j, lane);
     }
 }
 
@@ -1022,12 +1074,17 @@ int launch_legendre_anal(swe_ctx* ctx, int kind, const double* four, double* spe
 }
 
 int launch_ring(swe_ctx* ctx, int mode, const double* part, const int* segbase, int nseg, double* fout,
-                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega) {
+                const double* gin, double* gout, int nf, hipStream_t stream, double two_omega, bool lat_major) {
     RingArgs R = ring_args(ctx);
     R.two_omega = two_omega;
     R.part = reinterpret_cast<const double2*>(part);
     R.segbase = segbase;
     R.nseg = nseg;
+    if (lat_major && (segbase || nseg != ctx->L + 1))
+        return fail(REXI_EINVAL, "ring stage: latitude-major partials need one segment per order");
+    R.pfs = static_cast<long long>(nseg) * ctx->nlat;
+    R.pgs = lat_major ? 1 : ctx->nlat;
+    R.pjs = lat_major ? nseg : 1;
     R.fout = reinterpret_cast<double2*>(fout);
     R.gin = gin;
     R.gout = gout;

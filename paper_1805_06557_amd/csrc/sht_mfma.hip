@@ -39,8 +39,9 @@ namespace rexi {
 namespace {
 
 constexpr int WAVE = 64;
-constexpr int KB_SYN = 8;    // table K steps loaded per batch, synthesis
+constexpr int KB_SYN = 9;    // table K steps loaded per batch, synthesis (T255: one batch)
 constexpr int KB_ANA = 12;   // and analysis
+constexpr int SYN_THREADS = 256;   // synthesis block size (4 latitude tiles)
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
@@ -173,9 +174,10 @@ __device__ __forceinline__ void mfma3(f32x4& acc, const uint4& a, const uint4& b
 // red ([waves][16] floats) and every thread receives sc[c] = 2^-e with
 // max |column c| in [2^(e-1), 2^e) (1 for an all-zero column).  Columns NC ..
 // 15 are known to be zero and are not reduced.
-template <int NC>
+template <int NC, int NT>
 __device__ __forceinline__ void column_scales(float* cmax, float* red, float* sc) {
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    constexpr int nw = NT / WAVE;
 #pragma unroll
     for (int c = NC; c < 16; ++c) cmax[c] = 0.f;
 #pragma unroll
@@ -226,7 +228,10 @@ struct MfmaArgs {
     double a;
     // synthesis
     const double2* __restrict__ spec;   // KIND 0: [nf][modes]; KIND 1: state [3][modes]
-    double2* __restrict__ four_out;     // [nfo][L+1][nlat]
+    double2* __restrict__ four_out;     // element (field, m, latitude) at f ofs + m oms + j ojs
+    long long ofs;
+    int oms, ojs;
+    int xcd_blocks;                     // KIND 1: orders dealt to the XCDs in blocks of 8 (split_item)
     // analysis
     const double2* __restrict__ four_in;  // [nfi][L+1][nlat]
     double2* __restrict__ spec_out;       // KIND 0: [nf][modes]
@@ -239,8 +244,14 @@ struct MfmaArgs {
     int ntg, ng;                          // KIND 0: latitude-tile groups, 8-field groups (split_item)
 };
 
-// The (order m, latitude-tile group, 8-field group) of a workgroup.  KIND 1:
-// (blockIdx.x, blockIdx.y, 0).  KIND 0: a one-dimensional grid in which the ng
+// The (order m, latitude-tile group, 8-field group) of a workgroup.  KIND 1
+// (one-dimensional grid of (L+1) ntg workgroups): with xcd_blocks, the
+// workgroups of each block of 8 consecutive orders run on one XCD (workgroup b
+// runs on XCD b mod 8), so that the latitude-major Fourier rows they write
+// together (8 orders = one 128-byte line) are completed in that XCD's L2; the
+// blocks are dealt to the XCDs in snake order (x, 15 - x, 16 + x, ...) so that
+// long and short orders mix on every XCD; otherwise b = m + (L+1) tg.
+// KIND 0: a one-dimensional grid in which the ng
 // field groups of one (order, tile group) pair p share an XCD (workgroup b runs
 // on XCD b mod 8) and are dispatched within a window of 8 ng workgroups, so the
 // table tiles they all read come from HBM once and then from that XCD's L2:
@@ -249,9 +260,19 @@ struct MfmaArgs {
 template <int KIND>
 __device__ __forceinline__ bool split_item(const MfmaArgs& A, int& m, int& tg, int& g) {
     if constexpr (KIND == 1) {
-        m = blockIdx.x;
-        tg = blockIdx.y;
+        const int b = blockIdx.x;
         g = 0;
+        if (A.xcd_blocks) {
+            const int x = b & 7, i = b >> 3;            // XCD, slot on it
+            const int per = 8 * A.ntg;                  // workgroups per block of 8 orders
+            const int kb = i / per, r = i - kb * per;   // the XCD's kb-th block
+            const int blk = (kb & 1) ? (kb + 1) * 8 - 1 - x : kb * 8 + x;
+            m = blk * 8 + (r & 7);
+            tg = r >> 3;
+        } else {
+            m = b % (A.L + 1);
+            tg = b / (A.L + 1);
+        }
         return true;
     } else {
         const int b = blockIdx.x;
@@ -275,7 +296,7 @@ __host__ __device__ constexpr int split_grid_size(int pairs, int ng) { return (p
 //   V_l = -i m zeta_l a/N_l - hA_{l-1} delta_{l-1} a/N_{l-1} - hB_{l+1} delta_{l+1} a/N_{l+1}
 // (N_l = l(l+1)), rows up to degree L+1.
 template <int KIND, class E>
-__global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
+__global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short xs[];
     constexpr bool SCALED = std::is_same<E, F16>::value;
     __shared__ float sred[4 * 16], sc[16];
@@ -288,9 +309,69 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
     unsigned short* xp = xs;                        // [2][16][rowlen]
     const int f0 = 8 * g;
     const double dm = static_cast<double>(m);
-    // the 16 column values of staging row rp (parity, row), zero where there is
-    // no degree or column
-    auto row_values = [&](int rp, double* vp) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int tile = tg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave-uniform
+    const bool active = tile * 16 < A.hpad;
+    const int kq = lane >> 4;                       // K quarter of this lane
+    // table operand blocks of this latitude tile, per parity: 64 lanes x 8
+    // shorts per K step.  The first batch of the even parity is requested
+    // before the staging and that of the odd parity after it, so that their
+    // memory latency overlaps the staging's and the even products (both before
+    // the staging would hold too many registers for three workgroups per CU).
+    const int nks[2] = {ke >> 4, ko >> 4};
+    const unsigned short* ap[2];
+    const long long off_m = A.off[m];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const long long blk = off_m + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
+        ap[par] = A.p_syn + blk + (static_cast<long long>(active ? tile : 0) * nks[par] * 64 + lane) * 8;
+    }
+    // steps past the end reload the last block and are not multiplied
+    auto load_batch = [&](int par, int k0, uint4* a) {
+#pragma unroll
+        for (int u = 0; u < KB_SYN; ++u) {
+            const int ks = min(k0 + u, nks[par] - 1);
+            a[u] = *reinterpret_cast<const uint4*>(ap[par] + ks * 512);
+        }
+    };
+    uint4 pre[2][KB_SYN];
+    if (active) load_batch(0, 0, pre[0]);
+    // Staging row rp = (parity, row r), degree l = m + 2 r + parity.  Its
+    // inputs are loaded with indices clamped into the order (straight-line
+    // code, so that the loads of a thread's rows are in flight together);
+    // row_values then forms the 16 column values, zero where there is no
+    // degree or column.
+    struct RowIn {
+        double2 v[8];   // KIND 0: fields f0 .. f0+7; KIND 1: (h, zeta, delta)_l, (zeta, delta)_{l-1}, (zeta, delta)_{l+1}
+        double s[5];    // KIND 1: a/N_l, hA_{l-1}, a/N_{l-1}, hB_{l+1}, a/N_{l+1}
+    };
+    auto row_load = [&](int rp, RowIn& in) {
+        const int par = rp / A.kmax, r = rp - par * A.kmax;
+        const int i = 2 * r + par;                  // l - m
+        const int ic = min(i, Lm - 1);
+        if constexpr (KIND == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int fq = min(f0 + q, A.nf - 1);
+                in.v[q] = A.spec[static_cast<size_t>(fq) * A.modes + base + ic];
+            }
+        } else {
+            const int id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
+            in.v[0] = A.spec[base + ic];
+            in.v[1] = A.spec[A.modes + base + ic];
+            in.v[2] = A.spec[2 * A.modes + base + ic];
+            in.v[3] = A.spec[A.modes + base + id];
+            in.v[4] = A.spec[2 * A.modes + base + id];
+            in.v[5] = A.spec[A.modes + base + iu];
+            in.v[6] = A.spec[2 * A.modes + base + iu];
+            in.s[0] = A.aon[m + ic];
+            in.s[1] = A.rec[base + id].hA;
+            in.s[2] = A.aon[m + id];
+            in.s[3] = A.rec[base + iu].hB;
+            in.s[4] = A.aon[m + iu];
+        }
+    };
+    auto row_values = [&](int rp, const RowIn& in, double* vp) {
         const int par = rp / A.kmax, r = rp - par * A.kmax;
         const int i = 2 * r + par;                  // l - m
 #pragma unroll
@@ -300,19 +381,16 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     if (f0 + q < A.nf) {
-                        const double2 v = A.spec[static_cast<size_t>(f0 + q) * A.modes + base + i];
-                        vp[2 * q] = v.x;
-                        vp[2 * q + 1] = v.y;
+                        vp[2 * q] = in.v[q].x;
+                        vp[2 * q + 1] = in.v[q].y;
                     }
                 }
             }
         } else if (i <= Lm) {
             double2 U = make_double2(0.0, 0.0), V = make_double2(0.0, 0.0);
             if (i < Lm) {
-                const double2 ch = A.spec[base + i];
-                const double2 cz = A.spec[A.modes + base + i];
-                const double2 cd = A.spec[2 * A.modes + base + i];
-                const double maon = dm * A.aon[m + i];
+                const double2 ch = in.v[0], cz = in.v[1], cd = in.v[2];
+                const double maon = dm * in.s[0];
                 vp[0] = ch.x;
                 vp[1] = ch.y;
                 vp[2] = cz.x;
@@ -321,16 +399,14 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                 V = make_double2(cz.y * maon, -cz.x * maon);
             }
             if (i >= 1) {                           // hA_{l-1} H-term of degree l-1
-                const double t = A.rec[base + i - 1].hA * A.aon[m + i - 1];
-                const double2 cz = A.spec[A.modes + base + i - 1];
-                const double2 cd = A.spec[2 * A.modes + base + i - 1];
+                const double t = in.s[1] * in.s[2];
+                const double2 cz = in.v[3], cd = in.v[4];
                 U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
                 V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
             }
             if (i + 1 < Lm) {                       // hB_{l+1} H-term of degree l+1
-                const double t = A.rec[base + i + 1].hB * A.aon[m + i + 1];
-                const double2 cz = A.spec[A.modes + base + i + 1];
-                const double2 cd = A.spec[2 * A.modes + base + i + 1];
+                const double t = in.s[3] * in.s[4];
+                const double2 cz = in.v[5], cd = in.v[6];
                 U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
                 V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
             }
@@ -340,6 +416,9 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
             vp[7] = V.y;
         }
     };
+    // every thread takes rows rp and rp + SYN_THREADS of each 2 SYN_THREADS
+    const int nrows = 2 * A.kmax;
+    constexpr int bd = SYN_THREADS;
     if constexpr (SCALED) {
         // the values go to LDS as FP32 (24 bits, more than the split keeps)
         // with their column maxima; then they are scaled and split
@@ -347,18 +426,26 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
         float cmax[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) cmax[c] = 0.f;
-        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+        auto put = [&](int rp, const RowIn& in) {
             double vp[16];
-            row_values(rp, vp);
+            row_values(rp, in, vp);
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 const float v = static_cast<float>(vp[c]);
                 stage[c * 2 * A.kmax + rp] = v;
                 cmax[c] = fmaxf(cmax[c], fabsf(v));
             }
+        };
+        for (int rp = threadIdx.x; rp < nrows; rp += 2 * bd) {
+            RowIn in0, in1;
+            row_load(rp, in0);
+            row_load(min(rp + bd, nrows - 1), in1);
+            put(rp, in0);
+            if (rp + bd < nrows) put(rp + bd, in1);
         }
-        column_scales<KIND == 0 ? 16 : 8>(cmax, sred, sc);
-        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+        if (active) load_batch(1, 0, pre[1]);
+        column_scales<KIND == 0 ? 16 : 8, SYN_THREADS>(cmax, sred, sc);
+        for (int rp = threadIdx.x; rp < nrows; rp += bd) {
             const int par = rp / A.kmax, r = rp - par * A.kmax;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
@@ -370,11 +457,11 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
             }
         }
     } else {
-        // stage: one thread per (parity, row) writes the row's 16 columns
-        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += blockDim.x) {
+        // stage: the row's 16 columns, split, into the B operand
+        auto put = [&](int rp, const RowIn& in) {
             const int par = rp / A.kmax, r = rp - par * A.kmax;
             double vp[16];
-            row_values(rp, vp);
+            row_values(rp, in, vp);
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 unsigned short hi, lo;
@@ -383,38 +470,34 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
                 xp[o + grp_hi(r)] = hi;
                 xp[o + grp_lo(r)] = lo;
             }
+        };
+        for (int rp = threadIdx.x; rp < nrows; rp += 2 * bd) {
+            RowIn in0, in1;
+            row_load(rp, in0);
+            row_load(min(rp + bd, nrows - 1), in1);
+            put(rp, in0);
+            if (rp + bd < nrows) put(rp + bd, in1);
         }
     }
+    if (!SCALED && active) load_batch(1, 0, pre[1]);
     __syncthreads();
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int tile = tg * 4 + threadIdx.x / WAVE;
-    if (tile * 16 >= A.hpad) return;
-    const int kq = lane >> 4;                       // K quarter of this lane
+    if (!active) return;
     f32x4 acc[2];
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
         acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int K = par ? ko : ke;
-        const long long blk = A.off[m] + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-        // operand blocks of this latitude tile: 64 lanes x 8 shorts per K step
-        const unsigned short* ap = A.p_syn + blk + (static_cast<long long>(tile) * (K >> 4) * 64 + lane) * 8;
         const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
         // table operands in batches of KB steps, all loads of a batch issued
         // before its products (a serial load-multiply chain leaves the
-        // small-m workgroups, the longest ones, waiting on memory latency);
-        // steps past the end reload the last block and are not multiplied
-        const int nks = K >> 4;
-        for (int k0 = 0; k0 < nks; k0 += KB_SYN) {
-            uint4 a[KB_SYN];
-#pragma unroll
-            for (int u = 0; u < KB_SYN; ++u) {
-                const int ks = min(k0 + u, nks - 1);
-                a[u] = *reinterpret_cast<const uint4*>(ap + ks * 512);
-            }
+        // small-m workgroups, the longest ones, waiting on memory latency)
+        // pre[par] holds the current batch (the first one requested early)
+        for (int k0 = 0; k0 < nks[par]; k0 += KB_SYN) {
+            if (k0 > 0) load_batch(par, k0, pre[par]);
+            const uint4* a = pre[par];
             __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
 #pragma unroll
             for (int u = 0; u < KB_SYN; ++u) {
-                if (k0 + u < nks) {                         // uniform: no products past the end
+                if (k0 + u < nks[par]) {                    // uniform: no products past the end
                     const int g = 4 * (k0 + u) + kq;        // group of four rows for this lane
                     const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
                     mfma3<E>(acc[par], a[u], b);
@@ -438,9 +521,9 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
         const int j = tile * 16 + 4 * kq + t;
         const bool col_ok = (c & 1) == 0 && (KIND == 0 ? (f < A.nf) : (c < 8));
         if (!col_ok || j >= A.half) continue;
-        double2* row = A.four_out + (static_cast<size_t>(f) * (A.L + 1) + m) * A.nlat;
-        row[j] = make_double2(vn, vn_im);
-        row[A.nlat - 1 - j] = make_double2(vs, vs_im);
+        double2* row = A.four_out + f * A.ofs + static_cast<long long>(m) * A.oms;
+        row[static_cast<long long>(j) * A.ojs] = make_double2(vn, vn_im);
+        row[static_cast<long long>(A.nlat - 1 - j) * A.ojs] = make_double2(vs, vs_im);
     }
 }
 
@@ -460,6 +543,7 @@ __global__ __launch_bounds__(256) void leg_synth_mfma_kernel(MfmaArgs A) {
 // giving N_h (k 0-1), N_zeta (2-3), N_delta (4-5); then out = U0 + c0 N + c1 Nprev
 // and Nsave = N (FP64).
 constexpr int ANA_WAVES = 16;
+constexpr int ANA_THREADS = ANA_WAVES * WAVE;   // the launch's block size
 
 template <int KIND, class E>
 __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArgs A) {
@@ -562,7 +646,7 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
 #pragma unroll
                 for (int k = 0; k < 16; ++k) cmax[k] = col == k ? fmaxf(cmax[k], v) : cmax[k];
             });
-        column_scales<KIND == 0 ? 16 : 14>(cmax, sred, sc);
+        column_scales<KIND == 0 ? 16 : 14, ANA_THREADS>(cmax, sred, sc);
         for (int it = threadIdx.x; it < A.hpad * 16; it += blockDim.x) {
             const int col = it / A.hpad, j = it - col * A.hpad;
             unsigned short hi, lo;
@@ -747,7 +831,12 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     const int tiles = A.hpad / 16;
     A.ntg = (tiles + 3) / 4;
     A.ng = (nf + 7) / 8;
-    const dim3 grid = kind == 0 ? dim3(split_grid_size((ctx->L + 1) * A.ntg, A.ng)) : dim3(ctx->L + 1, A.ntg, 1);
+    // kind 0 order-major [nf][L+1][nlat], kind 1 latitude-major [3][nlat][L+1]
+    A.ofs = static_cast<long long>(ctx->L + 1) * ctx->nlat;
+    A.oms = kind == 0 ? ctx->nlat : 1;
+    A.ojs = kind == 0 ? 1 : ctx->L + 1;
+    A.xcd_blocks = (ctx->L + 1) % 64 == 0;
+    const dim3 grid = kind == 0 ? dim3(split_grid_size((ctx->L + 1) * A.ntg, A.ng)) : dim3((ctx->L + 1) * A.ntg);
     const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
     const void* fn = kind == 0 ? (f16 ? reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, F16>)
                                       : reinterpret_cast<const void*>(&leg_synth_mfma_kernel<0, Bf16>))
@@ -757,7 +846,7 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_SYNTH, stream);
     void* kargs[] = {&A};
-    REXI_HIP(hipLaunchKernel(fn, grid, dim3(256), kargs, lds, stream));
+    REXI_HIP(hipLaunchKernel(fn, grid, dim3(SYN_THREADS), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_SYNTH, slot, stream);
     return REXI_OK;
@@ -793,7 +882,7 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
     void* kargs[] = {&A};
-    REXI_HIP(hipLaunchKernel(fn, grid, dim3(ANA_WAVES * WAVE), kargs, lds, stream));
+    REXI_HIP(hipLaunchKernel(fn, grid, dim3(ANA_THREADS), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
     return REXI_OK;
