@@ -303,10 +303,19 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
     if ((rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
     if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
-    if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) != REXI_OK)
-        return rc;
+    if (split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
+        // the analysis of each order synthesises its U* directly (one launch;
+        // U* is not stored)
+        if ((rc = launch_legendre_anal_synth_split(ctx, ctx->d_fout, U0, ctx->d_n0, nullptr, tau, ctx->d_part,
+                                                   stream)) != REXI_OK)
+            return rc;
+    } else {
+        if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) !=
+            REXI_OK)
+            return rc;
+        if ((rc = to_fourier(ctx, 1, ctx->d_ustar, 3, stream)) != REXI_OK) return rc;
+    }
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
-    if ((rc = to_fourier(ctx, 1, ctx->d_ustar, 3, stream)) != REXI_OK) return rc;
     if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
     return from_fourier(ctx, 1, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau, stream);
 }

@@ -293,6 +293,14 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
 int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                                const double* Nprev, double* Nsave, double* out, double c0, double c1,
                                hipStream_t stream);
+// The state's analysis (kind 1, Nprev = 0) fused with the synthesis of its
+// output: Nsave = N, out = U0 + c0 N (written only if out is non-null), and
+// the Fourier coefficients of out, latitude-major, into four_next (as the
+// kind-1 synthesis writes them).  Needs the table's degree rows per parity to
+// fit the latitude rows (fused_anal_synth_supported).
+int fused_anal_synth_supported(const swe_ctx* ctx);
+int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, double* Nsave,
+                                     double* out, double c0, double* four_next, hipStream_t stream);
 // The REXI stage of the gravity-wave part L_g alone (Coriolis-free): per degree
 // l a 2x2 system in (h, delta), zeta multiplied by S(0); the sums over poles are
 // formed once per degree.

@@ -242,6 +242,7 @@ struct MfmaArgs {
     double c0, c1;
     unsigned* status;                     // non-finite outputs set a STATUS_* flag
     int ntg, ng;                          // KIND 0: latitude-tile groups, 8-field groups (split_item)
+    int zreg;                             // analysis: bytes of the zs region (the fused kernel's us follows)
 };
 
 // The (order m, latitude-tile group, 8-field group) of a workgroup.  KIND 1
@@ -287,6 +288,136 @@ __device__ __forceinline__ bool split_item(const MfmaArgs& A, int& m, int& tg, i
 
 __host__ __device__ constexpr int split_grid_size(int pairs, int ng) { return (pairs + 7) / 8 * 8 * ng; }
 
+// The 16 B-operand columns of synthesis staging row i = l - m of the state
+// (i <= Lm = L - m + 1; zero where there is no degree or column): h and zeta
+// (Pbar columns 0-3) and U, V (columns 4-7),
+//   U_l = -i m delta_l a/N_l + hA_{l-1} zeta_{l-1} a/N_{l-1} + hB_{l+1} zeta_{l+1} a/N_{l+1},
+//   V_l = -i m zeta_l a/N_l - hA_{l-1} delta_{l-1} a/N_{l-1} - hB_{l+1} delta_{l+1} a/N_{l+1}
+// (N_l = l(l+1)), from v = (h, zeta, delta)_l, (zeta, delta)_{l-1},
+// (zeta, delta)_{l+1} and s = a/N_l, hA_{l-1}, a/N_{l-1}, hB_{l+1}, a/N_{l+1}.
+__device__ __forceinline__ void state_row_values(const double2* v, const double* s, int i, int Lm, double dm,
+                                                 double* vp) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) vp[c] = 0.0;
+    if (i > Lm) return;
+    double2 U = make_double2(0.0, 0.0), V = make_double2(0.0, 0.0);
+    if (i < Lm) {
+        const double2 ch = v[0], cz = v[1], cd = v[2];
+        const double maon = dm * s[0];
+        vp[0] = ch.x;
+        vp[1] = ch.y;
+        vp[2] = cz.x;
+        vp[3] = cz.y;
+        U = make_double2(cd.y * maon, -cd.x * maon);
+        V = make_double2(cz.y * maon, -cz.x * maon);
+    }
+    if (i >= 1) {                           // hA_{l-1} H-term of degree l-1
+        const double t = s[1] * s[2];
+        const double2 cz = v[3], cd = v[4];
+        U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
+        V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
+    }
+    if (i + 1 < Lm) {                       // hB_{l+1} H-term of degree l+1
+        const double t = s[3] * s[4];
+        const double2 cz = v[5], cd = v[6];
+        U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
+        V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
+    }
+    vp[4] = U.x;
+    vp[5] = U.y;
+    vp[6] = V.x;
+    vp[7] = V.y;
+}
+
+// The synthesis table operands of one latitude tile of order m, per parity:
+// ap[par] = first K step's block (64 lanes x 8 shorts per K step), nks[par]
+// K steps; load_syn_batch reads KB_SYN steps from k0 (steps past the end
+// reload the last block, which is not multiplied).
+struct SynTile {
+    const unsigned short* ap[2];
+    int nks[2];
+};
+
+__device__ __forceinline__ SynTile syn_tile_ptrs(const MfmaArgs& A, int m, int tile, int lane) {
+    SynTile T;
+    const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
+    T.nks[0] = ke >> 4;
+    T.nks[1] = ko >> 4;
+    const long long off_m = A.off[m];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const long long blk = off_m + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
+        T.ap[par] = A.p_syn + blk + (static_cast<long long>(tile) * T.nks[par] * 64 + lane) * 8;
+    }
+    return T;
+}
+
+__device__ __forceinline__ void load_syn_batch(const SynTile& T, int par, int k0, uint4* a) {
+#pragma unroll
+    for (int u = 0; u < KB_SYN; ++u) {
+        const int ks = min(k0 + u, T.nks[par] - 1);
+        a[u] = *reinterpret_cast<const uint4*>(T.ap[par] + ks * 512);
+    }
+}
+
+// Products and Fourier output of one latitude tile of order m, both parities:
+// xp is the B operand in LDS ([2][16][rowlen], rows in groups of four), pre
+// the first table batch of each parity (requested by the caller), sc the
+// column scales (FP16 mode).  Lane (c = lane % 16, K quarter kq) holds column
+// c of latitudes 4 kq + t; the imaginary part (odd column) moves to the real
+// part's lane, which writes the complex value of (field, m, latitude) at
+// f ofs + m oms + j ojs, north and south (Pbar(-mu) = (-1)^(l-m) Pbar(mu)).
+template <int KIND, class E, bool LAZY1 = false>
+__device__ __forceinline__ void synth_tile(const MfmaArgs& A, int m, int tile, int f0, const SynTile& T,
+                                           uint4 (&pre)[2][KB_SYN], const unsigned short* xp, int rowlen,
+                                           const float* sc, int lane) {
+    constexpr bool SCALED = std::is_same<E, F16>::value;
+    const int kq = lane >> 4;
+    f32x4 acc[2];
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
+        // LAZY1: the odd parity's first batch is requested here, after the
+        // even products (fewer registers live)
+        if (LAZY1 && par == 1) load_syn_batch(T, 1, 0, pre[1]);
+        // table operands in batches of KB steps, all loads of a batch issued
+        // before its products (a serial load-multiply chain leaves the
+        // small-m workgroups, the longest ones, waiting on memory latency);
+        // pre[par] holds the current batch
+        for (int k0 = 0; k0 < T.nks[par]; k0 += KB_SYN) {
+            if (k0 > 0) load_syn_batch(T, par, k0, pre[par]);
+            const uint4* a = pre[par];
+            __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
+#pragma unroll
+            for (int u = 0; u < KB_SYN; ++u) {
+                if (k0 + u < T.nks[par]) {                  // uniform: no products past the end
+                    const int g = 4 * (k0 + u) + kq;        // group of four rows for this lane
+                    const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
+                    mfma3<E>(acc[par], a[u], b);
+                }
+            }
+        }
+    }
+    const int c = lane & 15;
+    const int f = KIND == 0 ? f0 + (c >> 1) : (c >> 1);
+    const double unscale = SCALED ? 1.0 / static_cast<double>(sc[c]) : 1.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float e = acc[0][t], o = acc[1][t];   // even, odd in mu
+        const double vn = (static_cast<double>(e) + static_cast<double>(o)) * unscale;
+        const double vs = (static_cast<double>(e) - static_cast<double>(o)) * unscale;
+        const double vn_im = __shfl(vn, lane + 1 < WAVE ? lane + 1 : lane);
+        const double vs_im = __shfl(vs, lane + 1 < WAVE ? lane + 1 : lane);
+        const int j = tile * 16 + 4 * kq + t;
+        const bool col_ok = (c & 1) == 0 && (KIND == 0 ? (f < A.nf) : (c < 8));
+        if (!col_ok || j >= A.half) continue;
+        double2* row = A.four_out + f * A.ofs + static_cast<long long>(m) * A.oms;
+        row[static_cast<long long>(j) * A.ojs] = make_double2(vn, vn_im);
+        row[static_cast<long long>(A.nlat - 1 - j) * A.ojs] = make_double2(vs, vs_im);
+    }
+}
+
 // ---------------------------------------------------------------- synthesis --
 // Workgroup (split_item): order m, 4 waves = 4 tiles of 16 northern latitudes
 // (tile 4 tg + wave); KIND 0: fields 8 g .. 8 g + 7.
@@ -302,7 +433,6 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
     __shared__ float sred[4 * 16], sc[16];
     int m, tg, g;
     if (!split_item<KIND>(A, m, tg, g)) return;
-    const int ke = A.kp[2 * m], ko = A.kp[2 * m + 1];
     const int Lm = A.L - m + 1;
     const int base = m * (2 * A.L + 3 - m) / 2;
     const int rowlen = lds_row(A.kmax);             // shorts per LDS column row
@@ -312,30 +442,13 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
     const int lane = threadIdx.x & (WAVE - 1);
     const int tile = tg * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave-uniform
     const bool active = tile * 16 < A.hpad;
-    const int kq = lane >> 4;                       // K quarter of this lane
-    // table operand blocks of this latitude tile, per parity: 64 lanes x 8
-    // shorts per K step.  The first batch of the even parity is requested
-    // before the staging and that of the odd parity after it, so that their
-    // memory latency overlaps the staging's and the even products (both before
-    // the staging would hold too many registers for three workgroups per CU).
-    const int nks[2] = {ke >> 4, ko >> 4};
-    const unsigned short* ap[2];
-    const long long off_m = A.off[m];
-#pragma unroll
-    for (int par = 0; par < 2; ++par) {
-        const long long blk = off_m + (par ? static_cast<long long>(ke) * A.hpad * 2 : 0);
-        ap[par] = A.p_syn + blk + (static_cast<long long>(active ? tile : 0) * nks[par] * 64 + lane) * 8;
-    }
-    // steps past the end reload the last block and are not multiplied
-    auto load_batch = [&](int par, int k0, uint4* a) {
-#pragma unroll
-        for (int u = 0; u < KB_SYN; ++u) {
-            const int ks = min(k0 + u, nks[par] - 1);
-            a[u] = *reinterpret_cast<const uint4*>(ap[par] + ks * 512);
-        }
-    };
+    // The first table batch of the even parity is requested before the
+    // staging and that of the odd parity after it, so that their memory
+    // latency overlaps the staging's and the even products (both before the
+    // staging would hold too many registers for three workgroups per CU).
+    const SynTile T = syn_tile_ptrs(A, m, active ? tile : 0, lane);
     uint4 pre[2][KB_SYN];
-    if (active) load_batch(0, 0, pre[0]);
+    if (active) load_syn_batch(T, 0, 0, pre[0]);
     // Staging row rp = (parity, row r), degree l = m + 2 r + parity.  Its
     // inputs are loaded with indices clamped into the order (straight-line
     // code, so that the loads of a thread's rows are in flight together);
@@ -374,9 +487,9 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
     auto row_values = [&](int rp, const RowIn& in, double* vp) {
         const int par = rp / A.kmax, r = rp - par * A.kmax;
         const int i = 2 * r + par;                  // l - m
-#pragma unroll
-        for (int c = 0; c < 16; ++c) vp[c] = 0.0;
         if constexpr (KIND == 0) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) vp[c] = 0.0;
             if (i < Lm) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -386,34 +499,8 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
                     }
                 }
             }
-        } else if (i <= Lm) {
-            double2 U = make_double2(0.0, 0.0), V = make_double2(0.0, 0.0);
-            if (i < Lm) {
-                const double2 ch = in.v[0], cz = in.v[1], cd = in.v[2];
-                const double maon = dm * in.s[0];
-                vp[0] = ch.x;
-                vp[1] = ch.y;
-                vp[2] = cz.x;
-                vp[3] = cz.y;
-                U = make_double2(cd.y * maon, -cd.x * maon);
-                V = make_double2(cz.y * maon, -cz.x * maon);
-            }
-            if (i >= 1) {                           // hA_{l-1} H-term of degree l-1
-                const double t = in.s[1] * in.s[2];
-                const double2 cz = in.v[3], cd = in.v[4];
-                U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
-                V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
-            }
-            if (i + 1 < Lm) {                       // hB_{l+1} H-term of degree l+1
-                const double t = in.s[3] * in.s[4];
-                const double2 cz = in.v[5], cd = in.v[6];
-                U = make_double2(__builtin_fma(t, cz.x, U.x), __builtin_fma(t, cz.y, U.y));
-                V = make_double2(__builtin_fma(-t, cd.x, V.x), __builtin_fma(-t, cd.y, V.y));
-            }
-            vp[4] = U.x;
-            vp[5] = U.y;
-            vp[6] = V.x;
-            vp[7] = V.y;
+        } else {
+            state_row_values(in.v, in.s, i, Lm, dm, vp);
         }
     };
     // every thread takes rows rp and rp + SYN_THREADS of each 2 SYN_THREADS
@@ -443,7 +530,7 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
             put(rp, in0);
             if (rp + bd < nrows) put(rp + bd, in1);
         }
-        if (active) load_batch(1, 0, pre[1]);
+        if (active) load_syn_batch(T, 1, 0, pre[1]);
         column_scales<KIND == 0 ? 16 : 8, SYN_THREADS>(cmax, sred, sc);
         for (int rp = threadIdx.x; rp < nrows; rp += bd) {
             const int par = rp / A.kmax, r = rp - par * A.kmax;
@@ -479,52 +566,10 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
             if (rp + bd < nrows) put(rp + bd, in1);
         }
     }
-    if (!SCALED && active) load_batch(1, 0, pre[1]);
+    if (!SCALED && active) load_syn_batch(T, 1, 0, pre[1]);
     __syncthreads();
     if (!active) return;
-    f32x4 acc[2];
-#pragma unroll
-    for (int par = 0; par < 2; ++par) {
-        acc[par] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const unsigned short* bp = xp + (par * 16 + (lane & 15)) * rowlen;
-        // table operands in batches of KB steps, all loads of a batch issued
-        // before its products (a serial load-multiply chain leaves the
-        // small-m workgroups, the longest ones, waiting on memory latency)
-        // pre[par] holds the current batch (the first one requested early)
-        for (int k0 = 0; k0 < nks[par]; k0 += KB_SYN) {
-            if (k0 > 0) load_batch(par, k0, pre[par]);
-            const uint4* a = pre[par];
-            __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its products
-#pragma unroll
-            for (int u = 0; u < KB_SYN; ++u) {
-                if (k0 + u < nks[par]) {                    // uniform: no products past the end
-                    const int g = 4 * (k0 + u) + kq;        // group of four rows for this lane
-                    const uint4 b = *reinterpret_cast<const uint4*>(bp + 8 * g);
-                    mfma3<E>(acc[par], a[u], b);
-                }
-            }
-        }
-    }
-    // lane holds column c = lane % 16 of rows (latitudes) 4 (lane / 16) + t; the
-    // imaginary part (odd column) moves to the real part's lane, which writes the
-    // complex value into row (field, m) of the Fourier buffer [nfo][L+1][nlat]
-    const int c = lane & 15;
-    const int f = KIND == 0 ? f0 + (c >> 1) : (c >> 1);
-    const double unscale = SCALED ? 1.0 / static_cast<double>(sc[c]) : 1.0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const float e = acc[0][t], o = acc[1][t];   // even, odd in mu
-        const double vn = (static_cast<double>(e) + static_cast<double>(o)) * unscale;
-        const double vs = (static_cast<double>(e) - static_cast<double>(o)) * unscale;
-        const double vn_im = __shfl(vn, lane + 1 < WAVE ? lane + 1 : lane);
-        const double vs_im = __shfl(vs, lane + 1 < WAVE ? lane + 1 : lane);
-        const int j = tile * 16 + 4 * kq + t;
-        const bool col_ok = (c & 1) == 0 && (KIND == 0 ? (f < A.nf) : (c < 8));
-        if (!col_ok || j >= A.half) continue;
-        double2* row = A.four_out + f * A.ofs + static_cast<long long>(m) * A.oms;
-        row[static_cast<long long>(j) * A.ojs] = make_double2(vn, vn_im);
-        row[static_cast<long long>(A.nlat - 1 - j) * A.ojs] = make_double2(vs, vs_im);
-    }
+    synth_tile<KIND, E>(A, m, tile, f0, T, pre, xp, rowlen, sc, lane);
 }
 
 // ----------------------------------------------------------------- analysis --
@@ -545,10 +590,17 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
 constexpr int ANA_WAVES = 16;
 constexpr int ANA_THREADS = ANA_WAVES * WAVE;   // the launch's block size
 
-template <int KIND, class E>
+// FUSE (KIND 1 only): the workgroup then synthesises the outputs of its order
+// for the next evaluation (the stage-1 state of a Heun step): they stay in LDS
+// (us, [L-m+1][6] doubles, after zs), the synthesis B operand is staged from
+// them into the region of yp (kmax <= hpad) and the waves take the latitude
+// tiles in turn; the Fourier coefficients go latitude-major to four_out (A.ofs,
+// A.oms, A.ojs) and out is written only if non-null.
+template <int KIND, class E, bool FUSE = false>
 __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArgs A) {
     extern __shared__ __align__(16) unsigned short ys[];
     constexpr bool SCALED = std::is_same<E, F16>::value;
+    static_assert(!FUSE || KIND == 1, "only the state's analysis is fused with a synthesis");
     __shared__ float sred[ANA_WAVES * 16], sc[16];
     int m, tg, g;
     if (!split_item<KIND>(A, m, tg, g)) return;
@@ -558,8 +610,25 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     const int rowlen = lds_row(A.hpad);
     unsigned short* yp = ys;                                        // [2][16][rowlen]
     float* zs = reinterpret_cast<float*>(ys + 2 * 16 * rowlen);     // KIND 1: [2][kmax][16]
+    double* us = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(zs) + A.zreg);   // FUSE
     const int f0 = 8 * g;
     const double dm = static_cast<double>(m);
+    // FUSE: the synthesis staging's per-degree factors of the thread's first
+    // staging row (a/N and the H coefficients), requested now
+    double syn_s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    auto syn_factors = [&](int rp, double* sf) {
+        const int par = rp / A.kmax, r = rp - par * A.kmax;
+        const int i = 2 * r + par;
+        const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
+        sf[0] = A.aon[m + ic];
+        sf[1] = A.rec[base + id].hA;
+        sf[2] = A.aon[m + id];
+        sf[3] = A.rec[base + iu].hB;
+        sf[4] = A.aon[m + iu];
+    };
+    if constexpr (FUSE) {
+        if (static_cast<int>(threadIdx.x) < 2 * A.kmax) syn_factors(threadIdx.x, syn_s);
+    }
     // KIND 1: the epilogue's inputs that do not depend on the products (H
     // coefficients, l(l+1)/a^2, U0 + c1 Nprev) of the thread's first EPI items
     // (degree, output column) are requested before anything else
@@ -743,7 +812,8 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             if (A.Nsave) reinterpret_cast<double*>(A.Nsave)[e2] = v;
             const double o = __builtin_fma(A.c0, v, ob);
             note_nonfinite(A.status, o, STATUS_NONLINEAR);
-            reinterpret_cast<double*>(A.out)[e2] = o;
+            if (FUSE) us[it] = o;                       // it = 6 i + k
+            if (!FUSE || A.out) reinterpret_cast<double*>(A.out)[e2] = o;
         };
 #pragma unroll
         for (int q = 0; q < EPI; ++q) {
@@ -754,6 +824,99 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
             double hA, hB, nk, ob;
             epi_inputs(it, hA, hB, nk, ob);
             finish(it, hA, hB, nk, ob);
+        }
+    }
+    if constexpr (FUSE) {
+        __syncthreads();   // us complete; yp, zs and sc free
+        const int lane = threadIdx.x & (WAVE - 1);
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+        const int ntile = A.hpad / 16;
+        SynTile T = syn_tile_ptrs(A, m, wv < ntile ? wv : 0, lane);
+        uint4 pre[2][KB_SYN];
+        // staging row rp = (parity, row r), degree l = m + 2 r + parity, from us
+        const int srow = lds_row(A.kmax);
+        unsigned short* xp = ys;                   // [2][16][srow]
+        auto row_in = [&](int rp, double2* v) {
+            const int par = rp / A.kmax, r = rp - par * A.kmax;
+            const int i = 2 * r + par;
+            const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
+            const double2* u2 = reinterpret_cast<const double2*>(us);   // [Lm][3] complex
+            v[0] = u2[3 * ic];
+            v[1] = u2[3 * ic + 1];
+            v[2] = u2[3 * ic + 2];
+            v[3] = u2[3 * id + 1];
+            v[4] = u2[3 * id + 2];
+            v[5] = u2[3 * iu + 1];
+            v[6] = u2[3 * iu + 2];
+            return i;
+        };
+        if constexpr (SCALED) {
+            float* stage = zs;                     // [16][2 kmax] FP32
+            float cmax[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) cmax[c] = 0.f;
+            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+                double sf[5], vp[16];
+                double2 v[7];
+                if (rp == static_cast<int>(threadIdx.x)) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
+                } else {
+                    syn_factors(rp, sf);
+                }
+                const int i = row_in(rp, v);
+                state_row_values(v, sf, i, Lm, dm, vp);
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const float fv = static_cast<float>(vp[c]);
+                    stage[c * 2 * A.kmax + rp] = fv;
+                    cmax[c] = fmaxf(cmax[c], fabsf(fv));
+                }
+            }
+            column_scales<8, ANA_THREADS>(cmax, sred, sc);
+            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+                const int par = rp / A.kmax, r = rp - par * A.kmax;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    unsigned short hi, lo;
+                    const int o = (par * 16 + c) * srow;
+                    split16<E>(static_cast<double>(stage[c * 2 * A.kmax + rp] * sc[c]), hi, lo);
+                    xp[o + grp_hi(r)] = hi;
+                    xp[o + grp_lo(r)] = lo;
+                }
+            }
+        } else {
+            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+                double sf[5], vp[16];
+                double2 v[7];
+                if (rp == static_cast<int>(threadIdx.x)) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
+                } else {
+                    syn_factors(rp, sf);
+                }
+                const int i = row_in(rp, v);
+                state_row_values(v, sf, i, Lm, dm, vp);
+                const int par = rp / A.kmax, r = rp - par * A.kmax;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    unsigned short hi, lo;
+                    const int o = (par * 16 + c) * srow;
+                    split16<E>(vp[c], hi, lo);
+                    xp[o + grp_hi(r)] = hi;
+                    xp[o + grp_lo(r)] = lo;
+                }
+            }
+        }
+        // the even parity's first table batch of the wave's first tile
+        if (wv < ntile) load_syn_batch(T, 0, 0, pre[0]);
+        __syncthreads();
+        for (int tile = wv; tile < ntile; tile += ANA_WAVES) {
+            if (tile != wv) {
+                T = syn_tile_ptrs(A, m, tile, lane);
+                load_syn_batch(T, 0, 0, pre[0]);
+            }
+            synth_tile<1, E, true>(A, m, tile, 0, T, pre, xp, srow, sc, lane);
         }
     }
 }
@@ -870,6 +1033,7 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     size_t zbytes = kind == 1 ? sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax) : 0;
     if (ctx->prec & REXI_PREC_FP16_SPLIT) zbytes = std::max(zbytes, sizeof(float) * 16 * 2 * static_cast<size_t>(A.hpad));
     lds += zbytes;
+    A.zreg = static_cast<int>(zbytes);
     A.ntg = 1;
     A.ng = (nf + 7) / 8;
     const dim3 grid = kind == 0 ? dim3(split_grid_size(ctx->L + 1, A.ng)) : dim3(ctx->L + 1, 1, 1);
@@ -883,6 +1047,48 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
     const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
     void* kargs[] = {&A};
     REXI_HIP(hipLaunchKernel(fn, grid, dim3(ANA_THREADS), kargs, lds, stream));
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
+    return REXI_OK;
+}
+
+int fused_anal_synth_supported(const swe_ctx* ctx) { return ctx->tab_kmax <= ctx->tab_hpad; }
+
+int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, double* Nsave,
+                                     double* out, double c0, double* four_next, hipStream_t stream) {
+    if (!fused_anal_synth_supported(ctx))
+        return fail(REXI_ENOTSUP, "fused analysis and synthesis: degree rows exceed the latitude rows");
+    MfmaArgs A = mfma_args(ctx);
+    A.four_in = reinterpret_cast<const double2*>(four);
+    A.U0 = reinterpret_cast<const double2*>(U0);
+    A.Nprev = nullptr;
+    A.Nsave = reinterpret_cast<double2*>(Nsave);
+    A.out = reinterpret_cast<double2*>(out);
+    A.c0 = c0;
+    A.c1 = 0.0;
+    A.nf = 3;
+    // the synthesis output of the state: latitude-major [3][nlat][L+1]
+    A.four_out = reinterpret_cast<double2*>(four_next);
+    A.ofs = static_cast<long long>(ctx->L + 1) * ctx->nlat;
+    A.oms = 1;
+    A.ojs = ctx->L + 1;
+    A.ntg = 1;
+    A.ng = 1;
+    A.xcd_blocks = (ctx->L + 1) % 64 == 0;
+    size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.hpad));
+    size_t zbytes = sizeof(float) * 2 * 16 * static_cast<size_t>(A.kmax);
+    if (ctx->prec & REXI_PREC_FP16_SPLIT) zbytes = std::max(zbytes, sizeof(float) * 16 * 2 * static_cast<size_t>(A.hpad));
+    zbytes = (zbytes + 15) / 16 * 16;
+    A.zreg = static_cast<int>(zbytes);
+    lds += zbytes + sizeof(double) * 6 * static_cast<size_t>(ctx->L + 1);
+    const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
+    const void* fn = f16 ? reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1, F16, true>)
+                         : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1, Bf16, true>);
+    int rc;
+    if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
+    const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
+    void* kargs[] = {&A};
+    REXI_HIP(hipLaunchKernel(fn, dim3(ctx->L + 1), dim3(ANA_THREADS), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
     return REXI_OK;
