@@ -608,6 +608,7 @@ def main():
     fact_ms, fact_n = ctx.profile_read(api.KERNEL_FACTOR)
     for kid in range(api.KERNEL_FACTOR):
         ctx.profile_read(kid)
+    ctx.profile_read(api.KERNEL_LEG_FUSED)
     # timed region: HIP events around the dominant kernel's launches only
     ctx.profile_kernels([api.KERNEL_SOLVE])
     start = torch.cuda.Event(enable_timing=True)
@@ -633,7 +634,8 @@ def main():
     stage_ms = {}
     for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, "sum_partials_kernel"),
                       (api.KERNEL_LEG_SYNTH, "legendre_synth_kernel"), (api.KERNEL_RING, "ring_kernel"),
-                      (api.KERNEL_LEG_ANAL, "legendre_anal_kernel")]:
+                      (api.KERNEL_LEG_ANAL, "legendre_anal_kernel"),
+                      (api.KERNEL_LEG_FUSED, "legendre_anal_synth_kernel")]:
         ms, n = ctx.profile_read(kid)
         stage_ms[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
                           "ms_per_launch": ms / max(n, 1)}
@@ -707,6 +709,7 @@ def main():
     if full and (w.prec & (api.PREC_BF16_SPLIT | api.PREC_FP16_SPLIT)):
         syn = stage_ms["legendre_synth_kernel"]["ms_per_launch"]
         ana = stage_ms["legendre_anal_kernel"]["ms_per_launch"]
+        fus = stage_ms["legendre_anal_synth_kernel"]
         fl = split_mfma_flops(w.L, w.nlat)
         out["legendre_mfma"] = {
             "precision": ("bf16" if w.prec & api.PREC_BF16_SPLIT else "fp16") + " hi/lo split, 3 products, FP32 accumulation",
@@ -719,6 +722,16 @@ def main():
             "synth_GB_s": split_table_bytes(w.L, w.nlat) / (syn * 1e-3) / 1e9,
             "anal_GB_s": split_table_bytes(w.L, w.nlat) / (ana * 1e-3) / 1e9,
         }
+        if fus["launches_per_step"] > 0:
+            # a Heun step's first analysis fused with the next synthesis: both
+            # contractions and both tables per launch
+            t = fus["ms_per_launch"] * 1e-3
+            out["legendre_mfma"].update({
+                "fused_anal_synth_launches_per_step": fus["launches_per_step"],
+                "fused_TFLOP_s": 2 * fl / t / 1e12,
+                "fused_frac": 2 * fl / t / 1e12 / PEAK_BF16_MFMA,
+                "fused_GB_s": 2 * split_table_bytes(w.L, w.nlat) / t / 1e9,
+            })
     out["graph"] = graph_steps(ctx, full, alpha, beta, w, U, V, args.steps)
     ctx.close()
     if not args.no_arms:

@@ -374,7 +374,8 @@ enum {
     REXI_KERNEL_RING = 3,        /* longitude FFTs and pointwise products */
     REXI_KERNEL_LEG_ANAL = 4,    /* Legendre analysis (Fourier -> spectral) */
     REXI_KERNEL_FACTOR = 5,      /* pivots of the chain factorization (once per coefficient set and dt) */
-    REXI_KERNEL_COUNT = 6
+    REXI_KERNEL_LEG_FUSED = 6,   /* split precision: a Heun step's first analysis fused with the next synthesis */
+    REXI_KERNEL_COUNT = 7
 };
 int swe_profile(swe_ctx* ctx, int enable);
 /* The same for a subset: bit k of mask records kernel k (0 stops recording).

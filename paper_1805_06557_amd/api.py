@@ -15,7 +15,7 @@ from . import _lib
 REXI_OK, REXI_EINVAL, REXI_ENOMEM, REXI_EDEVICE, REXI_ENOTSUP, REXI_ENUMERIC = 0, -1, -2, -3, -4, -5
 FN_EXP, FN_PSI1, FN_PSI2 = 0, 1, 2
 PREC_FP64, PREC_FP32_SOLVE, PREC_BF16_SPLIT, PREC_FP16_SPLIT = 0, 1, 2, 4
-KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_FACTOR = range(6)
+KERNEL_SOLVE, KERNEL_REDUCE, KERNEL_LEG_SYNTH, KERNEL_RING, KERNEL_LEG_ANAL, KERNEL_FACTOR, KERNEL_LEG_FUSED = range(7)
 SOLVER_FUSED, SOLVER_STREAM, SOLVER_HYBRID = 1, 2, 3
 SPLIT_REXI_V1, SPLIT_REXI_V0, SPLIT_CN_V1, SPLIT_CN_V0, SPLIT_LG_REXI_V1 = 0, 1, 2, 3, 4
 EARTH = dict(a=6.37122e6, g=9.80616, H=1.0e4, Omega=7.292e-5)

@@ -1086,11 +1086,11 @@ int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const dou
                          : reinterpret_cast<const void*>(&leg_anal_mfma_kernel<1, Bf16, true>);
     int rc;
     if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
-    const int slot = prof_begin(ctx, REXI_KERNEL_LEG_ANAL, stream);
+    const int slot = prof_begin(ctx, REXI_KERNEL_LEG_FUSED, stream);
     void* kargs[] = {&A};
     REXI_HIP(hipLaunchKernel(fn, dim3(ctx->L + 1), dim3(ANA_THREADS), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
-    prof_end(ctx, REXI_KERNEL_LEG_ANAL, slot, stream);
+    prof_end(ctx, REXI_KERNEL_LEG_FUSED, slot, stream);
     return REXI_OK;
 }
 
