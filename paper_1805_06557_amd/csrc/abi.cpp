@@ -297,11 +297,14 @@ int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     return launch_axpy(U1, U1, -1.0, U0, 6 * ctx->modes, ctx->d_status, STATUS_REXI, stream);
 }
 
-int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream, double two_omega = 0.0) {
+// synth_done: the synthesis of U0 is already in ctx->d_part (the pole sum of
+// a REXI stage fused with it).
+int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream, double two_omega = 0.0,
+              bool synth_done = false) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
-    if ((rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
+    if (!synth_done && (rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
     if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
     if (split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
         // the analysis of each order synthesises its U* directly (one launch;
@@ -706,8 +709,20 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N
     int rc;
     if ((rc = prepare_poles(ctx, alpha, beta, N, dt, true, "swe_strang_step", stream)) != REXI_OK) return rc;
     if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
-    if ((rc = launch_rexi_solve(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, stream)) != REXI_OK) return rc;
-    return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream);
+    int nparts = 0;
+    if ((rc = launch_rexi_chain(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, &nparts, stream)) != REXI_OK) return rc;
+    bool synth_done = false;
+    if (nparts > 1 && split_legendre(ctx)) {
+        // the pole sum of each order synthesises its result for the next Heun step
+        if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
+        if ((rc = launch_rexi_sum_synth_split(ctx, ctx->d_partial, nparts, ctx->d_tmpB, ctx->d_part, stream)) !=
+            REXI_OK)
+            return rc;
+        synth_done = true;
+    } else if (nparts > 1 && (rc = launch_rexi_sum(ctx, nparts, ctx->d_tmpB, stream)) != REXI_OK) {
+        return rc;
+    }
+    return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream, 0.0, synth_done);
 }
 
 int swe_cn_step(swe_ctx* ctx, double dt, const double* U0, double* U1, hipStream_t stream) {

@@ -256,9 +256,32 @@ __device__ __forceinline__ void note_nonfinite(unsigned* status, double v, unsig
     if (!__builtin_isfinite(v)) atomicOr(status, bit);
 }
 
+// Sum over pole waves of part[pw][i] (pole waves of count entries each), in
+// pole-wave order, with Neumaier compensation: the REXI stage's pole sum.
+__device__ __forceinline__ double2 sum_parts(const double2* __restrict__ part, int count, int nparts, int i) {
+    double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
+    for (int b = 0; b < nparts; ++b) {
+        const double2 v = part[static_cast<size_t>(b) * count + i];
+        double t = sx + v.x;
+        cx += (fabs(sx) >= fabs(v.x)) ? (sx - t) + v.x : (v.x - t) + sx;
+        sx = t;
+        t = sy + v.y;
+        cy += (fabs(sy) >= fabs(v.y)) ? (sy - t) + v.y : (v.y - t) + sy;
+        sy = t;
+    }
+    return make_double2(sx + cx, sy + cy);
+}
+
 // Launches the chain solve + reduction for one REXI stage on `stream`.
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1,
                       hipStream_t stream);
+// The chain solve alone: *nparts receives the number of pole-wave partial sums
+// it left in ctx->d_partial ([nparts][3 modes]); with one pole wave the solve
+// wrote U1 itself (*nparts = 1).
+int launch_rexi_chain(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, int* nparts,
+                      hipStream_t stream);
+// U1 = the pole sum of the nparts partials the chain solve left (nparts > 1).
+int launch_rexi_sum(swe_ctx* ctx, int nparts, double* U1, hipStream_t stream);
 
 // One member of an ensemble REXI stage (poles already prepared in ctx).
 struct BatchMember {
@@ -299,6 +322,11 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
 // kind-1 synthesis writes them).  Needs the table's degree rows per parity to
 // fit the latitude rows (fused_anal_synth_supported).
 int fused_anal_synth_supported(const swe_ctx* ctx);
+// The REXI stage's pole sum over nparts partials ([nparts][3 modes] complex)
+// into U1, fused with the split synthesis of U1 into four_next (latitude-major,
+// as the kind-1 synthesis writes it).
+int launch_rexi_sum_synth_split(swe_ctx* ctx, const double* part, int nparts, double* U1, double* four_next,
+                                hipStream_t stream);
 int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, double* Nsave,
                                      double* out, double c0, double* four_next, hipStream_t stream);
 // The REXI stage of the gravity-wave part L_g alone (Coriolis-free): per degree

@@ -715,21 +715,6 @@ __global__ __launch_bounds__(256) void rexi_factor_kernel(const RecT<T>* __restr
     }
 }
 
-// sum over pole waves of part[pw][i], in pole-wave order, compensated.
-__device__ __forceinline__ double2 sum_parts(const double2* __restrict__ part, int count, int nparts, int i) {
-    double sx = 0.0, sy = 0.0, cx = 0.0, cy = 0.0;
-    for (int b = 0; b < nparts; ++b) {
-        const double2 v = part[static_cast<size_t>(b) * count + i];
-        double t = sx + v.x;
-        cx += (fabs(sx) >= fabs(v.x)) ? (sx - t) + v.x : (v.x - t) + sx;
-        sx = t;
-        t = sy + v.y;
-        cy += (fabs(sy) >= fabs(v.y)) ? (sy - t) + v.y : (v.y - t) + sy;
-        sy = t;
-    }
-    return make_double2(sx + cx, sy + cy);
-}
-
 __global__ __launch_bounds__(256) void sum_partials_kernel(const double2* __restrict__ part,
                                                            double2* __restrict__ U1, int count, int nparts,
                                                            unsigned* status) {
@@ -1078,10 +1063,32 @@ int base_args(swe_ctx* ctx, int N, double dt, const double* U0, const double* U1
 }  // namespace
 
 int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream) {
+    int nparts = 0;
+    int rc = launch_rexi_chain(ctx, N, dt, U0, U1, &nparts, stream);
+    if (rc != REXI_OK) return rc;
+    return nparts > 1 ? launch_rexi_sum(ctx, nparts, U1, stream) : REXI_OK;
+}
+
+int launch_rexi_sum(swe_ctx* ctx, int nparts, double* U1, hipStream_t stream) {
+    const int threads = 256;
+    const int count = 3 * ctx->modes;
+    const unsigned blocks = static_cast<unsigned>((count + threads - 1) / threads);
+    const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks), dim3(threads), 0, stream,
+                       reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1), count,
+                       nparts, ctx->d_status);
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
+    return REXI_OK;
+}
+
+int launch_rexi_chain(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, int* nparts_out,
+                      hipStream_t stream) {
     SolveArgs A;
     int nparts = 0;
     int rc = base_args(ctx, N, dt, U0, U1, ctx->tune.poles_per_lane, A, nparts);
     if (rc != REXI_OK) return rc;
+    *nparts_out = nparts;
     if (ctx->tune.solver == REXI_SOLVER_STREAM || ctx->tune.solver == REXI_SOLVER_HYBRID) {
         // the streaming schedules read (and factorize) records built in HBM
         hipLaunchKernelGGL(rexi_rows_kernel, dim3(ctx->L + 1), dim3(256), 0, stream,
@@ -1090,20 +1097,7 @@ int launch_rexi_solve(swe_ctx* ctx, int N, double dt, const double* U0, double* 
         REXI_HIP(hipGetLastError());
     }
     const bool fp32 = (ctx->prec & REXI_PREC_FP32_SOLVE) != 0;
-    rc = fp32 ? launch_shape<float>(ctx, A, ctx->tune, stream) : launch_shape<double>(ctx, A, ctx->tune, stream);
-    if (rc != REXI_OK) return rc;
-    if (nparts > 1) {
-        const int threads = 256;
-        const int count = 3 * ctx->modes;
-        const unsigned blocks = static_cast<unsigned>((count + threads - 1) / threads);
-        const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
-        hipLaunchKernelGGL(sum_partials_kernel, dim3(blocks), dim3(threads), 0, stream,
-                           reinterpret_cast<const double2*>(ctx->d_partial), reinterpret_cast<double2*>(U1), count,
-                           nparts, ctx->d_status);
-        REXI_HIP(hipGetLastError());
-        prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
-    }
-    return REXI_OK;
+    return fp32 ? launch_shape<float>(ctx, A, ctx->tune, stream) : launch_shape<double>(ctx, A, ctx->tune, stream);
 }
 
 namespace {

@@ -42,6 +42,8 @@ constexpr int WAVE = 64;
 constexpr int KB_SYN = 9;    // table K steps loaded per batch, synthesis (T255: one batch)
 constexpr int KB_ANA = 12;   // and analysis
 constexpr int SYN_THREADS = 256;   // synthesis block size (4 latitude tiles)
+constexpr int ANA_WAVES = 16;      // analysis (and per-order synthesis) waves per workgroup
+constexpr int ANA_THREADS = ANA_WAVES * WAVE;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
@@ -572,6 +574,128 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
     synth_tile<KIND, E>(A, m, tile, f0, T, pre, xp, rowlen, sc, lane);
 }
 
+// The synthesis factors of staging row rp = (parity, row r), degree
+// l = m + 2 r + parity (indices clamped into the order): a/N_l, hA_{l-1},
+// a/N_{l-1}, hB_{l+1}, a/N_{l+1}.
+__device__ __forceinline__ void syn_factors(const MfmaArgs& A, int m, int rp, double* sf) {
+    const int Lm = A.L - m + 1;
+    const int base = m * (2 * A.L + 3 - m) / 2;
+    const int par = rp / A.kmax, r = rp - par * A.kmax;
+    const int i = 2 * r + par;
+    const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
+    sf[0] = A.aon[m + ic];
+    sf[1] = A.rec[base + id].hA;
+    sf[2] = A.aon[m + id];
+    sf[3] = A.rec[base + iu].hB;
+    sf[4] = A.aon[m + iu];
+}
+
+// Synthesis of the state of order m for every latitude by a workgroup of
+// ANA_THREADS threads, from its coefficients us in LDS ([L-m+1][3] complex:
+// h, zeta, delta; complete before the call).  syn_s holds the synthesis
+// factors of the thread's first staging row (syn_factors, threads < 2 kmax).
+// LDS: the B operand goes to ys ([2][16][lds_row(kmax)] shorts), FP16 mode
+// stages FP32 values in zs ([16][2 kmax] floats); sred and sc take the column
+// scales.  The waves take the latitude tiles in turn; the Fourier coefficients
+// go to four_out (f ofs + m oms + j ojs).
+template <class E>
+__device__ void synth_state_block(const MfmaArgs& A, int m, const double* us, const double* syn_s,
+                                  unsigned short* ys, float* zs, float* sred, float* sc) {
+    constexpr bool SCALED = std::is_same<E, F16>::value;
+    const int Lm = A.L - m + 1;
+    const double dm = static_cast<double>(m);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int ntile = A.hpad / 16;
+    SynTile T = syn_tile_ptrs(A, m, wv < ntile ? wv : 0, lane);
+    uint4 pre[2][KB_SYN];
+    // staging row rp = (parity, row r), degree l = m + 2 r + parity, from us
+    const int srow = lds_row(A.kmax);
+    unsigned short* xp = ys;                   // [2][16][srow]
+    auto row_in = [&](int rp, double2* v) {
+        const int par = rp / A.kmax, r = rp - par * A.kmax;
+        const int i = 2 * r + par;
+        const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
+        const double2* u2 = reinterpret_cast<const double2*>(us);   // [Lm][3] complex
+        v[0] = u2[3 * ic];
+        v[1] = u2[3 * ic + 1];
+        v[2] = u2[3 * ic + 2];
+        v[3] = u2[3 * id + 1];
+        v[4] = u2[3 * id + 2];
+        v[5] = u2[3 * iu + 1];
+        v[6] = u2[3 * iu + 2];
+        return i;
+    };
+    if constexpr (SCALED) {
+        float* stage = zs;                     // [16][2 kmax] FP32
+        float cmax[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) cmax[c] = 0.f;
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+            double sf[5], vp[16];
+            double2 v[7];
+            if (rp == static_cast<int>(threadIdx.x)) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
+            } else {
+                syn_factors(A, m, rp, sf);
+            }
+            const int i = row_in(rp, v);
+            state_row_values(v, sf, i, Lm, dm, vp);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const float fv = static_cast<float>(vp[c]);
+                stage[c * 2 * A.kmax + rp] = fv;
+                cmax[c] = fmaxf(cmax[c], fabsf(fv));
+            }
+        }
+        column_scales<8, ANA_THREADS>(cmax, sred, sc);
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+            const int par = rp / A.kmax, r = rp - par * A.kmax;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                unsigned short hi, lo;
+                const int o = (par * 16 + c) * srow;
+                split16<E>(static_cast<double>(stage[c * 2 * A.kmax + rp] * sc[c]), hi, lo);
+                xp[o + grp_hi(r)] = hi;
+                xp[o + grp_lo(r)] = lo;
+            }
+        }
+    } else {
+        for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
+            double sf[5], vp[16];
+            double2 v[7];
+            if (rp == static_cast<int>(threadIdx.x)) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
+            } else {
+                syn_factors(A, m, rp, sf);
+            }
+            const int i = row_in(rp, v);
+            state_row_values(v, sf, i, Lm, dm, vp);
+            const int par = rp / A.kmax, r = rp - par * A.kmax;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                unsigned short hi, lo;
+                const int o = (par * 16 + c) * srow;
+                split16<E>(vp[c], hi, lo);
+                xp[o + grp_hi(r)] = hi;
+                xp[o + grp_lo(r)] = lo;
+            }
+        }
+    }
+    // the even parity's first table batch of the wave's first tile
+    if (wv < ntile) load_syn_batch(T, 0, 0, pre[0]);
+    __syncthreads();
+    for (int tile = wv; tile < ntile; tile += ANA_WAVES) {
+        if (tile != wv) {
+            T = syn_tile_ptrs(A, m, tile, lane);
+            load_syn_batch(T, 0, 0, pre[0]);
+        }
+        synth_tile<1, E, true>(A, m, tile, 0, T, pre, xp, srow, sc, lane);
+    }
+}
+
 // ----------------------------------------------------------------- analysis --
 // Workgroup (split_item, one tile group): order m, ANA_WAVES waves taking the row tiles of 16
 // degrees of one parity (even-parity tiles first) in turn.  LDS: the B operand
@@ -587,8 +711,6 @@ __global__ __launch_bounds__(SYN_THREADS) void leg_synth_mfma_kernel(MfmaArgs A)
 //   Z[l][k] + hA_l Z[l+1][8+k] + hB_l Z[l-1][8+k] (+ l(l+1)/a^2 Z[l][k+2], k >= 4)
 // giving N_h (k 0-1), N_zeta (2-3), N_delta (4-5); then out = U0 + c0 N + c1 Nprev
 // and Nsave = N (FP64).
-constexpr int ANA_WAVES = 16;
-constexpr int ANA_THREADS = ANA_WAVES * WAVE;   // the launch's block size
 
 // FUSE (KIND 1 only): the workgroup then synthesises the outputs of its order
 // for the next evaluation (the stage-1 state of a Heun step): they stay in LDS
@@ -616,18 +738,8 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     // FUSE: the synthesis staging's per-degree factors of the thread's first
     // staging row (a/N and the H coefficients), requested now
     double syn_s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    auto syn_factors = [&](int rp, double* sf) {
-        const int par = rp / A.kmax, r = rp - par * A.kmax;
-        const int i = 2 * r + par;
-        const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
-        sf[0] = A.aon[m + ic];
-        sf[1] = A.rec[base + id].hA;
-        sf[2] = A.aon[m + id];
-        sf[3] = A.rec[base + iu].hB;
-        sf[4] = A.aon[m + iu];
-    };
     if constexpr (FUSE) {
-        if (static_cast<int>(threadIdx.x) < 2 * A.kmax) syn_factors(threadIdx.x, syn_s);
+        if (static_cast<int>(threadIdx.x) < 2 * A.kmax) syn_factors(A, m, threadIdx.x, syn_s);
     }
     // KIND 1: the epilogue's inputs that do not depend on the products (H
     // coefficients, l(l+1)/a^2, U0 + c1 Nprev) of the thread's first EPI items
@@ -828,97 +940,41 @@ __global__ __launch_bounds__(ANA_WAVES * WAVE) void leg_anal_mfma_kernel(MfmaArg
     }
     if constexpr (FUSE) {
         __syncthreads();   // us complete; yp, zs and sc free
-        const int lane = threadIdx.x & (WAVE - 1);
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-        const int ntile = A.hpad / 16;
-        SynTile T = syn_tile_ptrs(A, m, wv < ntile ? wv : 0, lane);
-        uint4 pre[2][KB_SYN];
-        // staging row rp = (parity, row r), degree l = m + 2 r + parity, from us
-        const int srow = lds_row(A.kmax);
-        unsigned short* xp = ys;                   // [2][16][srow]
-        auto row_in = [&](int rp, double2* v) {
-            const int par = rp / A.kmax, r = rp - par * A.kmax;
-            const int i = 2 * r + par;
-            const int ic = min(i, Lm - 1), id = max(min(i - 1, Lm - 1), 0), iu = min(i + 1, Lm - 1);
-            const double2* u2 = reinterpret_cast<const double2*>(us);   // [Lm][3] complex
-            v[0] = u2[3 * ic];
-            v[1] = u2[3 * ic + 1];
-            v[2] = u2[3 * ic + 2];
-            v[3] = u2[3 * id + 1];
-            v[4] = u2[3 * id + 2];
-            v[5] = u2[3 * iu + 1];
-            v[6] = u2[3 * iu + 2];
-            return i;
-        };
-        if constexpr (SCALED) {
-            float* stage = zs;                     // [16][2 kmax] FP32
-            float cmax[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) cmax[c] = 0.f;
-            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
-                double sf[5], vp[16];
-                double2 v[7];
-                if (rp == static_cast<int>(threadIdx.x)) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
-                } else {
-                    syn_factors(rp, sf);
-                }
-                const int i = row_in(rp, v);
-                state_row_values(v, sf, i, Lm, dm, vp);
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const float fv = static_cast<float>(vp[c]);
-                    stage[c * 2 * A.kmax + rp] = fv;
-                    cmax[c] = fmaxf(cmax[c], fabsf(fv));
-                }
-            }
-            column_scales<8, ANA_THREADS>(cmax, sred, sc);
-            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
-                const int par = rp / A.kmax, r = rp - par * A.kmax;
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    unsigned short hi, lo;
-                    const int o = (par * 16 + c) * srow;
-                    split16<E>(static_cast<double>(stage[c * 2 * A.kmax + rp] * sc[c]), hi, lo);
-                    xp[o + grp_hi(r)] = hi;
-                    xp[o + grp_lo(r)] = lo;
-                }
-            }
-        } else {
-            for (int rp = threadIdx.x; rp < 2 * A.kmax; rp += ANA_THREADS) {
-                double sf[5], vp[16];
-                double2 v[7];
-                if (rp == static_cast<int>(threadIdx.x)) {
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) sf[q] = syn_s[q];
-                } else {
-                    syn_factors(rp, sf);
-                }
-                const int i = row_in(rp, v);
-                state_row_values(v, sf, i, Lm, dm, vp);
-                const int par = rp / A.kmax, r = rp - par * A.kmax;
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    unsigned short hi, lo;
-                    const int o = (par * 16 + c) * srow;
-                    split16<E>(vp[c], hi, lo);
-                    xp[o + grp_hi(r)] = hi;
-                    xp[o + grp_lo(r)] = lo;
-                }
-            }
-        }
-        // the even parity's first table batch of the wave's first tile
-        if (wv < ntile) load_syn_batch(T, 0, 0, pre[0]);
-        __syncthreads();
-        for (int tile = wv; tile < ntile; tile += ANA_WAVES) {
-            if (tile != wv) {
-                T = syn_tile_ptrs(A, m, tile, lane);
-                load_syn_batch(T, 0, 0, pre[0]);
-            }
-            synth_tile<1, E, true>(A, m, tile, 0, T, pre, xp, srow, sc, lane);
-        }
+        synth_state_block<E>(A, m, us, syn_s, ys, zs, sred, sc);
     }
+}
+
+// The REXI stage's pole sum fused with the synthesis of its result (split
+// precision): the workgroup of order m sums the pole-wave partials of its
+// order's coefficients (sum_parts, the order of the separate reduction),
+// writes them to U1, keeps them in LDS and synthesises them for every
+// latitude (synth_state_block).  Order of workgroups as split_item<1>.
+// LDS: [2][16][lds_row(kmax)] shorts, then A.zreg bytes (FP16 staging), then
+// us ([L+1][3] complex).
+template <class E>
+__global__ __launch_bounds__(ANA_THREADS) void leg_sum_synth_mfma_kernel(MfmaArgs A, const double2* __restrict__ part,
+                                                                         int nparts, double2* __restrict__ U1) {
+    extern __shared__ __align__(16) unsigned short ys[];
+    __shared__ float sred[ANA_WAVES * 16], sc[16];
+    int m, tg, g;
+    if (!split_item<1>(A, m, tg, g)) return;
+    const int Lm = A.L - m + 1;
+    const int base = m * (2 * A.L + 3 - m) / 2;
+    float* zs = reinterpret_cast<float*>(ys + 2 * 16 * lds_row(A.kmax));
+    double* us = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(zs) + A.zreg);
+    double syn_s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (static_cast<int>(threadIdx.x) < 2 * A.kmax) syn_factors(A, m, threadIdx.x, syn_s);
+    double2* u2 = reinterpret_cast<double2*>(us);
+    for (int it = threadIdx.x; it < 3 * Lm; it += ANA_THREADS) {
+        const int i = it / 3, f = it - 3 * i;
+        const int e = f * A.modes + base + i;
+        const double2 v = sum_parts(part, 3 * A.modes, nparts, e);
+        note_nonfinite(A.status, v.x + v.y, STATUS_REXI);
+        U1[e] = v;
+        u2[it] = v;
+    }
+    __syncthreads();
+    synth_state_block<E>(A, m, us, syn_s, ys, zs, sred, sc);
 }
 
 MfmaArgs mfma_args(const swe_ctx* ctx) {
@@ -1091,6 +1147,38 @@ int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const dou
     REXI_HIP(hipLaunchKernel(fn, dim3(ctx->L + 1), dim3(ANA_THREADS), kargs, lds, stream));
     REXI_HIP(hipGetLastError());
     prof_end(ctx, REXI_KERNEL_LEG_FUSED, slot, stream);
+    return REXI_OK;
+}
+
+int launch_rexi_sum_synth_split(swe_ctx* ctx, const double* part, int nparts, double* U1, double* four_next,
+                                hipStream_t stream) {
+    if (nparts < 1) return fail(REXI_EINVAL, "pole sum and synthesis: no partial sums");
+    MfmaArgs A = mfma_args(ctx);
+    A.nf = 3;
+    A.four_out = reinterpret_cast<double2*>(four_next);
+    A.ofs = static_cast<long long>(ctx->L + 1) * ctx->nlat;
+    A.oms = 1;
+    A.ojs = ctx->L + 1;
+    A.ntg = 1;
+    A.ng = 1;
+    A.xcd_blocks = (ctx->L + 1) % 64 == 0;
+    size_t lds = sizeof(unsigned short) * 2 * 16 * static_cast<size_t>(lds_row(A.kmax));
+    size_t zbytes = (ctx->prec & REXI_PREC_FP16_SPLIT) ? sizeof(float) * 16 * 2 * static_cast<size_t>(A.kmax) : 0;
+    zbytes = (zbytes + 15) / 16 * 16;
+    A.zreg = static_cast<int>(zbytes);
+    lds += zbytes + sizeof(double) * 6 * static_cast<size_t>(ctx->L + 1);
+    const bool f16 = (ctx->prec & REXI_PREC_FP16_SPLIT) != 0;
+    const void* fn = f16 ? reinterpret_cast<const void*>(&leg_sum_synth_mfma_kernel<F16>)
+                         : reinterpret_cast<const void*>(&leg_sum_synth_mfma_kernel<Bf16>);
+    int rc;
+    if ((rc = allow_dyn_lds(fn, lds)) != REXI_OK) return rc;
+    const double2* p = reinterpret_cast<const double2*>(part);
+    double2* u = reinterpret_cast<double2*>(U1);
+    const int slot = prof_begin(ctx, REXI_KERNEL_REDUCE, stream);
+    void* kargs[] = {&A, &p, &nparts, &u};
+    REXI_HIP(hipLaunchKernel(fn, dim3(ctx->L + 1), dim3(ANA_THREADS), kargs, lds, stream));
+    REXI_HIP(hipGetLastError());
+    prof_end(ctx, REXI_KERNEL_REDUCE, slot, stream);
     return REXI_OK;
 }
 
