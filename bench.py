@@ -632,7 +632,10 @@ def main():
         U, V = V, U
     torch.cuda.synchronize()
     stage_ms = {}
-    for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, "sum_partials_kernel"),
+    split = bool(w.prec & (api.PREC_BF16_SPLIT | api.PREC_FP16_SPLIT))
+    # in a split-precision Strang step the pole sum is fused with the synthesis of its result
+    reduce_name = "pole_sum_synth_kernel" if (full and split) else "sum_partials_kernel"
+    for kid, name in [(api.KERNEL_SOLVE, "rexi_chain_kernel"), (api.KERNEL_REDUCE, reduce_name),
                       (api.KERNEL_LEG_SYNTH, "legendre_synth_kernel"), (api.KERNEL_RING, "ring_kernel"),
                       (api.KERNEL_LEG_ANAL, "legendre_anal_kernel"),
                       (api.KERNEL_LEG_FUSED, "legendre_anal_synth_kernel")]:
