@@ -416,6 +416,19 @@ int swe_set_tuning(swe_ctx* ctx, int solver, int seg_rows, int waves, int poles_
 int swe_get_tuning(swe_ctx* ctx, int* solver, int* seg_rows, int* waves, int* poles_per_lane);
 
 /*
+ * swe_set_fusion -- launch fusion of the split-precision transforms (contexts
+ * created with REXI_PREC_BF16_SPLIT or REXI_PREC_FP16_SPLIT): with enable = 1
+ * (the default) the first analysis of every Heun step is fused with the
+ * synthesis of its output, and in swe_strang_step the pole sum of the REXI
+ * stage with the synthesis of its result; 0 runs the separate launches.  The
+ * result bits are the same either way (Section 3.2 transforms; Section 4.4
+ * splitting).  swe_get_fusion returns the setting.
+ * Errors: REXI_EINVAL (NULL context or pointer, enable not 0 or 1).
+ */
+int swe_set_fusion(swe_ctx* ctx, int enable);
+int swe_get_fusion(swe_ctx* ctx, int* enable);
+
+/*
  * swe_autotune -- times every supported schedule and launch shape of the REXI
  * stage on this problem (reps timed calls each, after one untimed call that
  * also builds a factorization where the schedule needs one) with HIP events

@@ -45,6 +45,8 @@ SIGNATURES = {
     "rexi_last_error": (ctypes.c_char_p, []),
     "swe_set_tuning": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int]),
     "swe_get_tuning": (_c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "swe_set_fusion": (_c_int, [_vp, _c_int]),
+    "swe_get_fusion": (_c_int, [_vp, _ip]),
     "swe_autotune": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _c_int, _vp, _dp]),
     "rexi_linear_step_batched": (_c_int, [ctypes.POINTER(RexiMember), _c_int, _vp]),
     "swe_profile": (_c_int, [_vp, _c_int]),

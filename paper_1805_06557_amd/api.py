@@ -161,6 +161,15 @@ class SWE:
         """Schedule (SOLVER_*) and launch shape of the REXI solve; 0 keeps a value."""
         _check(self._lib.swe_set_tuning(self._h, solver, seg_rows, waves, poles_per_lane), "swe_set_tuning")
 
+    def set_fusion(self, enable: bool) -> None:
+        """Fused split-precision transform launches (default on; same result bits)."""
+        _check(self._lib.swe_set_fusion(self._h, 1 if enable else 0), "swe_set_fusion")
+
+    def get_fusion(self) -> bool:
+        v = ctypes.c_int()
+        _check(self._lib.swe_get_fusion(self._h, ctypes.byref(v)), "swe_get_fusion")
+        return bool(v.value)
+
     def get_tuning(self) -> dict:
         v = [ctypes.c_int() for _ in range(4)]
         _check(self._lib.swe_get_tuning(self._h, *[ctypes.byref(x) for x in v]), "swe_get_tuning")

@@ -306,7 +306,7 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
     if (!synth_done && (rc = to_fourier(ctx, 1, U0, 3, stream)) != REXI_OK) return rc;
     if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
-    if (split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
+    if (ctx->fuse && split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
         // the analysis of each order synthesises its U* directly (one launch;
         // U* is not stored)
         if ((rc = launch_legendre_anal_synth_split(ctx, ctx->d_fout, U0, ctx->d_n0, nullptr, tau, ctx->d_part,
@@ -534,6 +534,19 @@ int swe_set_tuning(swe_ctx* ctx, int solver, int seg_rows, int waves, int poles_
     return REXI_OK;
 }
 
+int swe_set_fusion(swe_ctx* ctx, int enable) {
+    if (!ctx) return fail(REXI_EINVAL, "swe_set_fusion: NULL context");
+    if (enable != 0 && enable != 1) return fail(REXI_EINVAL, "swe_set_fusion: enable must be 0 or 1");
+    ctx->fuse = enable != 0;
+    return REXI_OK;
+}
+
+int swe_get_fusion(swe_ctx* ctx, int* enable) {
+    if (!ctx || !enable) return fail(REXI_EINVAL, "swe_get_fusion: NULL argument");
+    *enable = ctx->fuse ? 1 : 0;
+    return REXI_OK;
+}
+
 int rexi_linear_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
                      const double* U0, double* U1, hipStream_t stream) {
     if (!ctx) return fail(REXI_EINVAL, "rexi_linear_step: NULL context");
@@ -712,7 +725,7 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N
     int nparts = 0;
     if ((rc = launch_rexi_chain(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, &nparts, stream)) != REXI_OK) return rc;
     bool synth_done = false;
-    if (nparts > 1 && split_legendre(ctx)) {
+    if (nparts > 1 && ctx->fuse && split_legendre(ctx)) {
         // the pole sum of each order synthesises its result for the next Heun step
         if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
         if ((rc = launch_rexi_sum_synth_split(ctx, ctx->d_partial, nparts, ctx->d_tmpB, ctx->d_part, stream)) !=

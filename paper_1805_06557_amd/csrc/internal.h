@@ -168,6 +168,7 @@ struct swe_ctx {
     // swe_sync (bit flags rexi::STATUS_*), set with vector atomics
     unsigned* d_status = nullptr;
     rexi::Tuning tune;
+    bool fuse = true;                  // swe_set_fusion
     rexi::Profiler prof;
 
     // REXI tables

@@ -56,6 +56,8 @@ def test_null_context_and_pointers_are_rejected():
     assert lib.swe_destroy(None) == 0
     assert lib.swe_sync(None) == api.REXI_EINVAL
     assert lib.rexi_linear_step(None, None, None, 2, 1.0, None, None, None) == api.REXI_EINVAL
+    assert lib.swe_set_fusion(None, 1) == api.REXI_EINVAL
+    assert lib.swe_get_fusion(None, None) == api.REXI_EINVAL
     assert b"NULL" in lib.rexi_last_error()
     out = ctypes.c_void_p()
     assert lib.swe_create(0, 0, 0, 1.0, 1.0, 1.0, 0.0, 0, ctypes.byref(out)) == api.REXI_EINVAL
