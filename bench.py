@@ -49,7 +49,7 @@ STREAM_BYTES_PER_POLE_UNKNOWN = {True: 16, False: 32}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, each
 # scaled by the same counter on a copy of known size (the chain-kernel summary under profiles/).
 # Valid only for the kernel source (sha256) and launch shape they were taken with.
-_D = "10a5fdc7883d061b150f57c2c5ca05fa6001112812081432dc34c35d82cc23ae"
+_D = "8236cc538d96de840874d140be04e1ea620ca70b68d5f13feabf2e1e8af7532f"
 MEASURED_TRAFFIC = {
     # FP32 fused solve at T255, N = 800 (the same launch in the FP32 workloads:
     # only the Legendre stage around it differs): 110.0 MB read + 121.2 MB written
