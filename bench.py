@@ -344,25 +344,25 @@ def graph_steps(ctx, full, alpha, beta, w, U, V, steps):
     between, must equal two eager steps bit for bit; then the replays are timed."""
     import torch
 
-    def one(src, dst, s):
+    def two(s):
+        # U -> U over two steps (a full step as one two-step swe_strang_steps call)
         if full:
-            ctx.strang_step(alpha, beta, w.dt, src, dst, s)
+            ctx.strang_steps(alpha, beta, w.dt, 2, U, U, s)
         else:
-            ctx.rexi_linear_step(alpha, beta, w.dt, src, dst, s)
+            ctx.rexi_linear_step(alpha, beta, w.dt, U, V, s)
+            ctx.rexi_linear_step(alpha, beta, w.dt, V, U, s)
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     ctx.profile(False)
     with torch.cuda.stream(side):
         S0 = U.clone()
-        one(U, V, side)
-        one(V, U, side)
+        two(side)
         ref = U.clone()
         g = torch.cuda.CUDAGraph()
         U.copy_(S0)
         with torch.cuda.graph(g, stream=side):
-            one(U, V, side)
-            one(V, U, side)
+            two(side)
         same = True
         for _ in range(3):
             U.copy_(S0)
@@ -599,10 +599,21 @@ def main():
         else:
             ctx.rexi_linear_step(alpha, beta, w.dt, src, dst, stream)
 
+    def run_steps(n, src, dst):
+        """n steps from src; returns (result, other buffer).  A full step runs as
+        one swe_strang_steps call (bit-identical to n single steps; in split
+        precision it fuses the last analysis of a step with the next synthesis)."""
+        if full:
+            ctx.strang_steps(alpha, beta, w.dt, n, src, dst, stream)
+            return dst, src
+        for _ in range(n):
+            step(src, dst)
+            src, dst = dst, src
+        return src, dst
+
     ctx.profile(True)
-    for i in range(args.warmup):
-        step(U, V)
-        U, V = V, U
+    if args.warmup:
+        U, V = run_steps(args.warmup, U, V)
     torch.cuda.synchronize()
     # the factorization of the streaming schedules is built by the first call
     fact_ms, fact_n = ctx.profile_read(api.KERNEL_FACTOR)
@@ -616,9 +627,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    for i in range(args.steps):
-        step(U, V)
-        U, V = V, U
+    U, V = run_steps(args.steps, U, V)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -627,9 +636,7 @@ def main():
     # a second pass of the same steps with HIP events around every kernel launch
     # for the per-stage breakdown (their gaps would add to a timed step)
     ctx.profile(True)
-    for i in range(args.steps):
-        step(U, V)
-        U, V = V, U
+    U, V = run_steps(args.steps, U, V)
     torch.cuda.synchronize()
     stage_ms = {}
     split = bool(w.prec & (api.PREC_BF16_SPLIT | api.PREC_FP16_SPLIT))

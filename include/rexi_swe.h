@@ -296,6 +296,19 @@ int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta,
                     int N, double dt, const double* U0, double* U1,
                     hipStream_t stream);
 
+/*
+ * swe_strang_steps -- nsteps (>= 1) consecutive swe_strang_step steps from U0,
+ * the result in U1 (U1 may equal U0).  Same result bits as nsteps separate
+ * calls; in split-precision contexts with fusion on (swe_set_fusion) the last
+ * analysis of each step is fused with the first synthesis of the next, which
+ * separate calls cannot do.  The states between steps are kept in U1 and in
+ * the context's own buffer.
+ * Errors: as swe_strang_step; REXI_EINVAL for nsteps < 1.
+ */
+int swe_strang_steps(swe_ctx* ctx, const double* alpha, const double* beta,
+                     int N, double dt, int nsteps, const double* U0, double* U1,
+                     hipStream_t stream);
+
 /* swe_sync -- waits for all work on the context's device; returns REXI_EDEVICE
  * if the device reported an error, and REXI_ENUMERIC if any kernel of this
  * context wrote a non-finite value (NaN or infinity) into an output since the

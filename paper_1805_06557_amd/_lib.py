@@ -38,6 +38,7 @@ SIGNATURES = {
     "sh_analysis": (_c_int, [_vp, _vp, _vp, _c_int, _vp]),
     "swe_nonlinear_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),
     "swe_strang_step": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
+    "swe_strang_steps": (_c_int, [_vp, _dp, _dp, _c_int, _c_double, _c_int, _vp, _vp, _vp]),
     "swe_etdrk2_step": (_c_int, [_vp, _dp, _dp, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),
     "swe_cn_step": (_c_int, [_vp, _c_double, _vp, _vp, _vp]),
     "swe_split_step": (_c_int, [_vp, _c_int, _dp, _dp, _c_int, _c_double, _vp, _vp, _vp]),

@@ -234,6 +234,14 @@ class SWE:
                                          _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
                                          _stream_handle(stream)), "swe_strang_step")
 
+    def strang_steps(self, alpha, beta, dt: float, nsteps: int, U0, U1, stream=None) -> None:
+        """nsteps Strang steps from U0, result in U1 (bit-identical to separate steps)."""
+        a = _host_coeffs(alpha)
+        b = _host_coeffs(beta)
+        _check(self._lib.swe_strang_steps(self._h, _dptr(a), _dptr(b), a.size // 2, float(dt), int(nsteps),
+                                          _state_ptr(U0, self.L, 3, "U0"), _state_ptr(U1, self.L, 3, "U1"),
+                                          _stream_handle(stream)), "swe_strang_steps")
+
     def cn_step(self, dt: float, U0, U1, stream=None) -> None:
         """Crank-Nicolson step of the linear part (U0 and U1 must differ)."""
         _check(self._lib.swe_cn_step(self._h, float(dt), _state_ptr(U0, self.L, 3, "U0"),

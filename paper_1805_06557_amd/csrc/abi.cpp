@@ -208,6 +208,7 @@ int setup_sht(swe_ctx* ctx) {
     REXI_HIP(hipMalloc(&ctx->d_n0, sizeof(double) * st));
     REXI_HIP(hipMalloc(&ctx->d_tmpA, sizeof(double) * st));
     REXI_HIP(hipMalloc(&ctx->d_tmpB, sizeof(double) * st));
+    REXI_HIP(hipMalloc(&ctx->d_tmpC, sizeof(double) * st));
     return sht_configure_kernels(ctx);
 }
 
@@ -298,9 +299,11 @@ int cn_linear(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
 }
 
 // synth_done: the synthesis of U0 is already in ctx->d_part (the pole sum of
-// a REXI stage fused with it).
+// a REXI stage, or the previous step's last analysis, fused with it).
+// synth_next (may be null): on input, ask for the synthesis of U1 to be left
+// in ctx->d_part (the last analysis fused with it); on return, whether it was.
 int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_t stream, double two_omega = 0.0,
-              bool synth_done = false) {
+              bool synth_done = false, bool* synth_next = nullptr) {
     int rc;
     if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
     // stage 1: U* = U0 + tau N(U0), keep N(U0)
@@ -309,8 +312,8 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     if (ctx->fuse && split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
         // the analysis of each order synthesises its U* directly (one launch;
         // U* is not stored)
-        if ((rc = launch_legendre_anal_synth_split(ctx, ctx->d_fout, U0, ctx->d_n0, nullptr, tau, ctx->d_part,
-                                                   stream)) != REXI_OK)
+        if ((rc = launch_legendre_anal_synth_split(ctx, ctx->d_fout, U0, nullptr, ctx->d_n0, nullptr, tau, 0.0,
+                                                   ctx->d_part, stream)) != REXI_OK)
             return rc;
     } else {
         if ((rc = from_fourier(ctx, 1, nullptr, 0, U0, nullptr, ctx->d_n0, ctx->d_ustar, tau, 0.0, stream)) !=
@@ -320,6 +323,12 @@ int heun_step(swe_ctx* ctx, double tau, const double* U0, double* U1, hipStream_
     }
     // stage 2: U1 = U0 + tau/2 (N(U0) + N(U*))
     if ((rc = ring_from_part(ctx, 2, nullptr, 0, stream, two_omega)) != REXI_OK) return rc;
+    if (synth_next && *synth_next && ctx->fuse && split_legendre(ctx) && fused_anal_synth_supported(ctx)) {
+        // U1 is stored and also synthesised for the caller's next Heun step
+        return launch_legendre_anal_synth_split(ctx, ctx->d_fout, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau,
+                                                ctx->d_part, stream);
+    }
+    if (synth_next) *synth_next = false;
     return from_fourier(ctx, 1, nullptr, 0, U0, ctx->d_n0, nullptr, U1, 0.5 * tau, 0.5 * tau, stream);
 }
 
@@ -501,7 +510,7 @@ int swe_destroy(swe_ctx* ctx) {
     void* sht_bufs[] = {ctx->d_rec, ctx->d_aon, ctx->d_noa2, ctx->d_mu, ctx->d_sint, ctx->d_w,
                         ctx->d_seg_m, ctx->d_seg_i0, ctx->d_seg_n, ctx->d_segbase, ctx->d_seed_pm,
                         ctx->d_seed_p, ctx->d_seed_e, ctx->d_tw, ctx->d_twr, ctx->d_radix, ctx->d_part,
-                        ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tab_psyn,
+                        ctx->d_fout, ctx->d_ustar, ctx->d_n0, ctx->d_tmpA, ctx->d_tmpB, ctx->d_tmpC, ctx->d_tab_psyn,
                         ctx->d_tab_pana, ctx->d_tab_off, ctx->d_tab_kp};
     for (void* p : sht_bufs)
         if (p) (void)hipFree(p);
@@ -711,31 +720,70 @@ int swe_nonlinear_step(swe_ctx* ctx, double tau, const double* U0, double* U1, h
     return heun_step(ctx, tau, U0, U1, stream);
 }
 
-int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
-                    const double* U0, double* U1, hipStream_t stream) {
-    if (!ctx) return fail(REXI_EINVAL, "swe_strang_step: NULL context");
-    if (!ctx->nlat) return fail(REXI_ENOTSUP, "swe_strang_step: linear-only context (no grid)");
-    if (!alpha || !beta || !U0 || !U1) return fail(REXI_EINVAL, "swe_strang_step: NULL pointer");
-    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, "swe_strang_step: N must be even and in [2, 2^20]");
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, "swe_strang_step: dt must be positive");
-    DeviceGuard guard(ctx->device);
+namespace {
+// One l_rexi_n_erk_ver1 step U0 -> U1 on prepared poles.  synth_done and
+// synth_next as in heun_step (the synthesis of U0 already in ctx->d_part; the
+// synthesis of U1 wanted there).
+int strang_once(swe_ctx* ctx, int N, double dt, const double* U0, double* U1, hipStream_t stream, bool synth_done,
+                bool* synth_next) {
     int rc;
-    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, true, "swe_strang_step", stream)) != REXI_OK) return rc;
-    if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream)) != REXI_OK) return rc;
+    if ((rc = heun_step(ctx, 0.5 * dt, U0, ctx->d_tmpA, stream, 0.0, synth_done)) != REXI_OK) return rc;
     int nparts = 0;
     if ((rc = launch_rexi_chain(ctx, N, dt, ctx->d_tmpA, ctx->d_tmpB, &nparts, stream)) != REXI_OK) return rc;
-    bool synth_done = false;
+    bool rexi_synth = false;
     if (nparts > 1 && ctx->fuse && split_legendre(ctx)) {
         // the pole sum of each order synthesises its result for the next Heun step
         if ((rc = reserve_fourier(ctx, 5)) != REXI_OK) return rc;
         if ((rc = launch_rexi_sum_synth_split(ctx, ctx->d_partial, nparts, ctx->d_tmpB, ctx->d_part, stream)) !=
             REXI_OK)
             return rc;
-        synth_done = true;
+        rexi_synth = true;
     } else if (nparts > 1 && (rc = launch_rexi_sum(ctx, nparts, ctx->d_tmpB, stream)) != REXI_OK) {
         return rc;
     }
-    return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream, 0.0, synth_done);
+    return heun_step(ctx, 0.5 * dt, ctx->d_tmpB, U1, stream, 0.0, rexi_synth, synth_next);
+}
+
+int strang_checks(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt, const double* U0,
+                  double* U1, const char* who) {
+    if (!ctx) return fail(REXI_EINVAL, std::string(who) + ": NULL context");
+    if (!ctx->nlat) return fail(REXI_ENOTSUP, std::string(who) + ": linear-only context (no grid)");
+    if (!alpha || !beta || !U0 || !U1) return fail(REXI_EINVAL, std::string(who) + ": NULL pointer");
+    if (N < 2 || (N & 1) || N > (1 << 20)) return fail(REXI_EINVAL, std::string(who) + ": N must be even and in [2, 2^20]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(REXI_EINVAL, std::string(who) + ": dt must be positive");
+    return REXI_OK;
+}
+}  // namespace
+
+int swe_strang_step(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt,
+                    const double* U0, double* U1, hipStream_t stream) {
+    int rc;
+    if ((rc = strang_checks(ctx, alpha, beta, N, dt, U0, U1, "swe_strang_step")) != REXI_OK) return rc;
+    DeviceGuard guard(ctx->device);
+    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, true, "swe_strang_step", stream)) != REXI_OK) return rc;
+    return strang_once(ctx, N, dt, U0, U1, stream, false, nullptr);
+}
+
+int swe_strang_steps(swe_ctx* ctx, const double* alpha, const double* beta, int N, double dt, int nsteps,
+                     const double* U0, double* U1, hipStream_t stream) {
+    int rc;
+    if ((rc = strang_checks(ctx, alpha, beta, N, dt, U0, U1, "swe_strang_steps")) != REXI_OK) return rc;
+    if (nsteps < 1) return fail(REXI_EINVAL, "swe_strang_steps: nsteps must be at least 1");
+    DeviceGuard guard(ctx->device);
+    if ((rc = prepare_poles(ctx, alpha, beta, N, dt, true, "swe_strang_steps", stream)) != REXI_OK) return rc;
+    // step k writes U1 when nsteps - 1 - k is even, else the context's state
+    // buffer, so that consecutive steps never share a buffer and the last
+    // writes U1
+    const double* src = U0;
+    bool synth_done = false;
+    for (int k = 0; k < nsteps; ++k) {
+        double* dst = ((nsteps - 1 - k) % 2 == 0) ? U1 : ctx->d_tmpC;
+        bool synth_next = k + 1 < nsteps;
+        if ((rc = strang_once(ctx, N, dt, src, dst, stream, synth_done, &synth_next)) != REXI_OK) return rc;
+        synth_done = synth_next;
+        src = dst;
+    }
+    return REXI_OK;
 }
 
 int swe_cn_step(swe_ctx* ctx, double dt, const double* U0, double* U1, hipStream_t stream) {

@@ -245,6 +245,7 @@ struct swe_ctx {
     size_t tab_len = 0;               // shorts per table
     double* d_tmpA = nullptr;         // Strang intermediates [3][modes]
     double* d_tmpB = nullptr;
+    double* d_tmpC = nullptr;         // swe_strang_steps: the state between steps
 };
 
 namespace rexi {
@@ -317,19 +318,21 @@ int launch_legendre_synth_split(swe_ctx* ctx, int kind, const double* spec, doub
 int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, double* spec, int nf, const double* U0,
                                const double* Nprev, double* Nsave, double* out, double c0, double c1,
                                hipStream_t stream);
-// The state's analysis (kind 1, Nprev = 0) fused with the synthesis of its
-// output: Nsave = N, out = U0 + c0 N (written only if out is non-null), and
-// the Fourier coefficients of out, latitude-major, into four_next (as the
-// kind-1 synthesis writes them).  Needs the table's degree rows per parity to
-// fit the latitude rows (fused_anal_synth_supported).
+// The state's analysis (kind 1) fused with the synthesis of its output:
+// Nsave = N (if non-null), out = U0 + c0 N + c1 Nprev (Nprev may be null;
+// out written only if non-null), and the Fourier coefficients of out,
+// latitude-major, into four_next (as the kind-1 synthesis writes them).
+// Needs the table's degree rows per parity to fit the latitude rows
+// (fused_anal_synth_supported).
 int fused_anal_synth_supported(const swe_ctx* ctx);
 // The REXI stage's pole sum over nparts partials ([nparts][3 modes] complex)
 // into U1, fused with the split synthesis of U1 into four_next (latitude-major,
 // as the kind-1 synthesis writes it).
 int launch_rexi_sum_synth_split(swe_ctx* ctx, const double* part, int nparts, double* U1, double* four_next,
                                 hipStream_t stream);
-int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, double* Nsave,
-                                     double* out, double c0, double* four_next, hipStream_t stream);
+int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, const double* Nprev,
+                                     double* Nsave, double* out, double c0, double c1, double* four_next,
+                                     hipStream_t stream);
 // The REXI stage of the gravity-wave part L_g alone (Coriolis-free): per degree
 // l a 2x2 system in (h, delta), zeta multiplied by S(0); the sums over poles are
 // formed once per degree.

@@ -1110,18 +1110,19 @@ int launch_legendre_anal_split(swe_ctx* ctx, int kind, const double* four, doubl
 
 int fused_anal_synth_supported(const swe_ctx* ctx) { return ctx->tab_kmax <= ctx->tab_hpad; }
 
-int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, double* Nsave,
-                                     double* out, double c0, double* four_next, hipStream_t stream) {
+int launch_legendre_anal_synth_split(swe_ctx* ctx, const double* four, const double* U0, const double* Nprev,
+                                     double* Nsave, double* out, double c0, double c1, double* four_next,
+                                     hipStream_t stream) {
     if (!fused_anal_synth_supported(ctx))
         return fail(REXI_ENOTSUP, "fused analysis and synthesis: degree rows exceed the latitude rows");
     MfmaArgs A = mfma_args(ctx);
     A.four_in = reinterpret_cast<const double2*>(four);
     A.U0 = reinterpret_cast<const double2*>(U0);
-    A.Nprev = nullptr;
+    A.Nprev = reinterpret_cast<const double2*>(Nprev);
     A.Nsave = reinterpret_cast<double2*>(Nsave);
     A.out = reinterpret_cast<double2*>(out);
     A.c0 = c0;
-    A.c1 = 0.0;
+    A.c1 = c1;
     A.nf = 3;
     // the synthesis output of the state: latitude-major [3][nlat][L+1]
     A.four_out = reinterpret_cast<double2*>(four_next);

@@ -55,3 +55,40 @@ def test_fusion_is_bit_identical(L, nlat, nlon, flags, N, p0, y, strang):
     b = _run(L, nlat, nlon, prec, False, 2, alpha, beta, dt, strang)
     assert np.all(np.isfinite(a))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("fuse", [True, False], ids=["fused", "separate"])
+@pytest.mark.parametrize("flags", [("FP32_SOLVE", "BF16_SPLIT"), ("FP32_SOLVE", "FP16_SPLIT"), ()],
+                         ids=["bf16", "fp16", "fp64"])
+def test_strang_steps_match_separate_steps(fuse, flags):
+    """swe_strang_steps(n) = n swe_strang_step calls, bit for bit, also in place
+    (the multi-step call fuses the last analysis of a step with the first
+    synthesis of the next in split precision)."""
+    from paper_1805_06557_amd import api
+    prec = 0
+    for f in flags:
+        prec |= getattr(api, "PREC_" + f)
+    L, nlat, nlon, dt = 127, 192, 384, 900.0
+    alpha, beta, _, _ = orexi.coefficients(orexi.FN_EXP, 256, 8.0, 24.0)
+    ctx = api.SWE(L, nlat, nlon, prec=prec)
+    ctx.set_fusion(fuse)
+    U0 = torch.from_numpy(jet_state(L, 5)).cuda()
+    for n in (1, 2, 3):
+        a = U0.clone()
+        b = torch.empty_like(a)
+        for _ in range(n):
+            ctx.strang_step(alpha, beta, dt, a, b)
+            a, b = b, a
+        many = torch.empty_like(U0)
+        ctx.strang_steps(alpha, beta, dt, n, U0, many)
+        inplace = U0.clone()
+        ctx.strang_steps(alpha, beta, dt, n, inplace, inplace)
+        torch.cuda.synchronize()
+        ref = a.cpu().numpy()
+        assert np.all(np.isfinite(ref))
+        assert np.array_equal(many.cpu().numpy(), ref), n
+        assert np.array_equal(inplace.cpu().numpy(), ref), n
+    with pytest.raises(api.RexiError):
+        ctx.strang_steps(alpha, beta, dt, 0, U0, many)
+    ctx.sync()
+    ctx.close()
