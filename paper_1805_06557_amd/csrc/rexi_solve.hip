@@ -90,22 +90,24 @@ __device__ __forceinline__ void static_for(F&& f) {
 // rexi_rows_kernel in HBM in chain order, record 2 base(m) + c Lm + j), so that
 // the sweeps read one record per row and do no wave-uniform arithmetic.
 struct RowRec {
-    double a, c;       // couplings to rows j-1 and j+1, signed for the row type, times dt
+    double a;          // coupling to row j-1, signed for the row type, times dt
+    double ac;         // a_j c_{j-1}: the product of this row's a and the previous row's c (0 for j = 0)
     double dts;        // dt m q_k
     double g2;         // dt^2 H g k(k+1)/a^2  (delta rows; 0 for zeta rows)
     double tx, ty;     // dt g k(k+1)/a^2 r_h   (delta rows; 0 for zeta rows)
     double rx, ry;     // right-hand side r_delta or r_zeta
+    double c;          // coupling to row j+1, signed for the row type, times dt
     double hx, hy;     // r_h (delta rows)
-    float af, cf;      // a, c rounded to FP32
-    float rfx, rfy;    // r rounded to FP32
+    double pad;
 };
 static_assert(sizeof(RowRec) == 96, "RowRec layout");
 
 // The FP32 solve's record: the same quantities rounded once to FP32 (48 B, so a
-// chain's records take half the LDS and half the broadcast reads).
+// chain's records take half the LDS and half the broadcast reads).  The first
+// 32 bytes hold everything the forward sweep reads.
 struct RowRec32 {
-    float a, c, dts, g2, tx, ty, rx, ry, hx, hy;
-    float pad[2];
+    float a, ac, dts, g2, tx, ty, rx, ry, c, hx, hy;
+    float pad;
 };
 static_assert(sizeof(RowRec32) == 48, "RowRec32 layout");
 
@@ -116,23 +118,34 @@ using RecT = typename std::conditional<std::is_same<T, float>::value, RowRec32, 
 __device__ __forceinline__ RowRec32 round_rec(const RowRec& r) {
     RowRec32 q;
     q.a = static_cast<float>(r.a);
+    q.ac = static_cast<float>(r.ac);
     q.c = static_cast<float>(r.c);
     q.dts = static_cast<float>(r.dts);
-    q.g2 = static_cast<float>(r.g2);
     q.tx = static_cast<float>(r.tx);
     q.ty = static_cast<float>(r.ty);
     q.rx = static_cast<float>(r.rx);
     q.ry = static_cast<float>(r.ry);
+    q.g2 = static_cast<float>(r.g2);
     q.hx = static_cast<float>(r.hx);
     q.hy = static_cast<float>(r.hy);
-    q.pad[0] = q.pad[1] = 0.0f;
+    q.pad = 0.0f;
     return q;
 }
 
+// a_j c_{j-1} of row j >= 1 (degree k = m + j, coefficients cf; the previous
+// degree's coefficients cfp).  The rows of a chain alternate between delta rows
+// (couplings -dt cm, -dt cp) and zeta rows (dt cm, dt cp), so the product is
+// -(dt cm_k)(dt cp_{k-1}) in either chain, the same bits as the product of the
+// two rows' signed couplings.
+__device__ __forceinline__ double coupling_product(const ModeCoef& cf, const ModeCoef& cfp, double dt) {
+    return -((dt * cf.cm) * (dt * cfp.cp));
+}
+
 // The delta row (coupled to h) and the zeta row of degree k = m + j.
-__device__ __forceinline__ RowRec delta_row(const ModeCoef& cf, double2 rh, double2 rd, double dt, double H) {
+__device__ __forceinline__ RowRec delta_row(const ModeCoef& cf, double ac, double2 rh, double2 rd, double dt, double H) {
     RowRec d;
     d.a = -dt * cf.cm;
+    d.ac = ac;
     d.c = -dt * cf.cp;
     d.dts = dt * cf.s;
     d.g2 = dt * dt * H * cf.gN;
@@ -142,16 +155,14 @@ __device__ __forceinline__ RowRec delta_row(const ModeCoef& cf, double2 rh, doub
     d.ry = rd.y;
     d.hx = rh.x;
     d.hy = rh.y;
-    d.af = static_cast<float>(d.a);
-    d.cf = static_cast<float>(d.c);
-    d.rfx = static_cast<float>(rd.x);
-    d.rfy = static_cast<float>(rd.y);
+    d.pad = 0.0;
     return d;
 }
 
-__device__ __forceinline__ RowRec zeta_row(const ModeCoef& cf, double2 rz, double dt) {
+__device__ __forceinline__ RowRec zeta_row(const ModeCoef& cf, double ac, double2 rz, double dt) {
     RowRec z;
     z.a = dt * cf.cm;
+    z.ac = ac;
     z.c = dt * cf.cp;
     z.dts = dt * cf.s;
     z.g2 = 0.0;
@@ -159,10 +170,7 @@ __device__ __forceinline__ RowRec zeta_row(const ModeCoef& cf, double2 rz, doubl
     z.rx = rz.x;
     z.ry = rz.y;
     z.hx = z.hy = 0.0;
-    z.af = static_cast<float>(z.a);
-    z.cf = static_cast<float>(z.c);
-    z.rfx = static_cast<float>(rz.x);
-    z.rfy = static_cast<float>(rz.y);
+    z.pad = 0.0;
     return z;
 }
 
@@ -173,11 +181,12 @@ __device__ __forceinline__ void build_row_pair(const double2* __restrict__ U0, c
     const int idx = base + j;
     const int Lm = L - m + 1;
     const ModeCoef cf = coef[idx];
+    const double ac = j > 0 ? coupling_product(cf, coef[idx - 1], dt) : 0.0;
     const int cd = j & 1;                                   // chain in which row j is a delta row
-    const RowRec d = delta_row(cf, U0[idx], U0[2 * modes + idx], dt, H);
+    const RowRec d = delta_row(cf, ac, U0[idx], U0[2 * modes + idx], dt, H);
     rec[2 * base + cd * Lm + j] = d;
     rec32[2 * base + cd * Lm + j] = round_rec(d);
-    const RowRec z = zeta_row(cf, U0[modes + idx], dt);
+    const RowRec z = zeta_row(cf, ac, U0[modes + idx], dt);
     rec[2 * base + (1 - cd) * Lm + j] = z;
     rec32[2 * base + (1 - cd) * Lm + j] = round_rec(z);
 }
@@ -271,14 +280,18 @@ __device__ __forceinline__ T coupling_a(const RecT<T>& R) { return R.a; }
 template <typename T>
 __device__ __forceinline__ T coupling_c(const RecT<T>& R) { return R.c; }
 
-// Pivot of a row: p = 1/(b - a c'_prev), then c' = c p, with the diagonal
-// b = z + g2/z - i dts (g2 = 0 for zeta rows) formed in T; an FP32 diagonal is off
-// by u_32 relative to |z| + g2/|z|, a backward error of the size the FP32 sweep
-// makes anyway (the shifted systems are well conditioned: the poles stay at a
-// distance y - rho from the spectrum).  Used by the factorization and by both
-// sweeps of the fused schedule, so cached and recomputed pivots agree bit for bit.
+// Pivot of a row: p_j = 1/(b_j - a_j c'_{j-1}) with c'_{j-1} = c_{j-1} p_{j-1},
+// formed as b_j - (a_j c_{j-1}) p_{j-1} from the record's product ac, so that the
+// recurrence runs on the pivots alone (c' = c p is formed only where the
+// back-substitution needs it).  The diagonal b = z + g2/z - i dts (g2 = 0 for
+// zeta rows) is formed in T; an FP32 diagonal is off by u_32 relative to
+// |z| + g2/|z|, a backward error of the size the FP32 sweep makes anyway (the
+// shifted systems are well conditioned: the poles stay at a distance y - rho
+// from the spectrum).  pp: the previous row's pivot on entry, this row's on
+// return.  Used by the factorization and by both sweeps of the fused schedule,
+// so cached and recomputed pivots agree bit for bit.
 template <typename T, bool DELTA>
-__device__ __forceinline__ Cx<T> pivot_row(const RecT<T>& R, const Lane& ln, Cx<T>& cp) {
+__device__ __forceinline__ Cx<T> pivot_row(const RecT<T>& R, const Lane& ln, Cx<T>& pp) {
     T bR, bI;
     if constexpr (std::is_same<T, float>::value) {
         if constexpr (DELTA) {
@@ -297,14 +310,20 @@ __device__ __forceinline__ Cx<T> pivot_row(const RecT<T>& R, const Lane& ln, Cx<
             bI = ln.p.zi - R.dts;
         }
     }
-    const T ta = coupling_a<T>(R), tc = coupling_c<T>(R);
-    const T wr = fmaT(-ta, cp.x, bR);
-    const T wi = fmaT(-ta, cp.y, bI);
+    const T tac = R.ac;
+    const T wr = fmaT(-tac, pp.x, bR);
+    const T wi = fmaT(-tac, pp.y, bI);
     const T inv = rcp_refined(fmaT(wr, wr, wi * wi));
     const Cx<T> p{wr * inv, -wi * inv};
-    cp.x = tc * p.x;
-    cp.y = tc * p.y;
+    pp = p;
     return p;
+}
+
+// c'_j = c_j p_j, the factor the back-substitution applies to x_{j+1}.
+template <typename T>
+__device__ __forceinline__ Cx<T> upper_factor(const RecT<T>& R, Cx<T> p) {
+    const T tc = coupling_c<T>(R);
+    return Cx<T>{tc * p.x, tc * p.y};
 }
 
 // The right-hand-side part of a forward step with pivot p: d' = (d - a d'_prev) p.
@@ -430,10 +449,11 @@ __device__ __forceinline__ void back_segment(const SolveArgs& A, const Lane* ln,
 }
 
 // Schedules of the two sweeps.  FUSED: both sweeps compute the pivots (the
-// forward sweep keeps c' and d' at segment starts; the backward pass recomputes
-// each segment from them).  STREAM: both sweeps read the pivots of the cached
-// factorization.  HYBRID: the forward sweep reads them and keeps c' = c p at
-// segment starts; the backward pass recomputes each segment's pivots.
+// forward sweep keeps d' and the previous pivot at segment starts; the backward
+// pass recomputes each segment from them).  STREAM: both sweeps read the pivots
+// of the cached factorization.  HYBRID: the forward sweep reads them and keeps
+// the previous pivot at segment starts; the backward pass recomputes each
+// segment's pivots.
 enum Sched { FUSED = 0, STREAM = 1, HYBRID = 2 };
 
 template <int SCHED>
@@ -465,8 +485,9 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
         for (int j = threadIdx.x; j < Lm; j += blockDim.x) {
             const int idx = base + j;
             const ModeCoef cf = A.coef[idx];
-            const RowRec r = ((j & 1) == C) ? delta_row(cf, A.U0[idx], A.U0[2 * A.modes + idx], A.dt, A.H)
-                                            : zeta_row(cf, A.U0[A.modes + idx], A.dt);
+            const double ac = j > 0 ? coupling_product(cf, A.coef[idx - 1], A.dt) : 0.0;
+            const RowRec r = ((j & 1) == C) ? delta_row(cf, ac, A.U0[idx], A.U0[2 * A.modes + idx], A.dt, A.H)
+                                            : zeta_row(cf, ac, A.U0[A.modes + idx], A.dt);
             if constexpr (std::is_same<T, float>::value) rc[j] = round_rec(r); else rc[j] = r;
         }
     } else {
@@ -522,9 +543,10 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     const Cx<T>* fact = reinterpret_cast<const Cx<T>*>(A.fact) + static_cast<size_t>(2 * base + C * Lm) * A.npad +
                         pw * PS * WAVE + lane;
 
-    Cx<T> cp[P], dp[P];
+    // the recurrence state: the previous row's pivot pp and d'
+    Cx<T> pp[P], dp[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) cp[k] = dp[k] = Cx<T>{T(0), T(0)};
+    for (int k = 0; k < P; ++k) pp[k] = dp[k] = Cx<T>{T(0), T(0)};
     // per segment row: the pivot p_j, replaced by c'_j = c_j p_j once the row's
     // d'_j is formed (the back-substitution needs only c'_j and d'_j)
     Cx<T> ps[P][S], ds[P][S];
@@ -535,7 +557,7 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 c0[k * WAVE] = dp[k];
-                if constexpr (CKW == 2) c0[(P + k) * WAVE] = cp[k];
+                if constexpr (CKW == 2) c0[(P + k) * WAVE] = pp[k];
             }
         }
         const RecT<T>* rs = rc + seg * S;
@@ -545,7 +567,7 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
                 constexpr bool DELTA = ((jj + C) & 1) == 0;
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
-                    const Cx<T> p = pivot_row<T, DELTA>(rs[jj], ln[k], cp[k]);
+                    const Cx<T> p = pivot_row<T, DELTA>(rs[jj], ln[k], pp[k]);
                     forward_rhs<T, DELTA>(rs[jj], ln[k], p, dp[k]);
                 }
             });
@@ -563,12 +585,8 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
                 for (int k = 0; k < P; ++k) forward_rhs<T, DELTA>(rs[jj], ln[k], ps[k][jj], dp[k]);
             });
             if constexpr (SCHED == HYBRID) {
-                const T tc = coupling_c<T>(rs[S - 1]);
 #pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    cp[k].x = tc * ps[k][S - 1].x;
-                    cp[k].y = tc * ps[k][S - 1].y;
-                }
+                for (int k = 0; k < P; ++k) pp[k] = ps[k][S - 1];
             }
         }
     }
@@ -588,12 +606,11 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
                     if constexpr (SCHED == STREAM) {
                         const Cx<T> p = fseg[static_cast<size_t>(jj) * A.npad + k * WAVE];
                         forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, dp[k]);
-                        const T tc = coupling_c<T>(rc[j0 + jj]);
-                        ps[k][jj] = Cx<T>{tc * p.x, tc * p.y};
+                        ps[k][jj] = upper_factor<T>(rc[j0 + jj], p);
                     } else {
-                        const Cx<T> p = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], cp[k]);
+                        const Cx<T> p = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], pp[k]);
                         forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, dp[k]);
-                        ps[k][jj] = cp[k];   // c'_j, formed by pivot_row as c_j p_j
+                        ps[k][jj] = upper_factor<T>(rc[j0 + jj], p);
                     }
                     ds[k][jj] = dp[k];
                 }
@@ -604,7 +621,7 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
     // earlier segments: rebuild pivots and d' from the checkpoint, then back-substitute
     for (int seg = nseg - 2; seg >= 0; --seg) {
         const int j0 = seg * S;
-        Cx<T> d[P], c[P];
+        Cx<T> d[P], c[P];   // d' and the pivot of the row before the segment
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             d[k] = c[k] = Cx<T>{T(0), T(0)};
@@ -629,12 +646,11 @@ __device__ __forceinline__ void solve_chain(const SolveArgs& A, int task, int m,
             for (int k = 0; k < P; ++k) {
                 if constexpr (SCHED == STREAM) {
                     forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], ps[k][jj], d[k]);
-                    const T tc = coupling_c<T>(rc[j0 + jj]);
-                    ps[k][jj] = Cx<T>{tc * ps[k][jj].x, tc * ps[k][jj].y};
+                    ps[k][jj] = upper_factor<T>(rc[j0 + jj], ps[k][jj]);
                 } else {
                     const Cx<T> p = pivot_row<T, DELTA>(rc[j0 + jj], ln[k], c[k]);
                     forward_rhs<T, DELTA>(rc[j0 + jj], ln[k], p, d[k]);
-                    ps[k][jj] = c[k];   // c'_j
+                    ps[k][jj] = upper_factor<T>(rc[j0 + jj], p);   // c'_j
                 }
                 ds[k][jj] = d[k];
             }
@@ -707,10 +723,10 @@ __global__ __launch_bounds__(256) void rexi_factor_kernel(const RecT<T>* __restr
     ln.ziif = static_cast<float>(ln.p.zii);
     const RecT<T>* rc = rec + 2 * base + C * Lm;
     Cx<T>* out = fact + static_cast<size_t>(2 * base + C * Lm) * npad + n;
-    Cx<T> cp{T(0), T(0)};
+    Cx<T> pp{T(0), T(0)};
     for (int j = 0; j < Lm; ++j) {
         const RecT<T> R = rc[j];
-        const Cx<T> p = ((j + C) & 1) == 0 ? pivot_row<T, true>(R, ln, cp) : pivot_row<T, false>(R, ln, cp);
+        const Cx<T> p = ((j + C) & 1) == 0 ? pivot_row<T, true>(R, ln, pp) : pivot_row<T, false>(R, ln, pp);
         out[static_cast<size_t>(j) * npad] = p;
     }
 }
