@@ -58,9 +58,12 @@ enum { REXI_FN_EXP = 0, REXI_FN_PSI1 = 1, REXI_FN_PSI2 = 2 };
  *   formed in FP32 from z and 1/z rounded to FP32, and the pivot reciprocal is
  *   the hardware's FP32 reciprocal without refinement (a backward error of a
  *   few FP32 units relative to the diagonal, the size the FP32 sweep makes
- *   anyway).  Solutions are widened to FP64 for the beta-weighted sum, which
- *   accumulates in FP64 (Section 4.2.2: the sum cancels; its terms are up to
- *   kappa = sum |beta_n| / |x + alpha_n| times larger than the result).
+ *   anyway).  Each pole's solution is weighted in FP32 (by -beta_n rounded to
+ *   FP32 once) and the weighted solutions of the (at most two) poles a GPU
+ *   lane carries are added in FP32; that sum is widened to FP64, and the sum
+ *   over all poles accumulates in FP64 (Section 4.2.2: the sum cancels; its
+ *   terms are up to kappa = sum |beta_n| / |x + alpha_n| times larger than the
+ *   result).
  * REXI_PREC_BF16_SPLIT, REXI_PREC_FP16_SPLIT (exclusive): the Legendre
  *   contractions of the transforms (Section 3.2) run on the matrix cores with
  *   every operand split into two 16-bit values (hi + lo) and three products
