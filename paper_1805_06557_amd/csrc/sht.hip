@@ -337,6 +337,18 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
     __syncthreads();
 
     for (int c0 = 0; c0 < n; c0 += D) {
+        // KIND 1: the update's inputs U0 and Nprev of this thread's output in
+        // the chunk, requested before the chunk's products so that their
+        // latency overlaps them (the update itself keeps its order below)
+        double u0v = 0.0, npv = 0.0;
+        if constexpr (KIND == 1) {
+            const int d = c0 + o_red / NC, k = o_red % NC;
+            if (o_red < NO && g_red == 0 && d < n) {
+                const size_t e2 = (static_cast<size_t>(k >> 1) * A.modes + base + i0 + d) * 2 + (k & 1);
+                if (P.U0) u0v = reinterpret_cast<const double*>(P.U0)[e2];
+                if (P.Nprev) npv = reinterpret_cast<const double*>(P.Nprev)[e2];
+            }
+        }
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
             const int d = c0 + dd;
@@ -416,8 +428,8 @@ __global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
                 } else {
                     const int f = k >> 1, part = k & 1;
                     const size_t e2 = (static_cast<size_t>(f) * A.modes + idx) * 2 + part;
-                    double v = __builtin_fma(P.c0, s, P.U0 ? reinterpret_cast<const double*>(P.U0)[e2] : 0.0);
-                    if (P.Nprev) v = __builtin_fma(P.c1, reinterpret_cast<const double*>(P.Nprev)[e2], v);
+                    double v = __builtin_fma(P.c0, s, u0v);
+                    if (P.Nprev) v = __builtin_fma(P.c1, npv, v);
                     if (P.Nsave) reinterpret_cast<double*>(P.Nsave)[e2] = s;
                     note_nonfinite(A.status, v, STATUS_NONLINEAR);
                     reinterpret_cast<double*>(P.out)[e2] = v;
