@@ -689,9 +689,23 @@ __device__ __forceinline__ void wave_load_coeffs(const RingArgs& A, int f, int j
 #pragma unroll
         for (int i = 0; i < MPL; ++i)
             acc[i] = g0[i] < g1[i] ? pf[static_cast<long long>(g0[i]) * A.pgs] : make_double2(0.0, 0.0);
+        // the later segments, segment t of every order the lane holds at once
+        // (one memory round trip per segment rank, not per segment); each
+        // order's partials are still added in segment order
+        int tmax = 0;
+#pragma unroll
+        for (int i = 0; i < MPL; ++i) tmax = max(tmax, g1[i] - g0[i]);
+        for (int t = 1; t < tmax; ++t) {
+            double2 v[MPL];
+#pragma unroll
+            for (int i = 0; i < MPL; ++i)
+                v[i] = g0[i] + t < g1[i] ? pf[static_cast<long long>(g0[i] + t) * A.pgs] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < MPL; ++i)
+                if (g0[i] + t < g1[i]) acc[i] = cadd(acc[i], v[i]);
+        }
 #pragma unroll
         for (int i = 0; i < MPL; ++i) {
-            for (int g = g0[i] + 1; g < g1[i]; ++g) acc[i] = cadd(acc[i], pf[static_cast<long long>(g) * A.pgs]);
             const int m = lane + i * WAVE;
             if (m <= A.L) x[pad8(m)] = acc[i];
         }
