@@ -264,8 +264,16 @@ template <int KIND>
 struct AnaTraits {
     static constexpr int NC = KIND == 0 ? 2 : 6;       // doubles contributed per (l, j)
     static constexpr int NIN = KIND == 0 ? 1 : 5;      // complex input fields
-    static constexpr int D = KIND == 0 ? 16 : 8;       // degrees per reduction chunk
 };
+
+// Degrees per reduction chunk.  The non-linear analysis with two waves per
+// workgroup (more than 192 northern latitudes) takes 4-degree chunks, whose
+// lane sums need half the LDS, and asks for two waves per SIMD; with one wave
+// the 8-degree chunk is faster.
+template <int KIND, int NW>
+constexpr int ana_chunk() { return KIND == 0 ? 16 : (NW == 2 ? 4 : 8); }
+template <int KIND, int NW>
+constexpr int ana_occupancy() { return KIND == 1 && NW == 2 ? 2 : 1; }
 
 // Folded, weighted inputs of one latitude (units of 2^e): for each field,
 // S = F(mu) + F(-mu) and D = F(mu) - F(-mu); zero for padding latitudes.
@@ -292,10 +300,11 @@ __device__ __forceinline__ void load_folded(const AnaArgs& P, int m, int j, bool
 constexpr int RED_STRIDE = 72;   // doubles per staged output row (64 lanes + pad)
 
 template <int KIND, int NJ, int NW>
-__global__ __launch_bounds__(NW * WAVE) void legendre_anal_kernel(AnaArgs P) {
+__global__ __launch_bounds__(NW * WAVE) __attribute__((amdgpu_waves_per_eu(ana_occupancy<KIND, NW>())))
+void legendre_anal_kernel(AnaArgs P) {
     constexpr int NC = AnaTraits<KIND>::NC;
     constexpr int NIN = AnaTraits<KIND>::NIN;
-    constexpr int D = AnaTraits<KIND>::D;
+    constexpr int D = ana_chunk<KIND, NW>();
     constexpr int NO = D * NC;                           // outputs per chunk
     constexpr int SL = KIND == 0 ? 1 : 3;                // staged double2 per degree
     constexpr int T = NW * WAVE;
